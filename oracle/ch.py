@@ -1,0 +1,201 @@
+"""FP64 CPU oracle for the stabilised semi-implicit Fourier-spectral Cahn-Hilliard step.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path imports this package: only the test
+suite, the smoke check and the CPU-baseline leg of the benchmark call it.  It shares no code with
+the HIP library; the only thing both sides share are the seeded inputs.
+
+What it computes (paper, Appendix "Semi-implicit timestepping" and "Phase transformations"):
+
+  * the Cahn-Hilliard problem dc/dt = div(M grad mu), mu = f'(c) - kappa lap(c), with constant M,
+    kappa and the double well f(c) = (c^2 - 1)^2 / 4 (so f' = c^3 - c);
+  * the semi-implicit Fourier-spectral step in the paper's increment form
+        c^{n+1} = c^n + T^{-1}{ dt / (1 - dt S) * T{rhs(c^n)} },
+    whose symbol S is the Fourier representation of the implicitly treated linear operator
+    (the symbol rule closing the appendix).  Here S = -(M kappa K2^2 + A K2): the fourth-order
+    term of the CH instance plus a linear stabilisation A K2 (the constant-coefficient splitting
+    Gamma = Gamma_0 + (Gamma - Gamma_0) of the same appendix, applied with Gamma_0 = A);
+  * the equivalent one-line k-space form
+        C^{n+1} = G * (P * C^n - dt M K2 F^n),  P = 1 + A dt K2,
+        G = 1 / (1 + dt M kappa K2^2 + A dt K2),  F^n = T[f'(c^n)],
+    which is the plain definition: one linear solve per step of
+        (I + dt M kappa L^2 - A dt L) c^{n+1} = (I - A dt L) c^n + dt M L f'(c^n)
+    with the discrete Laplacian L that T diagonalises.
+
+T is the 3D DFT (periodic) or the separable DCT-II (zero flux on a cell-centred grid, where the
+update has homogeneous Neumann data; the appendix notes the update inherits homogeneous boundary
+data, which is what makes a fast transform applicable).  K2 is the eigenvalue of -L: k^2 for the
+spectral Laplacian or (4/dx^2) sin^2(k dx/2) for the 7-point stencil, summed over the three axes.
+
+Both forms are implemented here independently (k-space form with spectral multipliers; increment
+form with a real-space 7-point stencil for the stencil scheme) and the tests assert that they agree.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.fft as sfft
+
+__all__ = [
+    "CHParams", "axis_k2", "k2_grid", "T", "Tinv", "fprime", "fsecond", "fwell",
+    "ch_step", "ch_step_increment", "ch_run", "laplacian", "energy", "mass", "growth_factor",
+]
+
+WORKERS = 1  # scipy.fft threads; the CPU-baseline leg raises it to the host core count
+
+
+@dataclass(frozen=True)
+class CHParams:
+    dx: float = 1.0
+    dt: float = 0.1
+    M: float = 1.0
+    kappa: float = 1.0
+    A: float = 2.0
+
+
+def fwell(c):
+    """Double-well bulk free energy density f(c) = (c^2 - 1)^2 / 4."""
+    return 0.25 * (c * c - 1.0) ** 2
+
+
+def fprime(c):
+    """f'(c) = c^3 - c."""
+    return c * c * c - c
+
+
+def fsecond(c):
+    """f''(c) = 3 c^2 - 1."""
+    return 3.0 * c * c - 1.0
+
+
+def axis_k2(n: int, dx: float, bc: str, scheme: str) -> np.ndarray:
+    """Eigenvalues of -d^2/dx^2 along one axis of n cells (float64).
+
+    periodic:  k = 2 pi m' / (n dx), m' = m for m <= n/2 else m - n;
+    zero flux: k = pi m / (n dx), m = 0..n-1 (cosine modes of the cell-centred grid).
+    spectral:  k^2;   stencil7: (4 / dx^2) sin^2(k dx / 2), the symbol of the 3-point
+    second difference (7 points in 3D).
+    """
+    m = np.arange(n, dtype=np.float64)
+    if bc == "periodic":
+        mp = np.where(m <= n // 2, m, m - n)
+        k = 2.0 * np.pi * mp / (n * dx)
+    elif bc == "zero_flux":
+        k = np.pi * m / (n * dx)
+    else:
+        raise ValueError(f"unknown bc {bc!r}")
+    if scheme == "spectral":
+        return k * k
+    if scheme == "stencil7":
+        return (4.0 / (dx * dx)) * np.sin(0.5 * k * dx) ** 2
+    raise ValueError(f"unknown scheme {scheme!r}")
+
+
+def k2_grid(shape, dx: float, bc: str, scheme: str) -> np.ndarray:
+    """K2(kz, ky, kx) = sum of the per-axis eigenvalues, shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    return (axis_k2(nz, dx, bc, scheme)[:, None, None]
+            + axis_k2(ny, dx, bc, scheme)[None, :, None]
+            + axis_k2(nx, dx, bc, scheme)[None, None, :])
+
+
+def T(c, bc: str):
+    """Forward transform: full complex 3D DFT (periodic) or 3D DCT-II (zero flux), unnormalised."""
+    if bc == "periodic":
+        return sfft.fftn(c, workers=WORKERS)
+    return sfft.dctn(c, type=2, workers=WORKERS)
+
+
+def Tinv(C, bc: str, keep_complex: bool = False):
+    """Inverse of T.  The periodic result is real up to round-off; its real part is returned unless
+    keep_complex (used by complex-step derivatives, whose data are genuinely complex)."""
+    if bc == "periodic":
+        out = sfft.ifftn(C, workers=WORKERS)
+        return out if keep_complex else out.real
+    return sfft.idctn(C, type=2, workers=WORKERS)
+
+
+def ch_step(c, p: CHParams, bc: str, scheme: str, source=None, keep_complex: bool = False):
+    """One step in k-space form: C' = G (P C - dt M K2 F) [+ G dt S_src]."""
+    K2 = k2_grid(c.shape, p.dx, bc, scheme)
+    C = T(c, bc)
+    F = T(fprime(c), bc)
+    P = 1.0 + p.A * p.dt * K2
+    G = 1.0 / (1.0 + p.dt * p.M * p.kappa * K2 * K2 + p.A * p.dt * K2)
+    num = P * C - p.dt * p.M * K2 * F
+    if source is not None:
+        num = num + p.dt * T(source, bc)
+    return Tinv(G * num, bc, keep_complex=keep_complex)
+
+
+def laplacian(u, dx: float, bc: str, scheme: str):
+    """Discrete Laplacian L u.  stencil7: real-space 3-point second difference per axis with
+    periodic wrap or, for zero flux on the cell-centred grid, a mirrored ghost cell (u_{-1} = u_0,
+    u_n = u_{n-1}).  spectral: multiplier -K2 through T."""
+    if scheme == "spectral":
+        return Tinv(-k2_grid(u.shape, dx, bc, scheme) * T(u, bc), bc)
+    out = np.zeros_like(u)
+    for ax in range(3):
+        if bc == "periodic":
+            up = np.roll(u, -1, axis=ax)
+            dn = np.roll(u, 1, axis=ax)
+        else:
+            pad = [(0, 0)] * 3
+            pad[ax] = (1, 1)
+            ue = np.pad(u, pad, mode="edge")
+            sl_up = [slice(None)] * 3
+            sl_dn = [slice(None)] * 3
+            sl_up[ax] = slice(2, None)
+            sl_dn[ax] = slice(0, -2)
+            up = ue[tuple(sl_up)]
+            dn = ue[tuple(sl_dn)]
+        out = out + (up - 2.0 * u + dn)
+    return out / (dx * dx)
+
+
+def ch_step_increment(c, p: CHParams, bc: str, scheme: str, source=None):
+    """One step in the paper's increment form with the right-hand side evaluated in real space:
+        rhs = M L(f'(c) - kappa L c) [+ s],   c' = c + T^{-1}[ dt / (1 - dt S) T[rhs] ],
+        S = -(M kappa K2^2 + A K2)."""
+    K2 = k2_grid(c.shape, p.dx, bc, scheme)
+    mu = fprime(c) - p.kappa * laplacian(c, p.dx, bc, scheme)
+    rhs = p.M * laplacian(mu, p.dx, bc, scheme)
+    if source is not None:
+        rhs = rhs + source
+    S = -(p.M * p.kappa * K2 * K2 + p.A * K2)
+    return c + Tinv(p.dt / (1.0 - p.dt * S) * T(rhs, bc), bc)
+
+
+def ch_run(c0, nsteps: int, p: CHParams, bc: str, scheme: str, every=None):
+    """nsteps k-space steps from c0 (float64 copy).  If every is given, also returns the list of
+    states at steps 0, every, 2*every, ... (including the last)."""
+    c = np.asarray(c0, dtype=np.float64).copy()
+    states = [c.copy()] if every else None
+    for n in range(nsteps):
+        c = ch_step(c, p, bc, scheme)
+        if every and ((n + 1) % every == 0 or n + 1 == nsteps):
+            states.append(c.copy())
+    return (c, states) if every else c
+
+
+def mass(c, dx: float = 1.0) -> float:
+    """Total mass dx^3 * sum(c)."""
+    return float(dx ** 3 * np.sum(c, dtype=np.float64))
+
+
+def energy(c, p: CHParams, bc: str, scheme: str) -> float:
+    """Discrete free energy E = dx^3 [ sum f(c) - (kappa/2) sum c L c ] (the Ginzburg-Landau
+    functional of the appendix with the spec double well; -sum c L c is the discrete
+    sum over |grad c|^2, i.e. the face differences for the stencil)."""
+    c = np.asarray(c, dtype=np.float64)
+    lap = laplacian(c, p.dx, bc, scheme)
+    return float(p.dx ** 3 * (np.sum(fwell(c)) - 0.5 * p.kappa * np.sum(c * lap)))
+
+
+def growth_factor(K2, cbar: float, p: CHParams):
+    """Per-step amplification of a small mode with eigenvalue K2 on a constant background cbar:
+    linearising f'(cbar + d) = f'(cbar) + f''(cbar) d in the k-space form gives
+        g = (1 + dt K2 (A - M f''(cbar))) / (1 + dt M kappa K2^2 + A dt K2)."""
+    K2 = np.asarray(K2, dtype=np.float64)
+    return ((1.0 + p.dt * K2 * (p.A - p.M * fsecond(cbar)))
+            / (1.0 + p.dt * p.M * p.kappa * K2 * K2 + p.A * p.dt * K2))
