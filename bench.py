@@ -1,0 +1,171 @@
+"""Benchmark of the HIP spectral Cahn-Hilliard stepper on one MI355X.
+
+A step is one pass of the whole per-step hot path (inverse y, fused x with f', forward y, fused z
+with the k-space update) over the seeded synthetic field, which is resident in HBM before the
+timed region starts.  The default workload is the 1024^3 periodic quench (mean 0, amplitude 0.05,
+seed 3, dt 0.5, spectral wavenumbers).  The line also carries:
+  roofline     - the dominant kernel's algorithmic bytes per launch over its average launch
+                 duration, timed with HIP events on the launch stream inside the timed region;
+  cpu_baseline - the FP64 oracle (SciPy FFTs) timed on this host on a bounded sample;
+  extra        - the 256^3 off-critical quench (periodic spectral and zero-flux stencil).
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PASS_NAMES = ["y_inverse", "x_fused_fprime", "y_forward", "z_fused_update"]
+
+
+def pass_bytes(shape, bc):
+    """Algorithmic HBM bytes per launch of each pass: one read and one write of a spectral
+    buffer (nz*ny*(nx/2+1) complex64, or nz*ny*nx float32 for zero flux); the z pass also reads
+    and writes the state."""
+    nz, ny, nx = shape
+    spec = nz * ny * ((nx // 2 + 1) * 8 if bc == "periodic" else nx * 4)
+    return [2 * spec, 2 * spec, 2 * spec, 4 * spec]
+
+
+def run_workload(evx, torch, w, steps, warmup, timing=True):
+    from paper_2507_21748_amd.inputs import quench_field
+    plan = evx.Plan(w.shape, w.bc, w.scheme, dx=w.dx)
+    prm = evx.CHParams(dt=w.dt, M=w.M, kappa=w.kappa, A=w.A)
+    c = torch.from_numpy(quench_field(w.shape, w.mean, w.amp, w.seed)).cuda()
+    plan.begin(c)
+    plan.advance(warmup, prm)
+    torch.cuda.synchronize()
+    plan.enable_pass_timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.advance(steps, prm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.enable_pass_timing(False)
+    ms, cnt = plan.read_pass_times() if timing else ([0] * 4, [0] * 4)
+    plan.end(c)
+    torch.cuda.synchronize()
+    ok = bool(torch.isfinite(c).all().item())
+    secs = t1 - t0
+    vox = w.voxels
+    out = {
+        "voxel_steps_per_s": vox * steps / secs,
+        "ms_per_step": 1e3 * secs / steps,
+        "finite": ok,
+        "workspace_bytes": plan.workspace_bytes,
+    }
+    if timing:
+        nbytes = pass_bytes(w.shape, w.bc)
+        per = {}
+        for i, name in enumerate(PASS_NAMES):
+            avg = ms[i] / max(cnt[i], 1)
+            per[name] = {"avg_ms": avg, "launches": cnt[i],
+                         "algorithmic_bytes": nbytes[i],
+                         "gbs": nbytes[i] / (avg * 1e-3) / 1e9 if avg > 0 else None}
+        out["passes"] = per
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline():
+    """FP64 oracle on this host: 2 timed steps (after 1 untimed) of a 512^3 periodic quench with
+    the same physics and IC recipe as the benchmark workload."""
+    import numpy as np
+    from oracle import ch
+    from paper_2507_21748_amd.inputs import quench_field
+    cores = min(16, os.cpu_count() or 1)
+    ch.WORKERS = cores
+    p = ch.CHParams(dt=0.5)
+    c = quench_field((512, 512, 512), 0.0, 0.05, 3).astype(np.float64)
+    c = ch.ch_step(c, p, "periodic", "spectral")
+    t0 = time.perf_counter()
+    nsteps = 2
+    for _ in range(nsteps):
+        c = ch.ch_step(c, p, "periodic", "spectral")
+    dt = time.perf_counter() - t0
+    return {"value": 512 ** 3 * nsteps / dt, "unit": "voxel-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "FP64 oracle (scipy.fft), 2 steps of a 512^3 periodic spectral quench "
+                      "(mean 0, amp 0.05, dt 0.5) after 1 warm-up step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="ch1024_periodic")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the spectral stepper here runs on a single device "
+              f"(--gpus {args.gpus} is not supported; multi-GPU sharding is design-only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_21748_amd import evx
+    from paper_2507_21748_amd.inputs import WORKLOADS
+    evx.load()
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    res = run_workload(evx, torch, w, args.steps, args.warmup)
+    passes = res["passes"]
+    dom = max(passes, key=lambda k: passes[k]["avg_ms"] * passes[k]["launches"])
+    d = passes[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": d["algorithmic_bytes"]}
+    step_bytes = sum(pass_bytes(w.shape, w.bc))
+    line = {
+        "metric": "CH voxel-steps/s FP32 (semi-implicit Fourier-spectral step)",
+        "value": res["voxel_steps_per_s"],
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic seeded quench field",
+        "config": {"workload": w.name, "grid": list(w.shape[::-1]), "bc": w.bc,
+                   "scheme": w.scheme, "dt": w.dt, "M": w.M, "kappa": w.kappa, "A": w.A,
+                   "mean": w.mean, "amp": w.amp, "seed": w.seed, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "step_effective_gbs": step_bytes * res["voxel_steps_per_s"] / w.voxels / 1e9,
+        "passes": passes,
+    }
+    if not args.no_extra:
+        extra = {}
+        for name in ("ch256_periodic", "ch256_zeroflux", "ch400_zeroflux"):
+            if name == args.workload:
+                continue
+            r = run_workload(evx, torch, WORKLOADS[name], 200, 10)
+            wb = sum(pass_bytes(WORKLOADS[name].shape, WORKLOADS[name].bc))
+            extra[name] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
+                           "ms_per_step": r["ms_per_step"],
+                           "step_effective_gbs": wb * r["voxel_steps_per_s"]
+                           / WORKLOADS[name].voxels / 1e9,
+                           "passes": {k: v["avg_ms"] for k, v in r["passes"].items()}}
+        line["extra"] = extra
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline()
+        line["cpu_baseline"] = cb
+        line["gpu_over_cpu"] = line["value"] / cb["value"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

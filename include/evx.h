@@ -1,0 +1,129 @@
+/*
+ * evx: MI355X (gfx950) Fourier-spectral semi-implicit Cahn-Hilliard stepper, C ABI.
+ *
+ * The operation (paper: Appendix, "Phase transformations of first and second order" for the
+ * Cahn-Hilliard equation and its free energy functional; "Semi-implicit timestepping" for the
+ * scheme, its increment form and the rule that the implicit prefactor is dt / (1 - dt S) with S
+ * the symbol of the implicitly treated operator):
+ *
+ *   dc/dt = div(M grad mu),  mu = f'(c) - kappa lap c,  f(c) = (c^2 - 1)^2 / 4,
+ *   C^{n+1} = G (P C^n - dt M K2 T[f'(c^n)]),   P = 1 + A dt K2,
+ *   G = 1 / (1 + dt M kappa K2^2 + A dt K2),
+ *
+ * i.e. the increment form c^{n+1} = c^n + T^{-1}[dt / (1 - dt S) T[rhs]] with symbol
+ * S = -(M kappa K2^2 + A K2): the fourth-order operator plus a linear stabilisation A K2 (the
+ * constant-coefficient splitting of the same appendix).  T is the 3D DFT (periodic boundaries)
+ * or the 3D DCT-II (zero flux on a cell-centred grid; the update then carries homogeneous
+ * Neumann data, so a cosine transform diagonalises it).  K2 is the eigenvalue of -lap: k^2
+ * (spectral) or sum over axes of (4/dx^2) sin^2(k dx / 2) (7-point stencil).
+ *
+ * Conventions for every entry point:
+ *   - Arrays are C order (nz, ny, nx), x fastest, FP32, in device memory of the device that was
+ *     current when the plan was created; that device must be current for every call.
+ *   - Large device memory belongs to the caller: fields, and the plan workspace
+ *     (evx_plan_workspace_bytes / evx_plan_set_workspace).  The plan itself owns host metadata
+ *     and a few KB of device tables (twiddles, per-axis K2).
+ *   - Calls validate synchronously and return a status; work is enqueued asynchronously on the
+ *     given HIP stream (NULL = default stream) and no call synchronises the stream except
+ *     evx_plan_read_pass_times.  On error nothing further is enqueued by that call; the message
+ *     is available from evx_last_error() (thread-local).
+ *   - A plan is not thread-safe; calls on one plan must be serialised by the caller.
+ */
+#ifndef EVX_H_
+#define EVX_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum evx_status {
+  EVX_OK = 0,
+  EVX_ERR_ARG = 1,         /* null pointer, bad enum, non-positive count, wrong device */
+  EVX_ERR_SIZE = 2,        /* grid size not supported (see evx_plan_create) */
+  EVX_ERR_UNSUPPORTED = 3, /* valid request this build does not implement */
+  EVX_ERR_NOMEM = 4,       /* workspace missing or too small, or table allocation failed */
+  EVX_ERR_HIP = 5,         /* a HIP runtime call or kernel launch failed */
+  EVX_ERR_STATE = 6        /* call out of order (e.g. advance before begin) */
+} evx_status;
+
+typedef enum evx_bc { EVX_BC_PERIODIC = 0, EVX_BC_ZERO_FLUX = 1 } evx_bc;
+typedef enum evx_scheme { EVX_SCHEME_SPECTRAL = 0, EVX_SCHEME_STENCIL7 = 1 } evx_scheme;
+
+/* Per-call physics: time step, mobility, gradient-energy coefficient, stabilisation.  They are
+ * per call (not plan fields) so gradient loops over kappa and M never re-plan.  A multiplies
+ * dt K2 alone (not M): P = 1 + A dt K2. */
+typedef struct evx_ch_params {
+  double dt;
+  double M;
+  double kappa;
+  double A;
+} evx_ch_params;
+
+/* Workspace users (bit mask for evx_plan_workspace_bytes). */
+enum { EVX_OP_STEP = 1, EVX_OP_DIAG = 2, EVX_OP_ADJOINT = 4 };
+
+typedef struct evx_plan evx_plan;
+
+/* Create a plan for an nx x ny x nz grid with spacing dx.
+ * Sizes: every axis length must be one of 4 6 8 10 12 16 20 24 32 40 48 50 64 80 96 100 128 160
+ * 192 200 256 320 384 400 512 1024, and nx must be even with nx/2 also in that list for periodic
+ * boundaries (the x transform is a real-to-complex FFT of length nx/2) -> EVX_ERR_SIZE otherwise.
+ * Allocates the device tables on the current device (EVX_ERR_HIP / EVX_ERR_NOMEM on failure).
+ * *out is set only on success and is released with evx_plan_destroy. */
+evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, evx_scheme scheme,
+                           double dx);
+evx_status evx_plan_destroy(evx_plan* plan);
+
+/* Device bytes the caller must provide for the given EVX_OP_* mask.  EVX_OP_STEP needs two
+ * spectral buffers (state S and work W) of nz*ny*(nx/2+1) complex64 (periodic) or nz*ny*nx float
+ * (zero flux) each, i.e. about 8 bytes per voxel. */
+evx_status evx_plan_workspace_bytes(const evx_plan* plan, int ops, size_t* bytes);
+
+/* Hand the plan a device buffer of at least evx_plan_workspace_bytes(plan, ops) bytes,
+ * 256-byte aligned.  The plan keeps the pointer (not ownership) until it is destroyed or given
+ * another buffer; contents are overwritten by the calls below. */
+evx_status evx_plan_set_workspace(evx_plan* plan, void* dev, size_t bytes);
+
+/* Spectral state S (device pointer and size in bytes), for checkpoint/resume: copying S out and
+ * later back in, followed by evx_ch_restore, resumes the trajectory bit-for-bit. */
+evx_status evx_plan_state(const evx_plan* plan, void** dev, size_t* bytes);
+
+/* S <- T[c] and primes the work buffer (W <- F_z^{-1} S).  c: device, nx*ny*nz floats, read. */
+evx_status evx_ch_begin(evx_plan* plan, const float* c, void* hip_stream);
+
+/* nsteps (>= 0) semi-implicit steps on the spectral state.  Requires a prior begin (or restore);
+ * runs the restore pass first if an end consumed the work buffer. */
+evx_status evx_ch_advance(evx_plan* plan, int nsteps, const evx_ch_params* params,
+                          void* hip_stream);
+
+/* c <- T^{-1}[S].  c: device, nx*ny*nz floats, written.  Consumes the work buffer; the next
+ * advance rebuilds it from S. */
+evx_status evx_ch_end(evx_plan* plan, float* c, void* hip_stream);
+
+/* W <- F_z^{-1} S after the caller has written S (resume from a checkpoint). */
+evx_status evx_ch_restore(evx_plan* plan, void* hip_stream);
+
+/* In place: c <- nsteps steps of c (begin + advance + end). */
+evx_status evx_ch_step(evx_plan* plan, float* c, int nsteps, const evx_ch_params* params,
+                       void* hip_stream);
+
+/* Kernel timing for measurement: when enabled, advance records a HIP event pair around every
+ * pass launch on the launch stream.  read synchronises those events and returns, per pass kind
+ * (0 inverse y, 1 fused x, 2 forward y, 3 fused z + update), the summed milliseconds and the
+ * number of launches since the last read. */
+evx_status evx_plan_enable_pass_timing(evx_plan* plan, int on);
+evx_status evx_plan_read_pass_times(evx_plan* plan, double ms[4], long long counts[4]);
+
+/* Block-order option: 1 (default) places consecutive column tiles on the same XCD. */
+evx_status evx_plan_set_xcd_remap(evx_plan* plan, int on);
+
+const char* evx_status_string(evx_status s);
+const char* evx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVX_H_ */

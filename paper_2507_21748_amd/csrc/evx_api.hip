@@ -1,0 +1,356 @@
+// C ABI of the spectral Cahn-Hilliard stepper: plan, workspace, step scheduling, timing.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/evx.h"
+#include "evx_launch.hpp"
+
+using namespace evx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+evx_status fail(evx_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+evx_status hip_fail(hipError_t e, const char* what) {
+  return fail(EVX_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct evx_plan {
+  Geom g;
+  int device = 0;
+  void* tables = nullptr;
+  TablePtrs t{};
+  float2* ws = nullptr;
+  size_t ws_bytes = 0;
+  float2* S = nullptr;
+  float2* W = nullptr;
+  bool begun = false;     // S holds a state
+  bool w_valid = false;   // W holds F_z^{-1} S
+  int remap = 1;
+  // pass timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;  // (pass kind, index of start event in pool)
+  size_t ev_next = 0;
+};
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t spec_bytes(const Geom& g) { return align256(size_t(g.spec) * sizeof(float2)); }
+
+evx_status check_plan(const evx_plan* p) {
+  if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != p->device)
+    return fail(EVX_ERR_ARG, "plan was created on device %d but device %d is current", p->device,
+                dev);
+  return EVX_OK;
+}
+
+evx_status check_params(const evx_ch_params* q) {
+  if (!q) return fail(EVX_ERR_ARG, "params is NULL");
+  if (!(q->dt > 0) || !(q->M >= 0) || !(q->kappa >= 0) || !(q->A >= 0))
+    return fail(EVX_ERR_ARG, "params need dt > 0, M >= 0, kappa >= 0, A >= 0");
+  return EVX_OK;
+}
+
+StepCoef coef_of(const evx_ch_params* q) {
+  return StepCoef{float(q->A * q->dt), float(q->dt * q->M * q->kappa), float(q->dt * q->M)};
+}
+
+// Launcher that optionally brackets each launch with an event pair.
+struct TimedLauncher : HipLauncher {
+  evx_plan* p = nullptr;
+  int kind = -1;
+  hipError_t ev_err = hipSuccess;
+  void mark_begin() {
+    if (!p->timing || kind < 0) return;
+    if (p->ev_next + 2 > p->ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) { ev_err = e; return; }
+        p->ev_pool.push_back(ev);
+      }
+    }
+    const size_t i0 = p->ev_next;
+    p->ev_next += 2;
+    p->ev_used.emplace_back(kind, int(i0));
+    hipError_t e = hipEventRecord(p->ev_pool[i0], stream);
+    if (e != hipSuccess) ev_err = e;
+  }
+  void mark_end() {
+    if (!p->timing || kind < 0 || p->ev_used.empty()) return;
+    hipError_t e = hipEventRecord(p->ev_pool[p->ev_used.back().second + 1], stream);
+    if (e != hipSuccess) ev_err = e;
+  }
+  void col(int n, int bc, int mode, const ColArgs& a) {
+    kind = (mode == COL_INV) ? 0 : (mode == COL_FWD) ? 2 : (mode == COL_Z_UPDATE) ? 3 : -1;
+    mark_begin();
+    HipLauncher::col(n, bc, mode, a);
+    mark_end();
+  }
+  void row(int n, int bc, int mode, const RowArgs& a) {
+    kind = (mode == ROW_FUSED) ? 1 : -1;
+    mark_begin();
+    HipLauncher::row(n, bc, mode, a);
+    mark_end();
+  }
+};
+
+evx_status finish(const TimedLauncher& l, const char* what) {
+  if (l.bad_len) return fail(EVX_ERR_SIZE, "%s: transform length has no kernel", what);
+  if (l.err != hipSuccess) return hip_fail(l.err, what);
+  if (l.ev_err != hipSuccess) return hip_fail(l.ev_err, "pass timing event");
+  return EVX_OK;
+}
+
+TimedLauncher launcher(evx_plan* p, void* s) {
+  TimedLauncher l;
+  l.stream = static_cast<hipStream_t>(s);
+  l.p = p;
+  return l;
+}
+
+bool axis_ok(int n) { return fft_len_supported(n); }
+
+}  // namespace
+
+extern "C" {
+
+const char* evx_status_string(evx_status s) {
+  switch (s) {
+    case EVX_OK: return "ok";
+    case EVX_ERR_ARG: return "invalid argument";
+    case EVX_ERR_SIZE: return "unsupported grid size";
+    case EVX_ERR_UNSUPPORTED: return "unsupported request";
+    case EVX_ERR_NOMEM: return "workspace missing or too small / out of memory";
+    case EVX_ERR_HIP: return "HIP runtime error";
+    case EVX_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* evx_last_error(void) { return g_last_error.c_str(); }
+
+evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, evx_scheme scheme,
+                           double dx) {
+  if (!out) return fail(EVX_ERR_ARG, "out is NULL");
+  if (bc != EVX_BC_PERIODIC && bc != EVX_BC_ZERO_FLUX) return fail(EVX_ERR_ARG, "bad bc %d", bc);
+  if (scheme != EVX_SCHEME_SPECTRAL && scheme != EVX_SCHEME_STENCIL7)
+    return fail(EVX_ERR_ARG, "bad scheme %d", scheme);
+  if (!(dx > 0)) return fail(EVX_ERR_ARG, "dx must be > 0");
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(EVX_ERR_ARG, "sizes must be positive");
+  if (!axis_ok(ny) || !axis_ok(nz)) return fail(EVX_ERR_SIZE, "ny=%d / nz=%d not supported", ny, nz);
+  if (bc == EVX_BC_PERIODIC) {
+    if (nx % 2 != 0 || !axis_ok(nx / 2))
+      return fail(EVX_ERR_SIZE, "periodic nx=%d needs nx/2 in the supported list", nx);
+  } else if (!axis_ok(nx)) {
+    return fail(EVX_ERR_SIZE, "nx=%d not supported", nx);
+  }
+  evx_plan* p = new evx_plan();
+  p->g = make_geom(nx, ny, nz, int(bc), int(scheme), dx);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  const HostTables h = make_tables(p->g);
+  // one allocation: every table at a 256-byte aligned offset
+  struct Part { const void* src; size_t bytes; size_t off; };
+  std::vector<Part> parts = {
+      {h.tw_x.data(), h.tw_x.size() * sizeof(float2), 0},
+      {h.tw_y.data(), h.tw_y.size() * sizeof(float2), 0},
+      {h.tw_z.data(), h.tw_z.size() * sizeof(float2), 0},
+      {h.post_x.data(), h.post_x.size() * sizeof(float2), 0},
+      {h.mk_y.data(), h.mk_y.size() * sizeof(float2), 0},
+      {h.mk_z.data(), h.mk_z.size() * sizeof(float2), 0},
+      {h.k2_x.data(), h.k2_x.size() * sizeof(float), 0},
+      {h.k2_y.data(), h.k2_y.size() * sizeof(float), 0},
+      {h.k2_z.data(), h.k2_z.size() * sizeof(float), 0}};
+  size_t total = 0;
+  for (auto& q : parts) {
+    q.off = total;
+    total += align256(q.bytes > 0 ? q.bytes : 1);
+  }
+  std::vector<unsigned char> host(total, 0);
+  for (auto& q : parts)
+    if (q.bytes) std::memcpy(host.data() + q.off, q.src, q.bytes);
+  e = hipMalloc(&p->tables, total);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(EVX_ERR_NOMEM, "table allocation (%zu bytes): %s", total, hipGetErrorString(e));
+  }
+  e = hipMemcpy(p->tables, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p->tables);
+    delete p;
+    return hip_fail(e, "table upload");
+  }
+  auto at = [&](int i) { return static_cast<unsigned char*>(p->tables) + parts[i].off; };
+  p->t.tw_x = reinterpret_cast<const float2*>(at(0));
+  p->t.tw_y = reinterpret_cast<const float2*>(at(1));
+  p->t.tw_z = reinterpret_cast<const float2*>(at(2));
+  p->t.post_x = reinterpret_cast<const float2*>(at(3));
+  p->t.mk_y = reinterpret_cast<const float2*>(at(4));
+  p->t.mk_z = reinterpret_cast<const float2*>(at(5));
+  p->t.k2_x = reinterpret_cast<const float*>(at(6));
+  p->t.k2_y = reinterpret_cast<const float*>(at(7));
+  p->t.k2_z = reinterpret_cast<const float*>(at(8));
+  *out = p;
+  return EVX_OK;
+}
+
+evx_status evx_plan_destroy(evx_plan* p) {
+  if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
+  for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
+  if (p->tables) (void)hipFree(p->tables);
+  delete p;
+  return EVX_OK;
+}
+
+evx_status evx_plan_workspace_bytes(const evx_plan* p, int ops, size_t* bytes) {
+  if (!p || !bytes) return fail(EVX_ERR_ARG, "NULL argument");
+  if (ops & ~(EVX_OP_STEP)) return fail(EVX_ERR_UNSUPPORTED, "workspace ops 0x%x", ops);
+  *bytes = 2 * spec_bytes(p->g);
+  return EVX_OK;
+}
+
+evx_status evx_plan_set_workspace(evx_plan* p, void* dev, size_t bytes) {
+  if (!p || !dev) return fail(EVX_ERR_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(dev) % 256 != 0)
+    return fail(EVX_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < 2 * spec_bytes(p->g))
+    return fail(EVX_ERR_NOMEM, "workspace of %zu bytes, need %zu", bytes, 2 * spec_bytes(p->g));
+  p->ws = static_cast<float2*>(dev);
+  p->ws_bytes = bytes;
+  p->S = p->ws;
+  p->W = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(p->ws) + spec_bytes(p->g));
+  p->begun = false;
+  p->w_valid = false;
+  return EVX_OK;
+}
+
+evx_status evx_plan_state(const evx_plan* p, void** dev, size_t* bytes) {
+  if (!p || !dev || !bytes) return fail(EVX_ERR_ARG, "NULL argument");
+  if (!p->S) return fail(EVX_ERR_NOMEM, "no workspace set");
+  *dev = p->S;
+  *bytes = size_t(p->g.spec) * sizeof(float2);
+  return EVX_OK;
+}
+
+evx_status evx_ch_begin(evx_plan* p, const float* c, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!c) return fail(EVX_ERR_ARG, "c is NULL");
+  if (!p->S) return fail(EVX_ERR_NOMEM, "no workspace set");
+  TimedLauncher l = launcher(p, s);
+  sched_begin(l, p->g, p->t, c, p->S, p->W, p->remap);
+  st = finish(l, "begin");
+  p->begun = (st == EVX_OK);
+  p->w_valid = p->begun;
+  return st;
+}
+
+evx_status evx_ch_restore(evx_plan* p, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!p->S) return fail(EVX_ERR_NOMEM, "no workspace set");
+  TimedLauncher l = launcher(p, s);
+  sched_restore(l, p->g, p->t, p->S, p->W, p->remap);
+  st = finish(l, "restore");
+  p->begun = (st == EVX_OK);
+  p->w_valid = p->begun;
+  return st;
+}
+
+evx_status evx_ch_advance(evx_plan* p, int nsteps, const evx_ch_params* q, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if ((st = check_params(q)) != EVX_OK) return st;
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  if (!p->begun) return fail(EVX_ERR_STATE, "advance before begin/restore");
+  if (!p->w_valid) {
+    if ((st = evx_ch_restore(p, s)) != EVX_OK) return st;
+  }
+  TimedLauncher l = launcher(p, s);
+  sched_advance(l, p->g, p->t, p->S, p->W, coef_of(q), nsteps, p->remap);
+  return finish(l, "advance");
+}
+
+evx_status evx_ch_end(evx_plan* p, float* c, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!c) return fail(EVX_ERR_ARG, "c is NULL");
+  if (!p->begun) return fail(EVX_ERR_STATE, "end before begin/restore");
+  if (!p->w_valid) {
+    if ((st = evx_ch_restore(p, s)) != EVX_OK) return st;
+  }
+  TimedLauncher l = launcher(p, s);
+  sched_end(l, p->g, p->t, c, p->W, p->remap);
+  p->w_valid = false;
+  return finish(l, "end");
+}
+
+evx_status evx_ch_step(evx_plan* p, float* c, int nsteps, const evx_ch_params* q, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if ((st = check_params(q)) != EVX_OK) return st;
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  if ((st = evx_ch_begin(p, c, s)) != EVX_OK) return st;
+  if ((st = evx_ch_advance(p, nsteps, q, s)) != EVX_OK) return st;
+  return evx_ch_end(p, c, s);
+}
+
+evx_status evx_plan_enable_pass_timing(evx_plan* p, int on) {
+  if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
+  p->timing = on != 0;
+  return EVX_OK;
+}
+
+evx_status evx_plan_read_pass_times(evx_plan* p, double ms[4], long long counts[4]) {
+  if (!p || !ms || !counts) return fail(EVX_ERR_ARG, "NULL argument");
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = 0;
+    counts[k] = 0;
+  }
+  for (auto& u : p->ev_used) {
+    hipError_t e = hipEventSynchronize(p->ev_pool[u.second + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float t = 0;
+    e = hipEventElapsedTime(&t, p->ev_pool[u.second], p->ev_pool[u.second + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    ms[u.first] += t;
+    counts[u.first] += 1;
+  }
+  p->ev_used.clear();
+  p->ev_next = 0;
+  return EVX_OK;
+}
+
+evx_status evx_plan_set_xcd_remap(evx_plan* p, int on) {
+  if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
+  p->remap = on ? 1 : 0;
+  return EVX_OK;
+}
+
+}  // extern "C"

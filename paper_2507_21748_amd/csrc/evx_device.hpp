@@ -1,0 +1,58 @@
+// Thin device layer shared by the gfx950 build and the host emulation build used by the CPU
+// tests.  The kernels below are written as bodies that take (thread, block, LDS) explicitly and
+// call evx_sync() at workgroup barriers; on the GPU those map to threadIdx/blockIdx/__shared__
+// and __syncthreads(), in the emulator to one std::thread per lane and a std::barrier.
+#pragma once
+
+#include <cstdint>
+
+#ifdef EVX_HOST_EMULATION
+#include <barrier>
+#include <cmath>
+
+#define EVX_DEV inline
+#define EVX_HD inline
+#define EVX_RESTRICT
+
+struct float2 {
+  float x, y;
+};
+inline float2 make_float2(float a, float b) { return float2{a, b}; }
+
+namespace evx_emu {
+extern thread_local std::barrier<>* block_barrier;
+}
+inline void evx_sync() { evx_emu::block_barrier->arrive_and_wait(); }
+inline float evx_rcp(float x) { return 1.0f / x; }
+
+#else
+#include <hip/hip_runtime.h>
+
+#define EVX_DEV __device__ __forceinline__
+#define EVX_HD __host__ __device__ __forceinline__
+#define EVX_RESTRICT __restrict__
+
+__device__ __forceinline__ void evx_sync() { __syncthreads(); }
+__device__ __forceinline__ float evx_rcp(float x) { return 1.0f / x; }
+#endif
+
+namespace evx {
+
+EVX_HD float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+EVX_HD float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+EVX_HD float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+EVX_HD float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+EVX_HD float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+EVX_HD float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by +i (dir=+1) or -i (dir=-1)
+template <int SGN>
+EVX_HD float2 cmul_i(float2 a) {
+  return SGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+}  // namespace evx

@@ -1,0 +1,86 @@
+// __global__ wrappers of the pass bodies for one transform length.  This file is compiled once
+// per supported length (EVX_INST_N) so the instantiations build in parallel; each object exports
+// evx_launch_col_<N> and evx_launch_row_<N>.
+#include "evx_launch.hpp"
+
+#ifndef EVX_INST_N
+#error "compile with -DEVX_INST_N=<transform length>"
+#endif
+
+namespace evx {
+
+template <int N, int BC, int MODE>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void col_kernel(ColArgs a) {
+  __shared__ float2 lds[ColCfg<N>::LDS];
+  colpass_body<N, BC, MODE>(a, threadIdx.x, blockIdx.x, gridDim.x, lds);
+}
+
+template <int NH, int BC>
+constexpr int row_threads() {
+  return RowCfg<NH, BC>::THREADS;
+}
+
+template <int NH, int BC, int MODE>
+__global__ __launch_bounds__((row_threads<NH, BC>())) void row_kernel(RowArgs a) {
+  __shared__ float2 lds[RowCfg<NH, BC>::LDS];
+  rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, lds);
+}
+
+template <int N, int BC, int MODE>
+static hipError_t col_go(const ColArgs& a, hipStream_t s) {
+  using C = ColCfg<N>;
+  const long long nblk = (a.nseq + C::B - 1) / C::B;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((col_kernel<N, BC, MODE>), dim3(unsigned(nblk)), dim3(C::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int NH, int BC, int MODE>
+static hipError_t row_go(const RowArgs& a, hipStream_t s) {
+  using C = RowCfg<NH, BC>;
+  const long long nblk = (a.nrows + C::ROWS - 1) / C::ROWS;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((row_kernel<NH, BC, MODE>), dim3(unsigned(nblk)), dim3(C::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N, int BC>
+static hipError_t col_mode(int mode, const ColArgs& a, hipStream_t s) {
+  switch (mode) {
+    case COL_FWD: return col_go<N, BC, COL_FWD>(a, s);
+    case COL_INV: return col_go<N, BC, COL_INV>(a, s);
+    case COL_Z_INIT: return col_go<N, BC, COL_Z_INIT>(a, s);
+    case COL_Z_UPDATE: return col_go<N, BC, COL_Z_UPDATE>(a, s);
+    case COL_Z_INV_STATE: return col_go<N, BC, COL_Z_INV_STATE>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NH, int BC>
+static hipError_t row_mode(int mode, const RowArgs& a, hipStream_t s) {
+  switch (mode) {
+    case ROW_FUSED: return row_go<NH, BC, ROW_FUSED>(a, s);
+    case ROW_FWD: return row_go<NH, BC, ROW_FWD>(a, s);
+    case ROW_INV: return row_go<NH, BC, ROW_INV>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define EVX_PASTE2(a, b) a##b
+#define EVX_PASTE(a, b) EVX_PASTE2(a, b)
+
+hipError_t EVX_PASTE(evx_launch_col_, EVX_INST_N)(int bc, int mode, const ColArgs& a,
+                                                  hipStream_t s) {
+  return bc == BC_PERIODIC ? col_mode<EVX_INST_N, BC_PERIODIC>(mode, a, s)
+                           : col_mode<EVX_INST_N, BC_ZERO_FLUX>(mode, a, s);
+}
+
+hipError_t EVX_PASTE(evx_launch_row_, EVX_INST_N)(int bc, int mode, const RowArgs& a,
+                                                  hipStream_t s) {
+  return bc == BC_PERIODIC ? row_mode<EVX_INST_N, BC_PERIODIC>(mode, a, s)
+                           : row_mode<EVX_INST_N, BC_ZERO_FLUX>(mode, a, s);
+}
+
+}  // namespace evx

@@ -1,0 +1,44 @@
+// Declarations of the per-length launchers and the HIP launcher object used by the schedule.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "evx_schedule.hpp"
+
+namespace evx {
+
+#define EVX_DECL(N)                                                                     \
+  hipError_t evx_launch_col_##N(int bc, int mode, const ColArgs& a, hipStream_t s);      \
+  hipError_t evx_launch_row_##N(int bc, int mode, const RowArgs& a, hipStream_t s);
+EVX_FOR_EACH_N(EVX_DECL)
+#undef EVX_DECL
+
+// Records the first launch error; the schedule keeps enqueuing nothing after one.
+struct HipLauncher {
+  hipStream_t stream = nullptr;
+  hipError_t err = hipSuccess;
+  bool bad_len = false;
+
+  void col(int n, int bc, int mode, const ColArgs& a) {
+    if (err != hipSuccess || bad_len) return;
+    switch (n) {
+#define EVX_CASE(N) \
+  case N: err = evx_launch_col_##N(bc, mode, a, stream); return;
+      EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+      default: bad_len = true;
+    }
+  }
+  void row(int n, int bc, int mode, const RowArgs& a) {
+    if (err != hipSuccess || bad_len) return;
+    switch (n) {
+#define EVX_CASE(N) \
+  case N: err = evx_launch_row_##N(bc, mode, a, stream); return;
+      EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+      default: bad_len = true;
+    }
+  }
+};
+
+}  // namespace evx

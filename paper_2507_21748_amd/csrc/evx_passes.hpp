@@ -1,0 +1,406 @@
+// Pass bodies of the Cahn-Hilliard spectral step.  Each body is the work of one workgroup; it
+// is wrapped by a __global__ kernel for gfx950 and by a threaded host emulator in the CPU tests.
+//
+// Data layout (C order, x fastest).  Periodic: the half spectrum, nz x ny x (nx/2+1) complex.
+// Zero flux: the DCT-II spectrum is real, nz x ny x nx floats, handled as nx/2 float2 "column
+// pairs" by the y and z passes.  Two such buffers exist: S (spectral state) and W (work).
+//
+// One time step is four passes over W (and one over S):
+//   inverse y  ->  x: inverse x, f'(c) = c^3 - c, forward x  ->  forward y  ->
+//   z: forward z, k-space update of S, inverse z.
+// The real-space field is never stored between steps.
+#pragma once
+
+#include "evx_fft.hpp"
+
+namespace evx {
+
+enum : int { BC_PERIODIC = 0, BC_ZERO_FLUX = 1 };
+
+// column (y or z) pass modes
+enum : int {
+  COL_FWD = 0,         // in -> forward transform -> out
+  COL_INV = 1,         // in -> inverse transform -> out
+  COL_Z_INIT = 2,      // in -> forward -> state; -> inverse -> out
+  COL_Z_UPDATE = 3,    // in -> forward -> k-space update of state -> inverse -> out
+  COL_Z_INV_STATE = 4  // state -> inverse -> out
+};
+
+// row (x) pass modes
+enum : int {
+  ROW_FUSED = 0,  // complex row -> inverse x -> f' -> forward x -> complex row
+  ROW_FWD = 1,    // real row -> forward x -> complex row
+  ROW_INV = 2     // complex row -> inverse x -> real row
+};
+
+struct ColArgs {
+  const float2* in;
+  float2* out;
+  float2* state;
+  long long nseq;          // sequences = ncols * nouter
+  int ncols;               // float2 columns per row of the array
+  long long row_stride;    // float2 stride between consecutive points of the transform axis
+  long long outer_stride;  // float2 stride between consecutive outer indices
+  const float2* tw;        // exp(-2 pi i j / N), j < N
+  const float2* mk;        // zero flux: exp(-i pi k / (2N)), k < N
+  const float* k2c;        // K2 along the column axis (x): nx/2+1 entries, or nx for zero flux
+  const float* k2o;        // K2 along the outer axis
+  const float* k2r;        // K2 along the transform axis
+  float a_dt;              // A dt
+  float dt_m_kappa;        // dt M kappa
+  float dt_m;              // dt M
+  int remap;               // XCD-aware block order
+};
+
+struct RowArgs {
+  const float2* in_c;
+  const float* in_r;
+  float2* out_c;
+  float* out_r;
+  long long nrows;     // rows of nx real points (ny * nz)
+  const float2* tw;    // row FFT twiddles
+  const float2* post;  // periodic: exp(-2 pi i k / nx), k <= nx/2; zero flux: exp(-i pi k/(2 nx))
+  float scale;         // 1/V (periodic) or 1/(8V) (zero flux), applied after the inverse
+};
+
+// Block order: consecutive logical blocks (neighbouring columns, sharing 128-byte lines) are
+// placed on the same XCD.  Hardware dispatches block i to XCD i % 8.
+EVX_DEV int remap_block(int bid, int nblk, int on) {
+  if (!on) return bid;
+  const int per = nblk / 8;
+  if (bid >= per * 8) return bid;
+  return (bid % 8) * per + bid / 8;
+}
+
+EVX_DEV float fprime(float c) { return c * c * c - c; }
+
+// Index of the cell-centred input point that becomes point n of Makhoul's reordered sequence
+// (v_n = x_{2n} for 2n < N, else x_{2N-2n-1}).
+template <int N>
+EVX_DEV int makhoul_src(int n) {
+  return (2 * n < N) ? 2 * n : 2 * N - 2 * n - 1;
+}
+
+// ------------------------------------------------------------------ column pass
+template <int N>
+struct ColCfg {
+  static constexpr int E = FftPlan<N>::E;
+  static constexpr int TPS = FftPlan<N>::TPS;
+  static constexpr int B = seqs_per_block<N>();
+  static constexpr int THREADS = B * TPS;
+  static constexpr int LDS = B * N;  // float2 slots
+};
+
+// Zero flux, after a forward FFT of packed columns (a + i b): x holds Z[k], k = t + TPS e.
+// Produces (Da[k], Db[k]) with D[k] = 2 sum_n x_n cos(pi k (2n+1) / 2N) (Makhoul).
+template <int N, int B>
+EVX_DEV void makhoul_post(float2 (&x)[FftPlan<N>::E], float2* lds, int b, int t,
+                          const float2* EVX_RESTRICT mk) {
+  constexpr int E = FftPlan<N>::E, TPS = FftPlan<N>::TPS;
+  static_for<E>([&](auto e) { lds[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });
+  evx_sync();
+  static_for<E>([&](auto e) {
+    const int k = t + TPS * decltype(e)::value;
+    const int kr = (k == 0) ? 0 : N - k;
+    const float2 P = x[e];
+    const float2 Q = cconj(lds[lidx<B>(kr, b)]);
+    const float2 w = mk[k];
+    const float2 sp = cmul(w, cadd(P, Q));
+    const float2 sm = cmul(w, csub(P, Q));
+    x[e] = make_float2(sp.x, sm.y);
+  });
+  evx_sync();
+}
+
+// Zero flux, before an inverse FFT: x holds (Da[k], Db[k]); produces
+// Z[k] = Va[k] + i Vb[k],  V[k] = exp(i pi k / 2N) (D[k] - i D[N-k]),  D[N] = 0.
+template <int N, int B>
+EVX_DEV void makhoul_pre(float2 (&x)[FftPlan<N>::E], float2* lds, int b, int t,
+                         const float2* EVX_RESTRICT mk) {
+  constexpr int E = FftPlan<N>::E, TPS = FftPlan<N>::TPS;
+  static_for<E>([&](auto e) { lds[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });
+  evx_sync();
+  static_for<E>([&](auto e) {
+    const int k = t + TPS * decltype(e)::value;
+    const float2 D = x[e];
+    const float2 Dr = (k == 0) ? make_float2(0.f, 0.f) : lds[lidx<B>(N - k, b)];
+    const float2 w = cconj(mk[k]);
+    const float2 va = cmul(w, make_float2(D.x, -Dr.x));
+    const float2 vb = cmul(w, make_float2(D.y, -Dr.y));
+    x[e] = make_float2(va.x - vb.y, va.y + vb.x);
+  });
+  evx_sync();
+}
+
+template <int N, int BC, int MODE>
+EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* lds) {
+  using C = ColCfg<N>;
+  constexpr int E = C::E, TPS = C::TPS, B = C::B;
+  const int lb = remap_block(bid, nblk, a.remap);
+  const int b = tid % B;
+  const int t = tid / B;
+  const long long seq = (long long)lb * B + b;
+  const bool live = seq < a.nseq;
+  long long outer = 0, col = 0;
+  if (live) {
+    outer = seq / a.ncols;
+    col = seq - outer * a.ncols;
+  }
+  const long long base = outer * a.outer_stride + col;
+  float2 x[E];
+
+  constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE;
+  constexpr bool has_inv = MODE != COL_FWD;
+
+  if constexpr (MODE == COL_Z_INV_STATE) {
+    static_for<E>([&](auto e) {
+      const int n = t + TPS * decltype(e)::value;
+      x[e] = live ? a.state[base + (long long)n * a.row_stride] : make_float2(0.f, 0.f);
+    });
+  } else {
+    static_for<E>([&](auto e) {
+      const int n = t + TPS * decltype(e)::value;
+      const int row = (BC == BC_ZERO_FLUX && has_fwd) ? makhoul_src<N>(n) : n;
+      x[e] = live ? a.in[base + (long long)row * a.row_stride] : make_float2(0.f, 0.f);
+    });
+  }
+
+  if constexpr (has_fwd) {
+    fft_regs<N, -1, B>(x, lds, b, t, a.tw);
+    if constexpr (BC == BC_ZERO_FLUX) makhoul_post<N, B>(x, lds, b, t, a.mk);
+  }
+
+  if constexpr (MODE == COL_FWD) {
+    if (live) {
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        a.out[base + (long long)k * a.row_stride] = x[e];
+      });
+    }
+    return;
+  }
+
+  if constexpr (MODE == COL_Z_INIT) {
+    if (live) {
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        a.state[base + (long long)k * a.row_stride] = x[e];
+      });
+    }
+  }
+
+  if constexpr (MODE == COL_Z_UPDATE) {
+    // C' = G (P C - dt M K2 F), P = 1 + A dt K2, G = 1 / (1 + dt M kappa K2^2 + A dt K2)
+    if (live) {
+      const float ko = a.k2o[outer];
+      float kca, kcb;
+      if constexpr (BC == BC_ZERO_FLUX) {
+        kca = a.k2c[2 * col] + ko;
+        kcb = a.k2c[2 * col + 1] + ko;
+      } else {
+        kca = a.k2c[col] + ko;
+        kcb = kca;
+      }
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        const long long idx = base + (long long)k * a.row_stride;
+        const float kr = a.k2r[k];
+        const float2 Cs = a.state[idx];
+        const float2 F = x[e];
+        const float K2a = kca + kr, K2b = kcb + kr;
+        const float Pa = 1.0f + a.a_dt * K2a, Pb = 1.0f + a.a_dt * K2b;
+        const float Ga = evx_rcp(1.0f + a.dt_m_kappa * K2a * K2a + a.a_dt * K2a);
+        const float Gb = evx_rcp(1.0f + a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
+        const float2 nv = make_float2(Ga * (Pa * Cs.x - a.dt_m * K2a * F.x),
+                                      Gb * (Pb * Cs.y - a.dt_m * K2b * F.y));
+        a.state[idx] = nv;
+        x[e] = nv;
+      });
+    } else {
+      static_for<E>([&](auto e) { x[e] = make_float2(0.f, 0.f); });
+    }
+  }
+
+  if constexpr (has_inv) {
+    if constexpr (BC == BC_ZERO_FLUX) makhoul_pre<N, B>(x, lds, b, t, a.mk);
+    fft_regs<N, +1, B>(x, lds, b, t, a.tw);
+    if (live) {
+      static_for<E>([&](auto e) {
+        const int n = t + TPS * decltype(e)::value;
+        const int row = (BC == BC_ZERO_FLUX) ? makhoul_src<N>(n) : n;
+        a.out[base + (long long)row * a.row_stride] = x[e];
+      });
+    }
+  }
+}
+
+// ------------------------------------------------------------------ row pass
+// Periodic: template length NH = nx/2, the complex FFT length of the packed real row; the row
+// has NH+1 complex points.  Zero flux: NH = nx, one sequence carries two rows packed as a + i b.
+template <int NH, int BC>
+struct RowCfg {
+  static constexpr int E = FftPlan<NH>::E;
+  static constexpr int TPS = FftPlan<NH>::TPS;
+  static constexpr int B = seqs_per_block<NH>();       // sequences per block
+  static constexpr int THREADS = B * TPS;
+  static constexpr int ROWS = (BC == BC_PERIODIC) ? B : 2 * B;  // rows per block
+  static constexpr int STAGE = (BC == BC_PERIODIC) ? B * (NH + 1) : B * NH;  // float2 slots
+  static constexpr int LDS = STAGE > B * NH ? STAGE : B * NH;
+};
+
+template <int NH, int BC, int MODE>
+EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
+  using C = RowCfg<NH, BC>;
+  constexpr int E = C::E, TPS = C::TPS, B = C::B, T = C::THREADS;
+  const int b = tid % B;
+  const int t = tid / B;
+  const long long r0 = (long long)bid * C::ROWS;
+  float2 x[E];
+
+  if constexpr (BC == BC_PERIODIC) {
+    constexpr int NX = 2 * NH, W = NH + 1;
+    // ---------------------------------------------------------------- input
+    if constexpr (MODE == ROW_FWD) {
+      // real rows, read as pairs (c[2n], c[2n+1]) into stage[b*NH + n]
+      const float2* src = reinterpret_cast<const float2*>(a.in_r);
+      for (int i = tid; i < B * NH; i += T) {
+        const int rr = i / NH;
+        x[0] = (r0 + rr < a.nrows) ? src[r0 * NH + i] : make_float2(0.f, 0.f);
+        lds[i] = x[0];
+      }
+      evx_sync();
+      static_for<E>([&](auto e) { x[e] = lds[b * NH + t + TPS * decltype(e)::value]; });
+      evx_sync();
+    } else {
+      for (int i = tid; i < B * W; i += T) {
+        const int rr = i / W;
+        lds[i] = (r0 + rr < a.nrows) ? a.in_c[r0 * W + i] : make_float2(0.f, 0.f);
+      }
+      evx_sync();
+      // C2R pre-processing: Z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) e^{+2pi i k/NX}
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        const float2 X = lds[b * W + k];
+        const float2 Xr = cconj(lds[b * W + NH - k]);
+        const float2 Ev = cadd(X, Xr);
+        const float2 Od = cmulc(csub(X, Xr), a.post[k]);
+        x[e] = make_float2(Ev.x - Od.y, Ev.y + Od.x);
+      });
+      evx_sync();
+      fft_regs<NH, +1, B>(x, lds, b, t, a.tw);
+      static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
+      if constexpr (MODE == ROW_INV) {
+        static_for<E>([&](auto e) { lds[b * NH + t + TPS * decltype(e)::value] = x[e]; });
+        evx_sync();
+        float2* dst = reinterpret_cast<float2*>(a.out_r);
+        for (int i = tid; i < B * NH; i += T) {
+          const int rr = i / NH;
+          if (r0 + rr < a.nrows) dst[r0 * NH + i] = lds[i];
+        }
+        return;
+      }
+      static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
+    }
+    // ---------------------------------------------------------------- forward x (R2C)
+    fft_regs<NH, -1, B>(x, lds, b, t, a.tw);
+    static_for<E>([&](auto e) { lds[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });
+    evx_sync();
+    float2 y[E];
+    float2 ynyq = make_float2(0.f, 0.f);
+    static_for<E>([&](auto e) {
+      const int k = t + TPS * decltype(e)::value;
+      const float2 P = x[e];
+      const float2 Q = cconj(lds[lidx<B>(k == 0 ? 0 : NH - k, b)]);
+      const float2 Ev = cscale(cadd(P, Q), 0.5f);
+      const float2 dq = cscale(csub(P, Q), 0.5f);
+      const float2 Od = make_float2(dq.y, -dq.x);  // -i (P - Q) / 2
+      y[e] = cadd(Ev, cmul(a.post[k], Od));
+      if (k == 0) ynyq = make_float2(Ev.x - Od.x, 0.f);
+    });
+    evx_sync();
+    static_for<E>([&](auto e) { lds[b * W + t + TPS * decltype(e)::value] = y[e]; });
+    if (t == 0) lds[b * W + NH] = ynyq;
+    evx_sync();
+    for (int i = tid; i < B * W; i += T) {
+      const int rr = i / W;
+      if (r0 + rr < a.nrows) a.out_c[r0 * W + i] = lds[i];
+    }
+    (void)NX;
+  } else {
+    // zero flux: rows ra = r0 + 2b, rb = ra + 1, stage as floats [2B][NH]
+    constexpr int NX = NH;
+    float* st = reinterpret_cast<float*>(lds);
+    const float* in = (MODE == ROW_FWD) ? a.in_r : reinterpret_cast<const float*>(a.in_c);
+    if constexpr (MODE == ROW_FWD || MODE == ROW_FUSED || MODE == ROW_INV) {
+      for (int i = tid; i < 2 * B * NX; i += T) {
+        const int rr = i / NX;
+        st[i] = (r0 + rr < a.nrows) ? in[r0 * NX + i] : 0.f;
+      }
+      evx_sync();
+    }
+    if constexpr (MODE == ROW_FWD) {
+      static_for<E>([&](auto e) {
+        const int n = t + TPS * decltype(e)::value;
+        const int s = makhoul_src<NX>(n);
+        x[e] = make_float2(st[(2 * b) * NX + s], st[(2 * b + 1) * NX + s]);
+      });
+      evx_sync();
+    } else {
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        const float Da = st[(2 * b) * NX + k], Db = st[(2 * b + 1) * NX + k];
+        const float Dar = (k == 0) ? 0.f : st[(2 * b) * NX + NX - k];
+        const float Dbr = (k == 0) ? 0.f : st[(2 * b + 1) * NX + NX - k];
+        const float2 w = cconj(a.post[k]);
+        const float2 va = cmul(w, make_float2(Da, -Dar));
+        const float2 vb = cmul(w, make_float2(Db, -Dbr));
+        x[e] = make_float2(va.x - vb.y, va.y + vb.x);
+      });
+      evx_sync();
+      fft_regs<NX, +1, B>(x, lds, b, t, a.tw);
+      static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
+      if constexpr (MODE == ROW_INV) {
+        static_for<E>([&](auto e) {
+          const int n = t + TPS * decltype(e)::value;
+          const int s = makhoul_src<NX>(n);
+          st[(2 * b) * NX + s] = x[e].x;
+          st[(2 * b + 1) * NX + s] = x[e].y;
+        });
+        evx_sync();
+        for (int i = tid; i < 2 * B * NX; i += T) {
+          const int rr = i / NX;
+          if (r0 + rr < a.nrows) a.out_r[r0 * NX + i] = st[i];
+        }
+        return;
+      }
+      static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
+    }
+    fft_regs<NX, -1, B>(x, lds, b, t, a.tw);
+    static_for<E>([&](auto e) { lds[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });
+    evx_sync();
+    float2 y[E];
+    static_for<E>([&](auto e) {
+      const int k = t + TPS * decltype(e)::value;
+      const float2 P = x[e];
+      const float2 Q = cconj(lds[lidx<B>(k == 0 ? 0 : NX - k, b)]);
+      const float2 w = a.post[k];
+      const float2 sp = cmul(w, cadd(P, Q));
+      const float2 sm = cmul(w, csub(P, Q));
+      y[e] = make_float2(sp.x, sm.y);
+    });
+    evx_sync();
+    static_for<E>([&](auto e) {
+      const int k = t + TPS * decltype(e)::value;
+      st[(2 * b) * NX + k] = y[e].x;
+      st[(2 * b + 1) * NX + k] = y[e].y;
+    });
+    evx_sync();
+    float* out = reinterpret_cast<float*>(a.out_c);
+    for (int i = tid; i < 2 * B * NX; i += T) {
+      const int rr = i / NX;
+      if (r0 + rr < a.nrows) out[r0 * NX + i] = st[i];
+    }
+  }
+}
+
+}  // namespace evx

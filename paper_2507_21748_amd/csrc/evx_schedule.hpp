@@ -1,0 +1,228 @@
+// Host-side geometry, tables and pass schedule of the spectral CH step.  Shared by the HIP
+// launcher and by the host emulator used in the CPU tests, so both run the same sequence of
+// passes with the same arguments.
+#pragma once
+
+#include <cmath>
+#include <cstddef>
+#include <vector>
+
+#include "evx_passes.hpp"
+
+namespace evx {
+
+// Supported transform lengths (every FftPlan specialisation).  A test build may predefine a
+// shorter list.
+#ifndef EVX_FOR_EACH_N
+#define EVX_FOR_EACH_N(X) \
+  X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(50) X(64) X(80) X(96) \
+  X(100) X(128) X(160) X(192) X(200) X(256) X(320) X(384) X(400) X(512) X(1024)
+#endif
+
+inline bool fft_len_supported(int n) {
+  switch (n) {
+#define EVX_CASE(N) case N:
+    EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+struct Geom {
+  int nx = 0, ny = 0, nz = 0;
+  int bc = BC_PERIODIC;
+  int scheme = 0;        // 0 spectral, 1 stencil7
+  double dx = 1.0;       // grid spacing baked into the K2 tables
+  long long V = 0;       // voxels
+  int ncols = 0;         // float2 columns per row of a spectral buffer
+  int row_len = 0;       // x-pass FFT length: nx/2 (periodic) or nx (zero flux)
+  long long spec = 0;    // float2 per spectral buffer
+  long long nrows = 0;   // ny * nz
+};
+
+inline Geom make_geom(int nx, int ny, int nz, int bc, int scheme, double dx) {
+  Geom g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.bc = bc;
+  g.scheme = scheme;
+  g.dx = dx;
+  g.V = (long long)nx * ny * nz;
+  g.ncols = (bc == BC_PERIODIC) ? nx / 2 + 1 : nx / 2;
+  g.row_len = (bc == BC_PERIODIC) ? nx / 2 : nx;
+  g.spec = (long long)nz * ny * g.ncols;
+  g.nrows = (long long)ny * nz;
+  return g;
+}
+
+// Host copies of every table, FP64-computed and rounded once.
+struct HostTables {
+  std::vector<float2> tw_x, tw_y, tw_z;  // exp(-2 pi i j / N) for the x-row, y and z FFT lengths
+  std::vector<float2> post_x;            // periodic exp(-2 pi i k / nx), k <= nx/2; zf below
+  std::vector<float2> mk_x, mk_y, mk_z;  // zero flux exp(-i pi k / (2N)), k < N
+  std::vector<float> k2_x, k2_y, k2_z;   // per-axis K2
+};
+
+inline std::vector<float2> twiddles(int n) {
+  std::vector<float2> t(n);
+  for (int j = 0; j < n; ++j) {
+    const double a = -2.0 * M_PI * double(j) / double(n);
+    t[j] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
+  return t;
+}
+
+inline std::vector<float2> makhoul_twiddles(int n) {
+  std::vector<float2> t(n);
+  for (int k = 0; k < n; ++k) {
+    const double a = -M_PI * double(k) / (2.0 * double(n));
+    t[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
+  return t;
+}
+
+// Eigenvalue of -d2/dx2 for mode m on an axis of n cells (periodic: k = 2 pi m'/(n dx), zero
+// flux: k = pi m / (n dx)); spectral k^2 or 3-point stencil (4/dx^2) sin^2(k dx / 2).
+inline double axis_k2(int m, int n, int bc, int scheme, double dx) {
+  double k;
+  if (bc == BC_PERIODIC) {
+    const int mp = (m <= n / 2) ? m : m - n;
+    k = 2.0 * M_PI * double(mp) / (double(n) * dx);
+  } else {
+    k = M_PI * double(m) / (double(n) * dx);
+  }
+  if (scheme == 0) return k * k;
+  const double s = std::sin(0.5 * k * dx);
+  return 4.0 / (dx * dx) * s * s;
+}
+
+inline std::vector<float> k2_table(int count, int n, int bc, int scheme, double dx) {
+  std::vector<float> t(count);
+  for (int m = 0; m < count; ++m) t[m] = float(axis_k2(m, n, bc, scheme, dx));
+  return t;
+}
+
+inline HostTables make_tables(const Geom& g) {
+  HostTables h;
+  h.tw_x = twiddles(g.row_len);
+  h.tw_y = twiddles(g.ny);
+  h.tw_z = twiddles(g.nz);
+  if (g.bc == BC_PERIODIC) {
+    h.post_x.resize(g.nx / 2 + 1);
+    for (int k = 0; k <= g.nx / 2; ++k) {
+      const double a = -2.0 * M_PI * double(k) / double(g.nx);
+      h.post_x[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    }
+    h.k2_x = k2_table(g.nx / 2 + 1, g.nx, g.bc, g.scheme, g.dx);
+  } else {
+    h.post_x = makhoul_twiddles(g.nx);
+    h.mk_y = makhoul_twiddles(g.ny);
+    h.mk_z = makhoul_twiddles(g.nz);
+    h.k2_x = k2_table(g.nx, g.nx, g.bc, g.scheme, g.dx);
+  }
+  h.k2_y = k2_table(g.ny, g.ny, g.bc, g.scheme, g.dx);
+  h.k2_z = k2_table(g.nz, g.nz, g.bc, g.scheme, g.dx);
+  return h;
+}
+
+// Pointers to the tables as the kernels see them (device or host copies).
+struct TablePtrs {
+  const float2 *tw_x, *tw_y, *tw_z, *post_x, *mk_y, *mk_z;
+  const float *k2_x, *k2_y, *k2_z;
+};
+
+struct StepCoef {
+  float a_dt, dt_m_kappa, dt_m;
+};
+
+inline ColArgs y_args(const Geom& g, const TablePtrs& t, const float2* in, float2* out,
+                      int remap) {
+  ColArgs a{};
+  a.in = in;
+  a.out = out;
+  a.nseq = (long long)g.ncols * g.nz;
+  a.ncols = g.ncols;
+  a.row_stride = g.ncols;
+  a.outer_stride = (long long)g.ncols * g.ny;
+  a.tw = t.tw_y;
+  a.mk = t.mk_y;
+  a.remap = remap;
+  return a;
+}
+
+inline ColArgs z_args(const Geom& g, const TablePtrs& t, const float2* in, float2* out,
+                      float2* state, StepCoef c, int remap) {
+  ColArgs a{};
+  a.in = in;
+  a.out = out;
+  a.state = state;
+  a.nseq = (long long)g.ncols * g.ny;
+  a.ncols = g.ncols;
+  a.row_stride = (long long)g.ncols * g.ny;
+  a.outer_stride = g.ncols;
+  a.tw = t.tw_z;
+  a.mk = t.mk_z;
+  a.k2c = t.k2_x;
+  a.k2o = t.k2_y;
+  a.k2r = t.k2_z;
+  a.a_dt = c.a_dt;
+  a.dt_m_kappa = c.dt_m_kappa;
+  a.dt_m = c.dt_m;
+  a.remap = remap;
+  return a;
+}
+
+inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, const float* in_r,
+                      float2* out_c, float* out_r) {
+  RowArgs a{};
+  a.in_c = in_c;
+  a.in_r = in_r;
+  a.out_c = out_c;
+  a.out_r = out_r;
+  a.nrows = g.nrows;
+  a.tw = t.tw_x;
+  a.post = t.post_x;
+  a.scale = (g.bc == BC_PERIODIC) ? float(1.0 / double(g.V)) : float(1.0 / (8.0 * double(g.V)));
+  return a;
+}
+
+// Launcher L provides col(N, bc, mode, ColArgs) and row(NH, bc, mode, RowArgs).
+
+// Initial forward transform of the real field c: S <- T[c], W <- F_z^{-1} S.
+template <class L>
+void sched_begin(L& l, const Geom& g, const TablePtrs& t, const float* c, float2* S, float2* W,
+                 int remap) {
+  l.row(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, c, W, nullptr));
+  l.col(g.ny, g.bc, COL_FWD, y_args(g, t, W, W, remap));
+  l.col(g.nz, g.bc, COL_Z_INIT, z_args(g, t, W, W, S, StepCoef{0, 0, 0}, remap));
+}
+
+// nsteps steps; W must hold F_z^{-1} S on entry and holds it again on exit.
+template <class L>
+void sched_advance(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, StepCoef c,
+                   int nsteps, int remap) {
+  for (int n = 0; n < nsteps; ++n) {
+    l.col(g.ny, g.bc, COL_INV, y_args(g, t, W, W, remap));
+    l.row(g.row_len, g.bc, ROW_FUSED, x_args(g, t, W, nullptr, W, nullptr));
+    l.col(g.ny, g.bc, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.nz, g.bc, COL_Z_UPDATE, z_args(g, t, W, W, S, c, remap));
+  }
+}
+
+// Real field from W = F_z^{-1} S (consumes W).
+template <class L>
+void sched_end(L& l, const Geom& g, const TablePtrs& t, float* c, float2* W, int remap) {
+  l.col(g.ny, g.bc, COL_INV, y_args(g, t, W, W, remap));
+  l.row(g.row_len, g.bc, ROW_INV, x_args(g, t, W, nullptr, nullptr, c));
+}
+
+// W <- F_z^{-1} S (restores the loop-entry buffer from the state).
+template <class L>
+void sched_restore(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, int remap) {
+  l.col(g.nz, g.bc, COL_Z_INV_STATE, z_args(g, t, nullptr, W, S, StepCoef{0, 0, 0}, remap));
+}
+
+}  // namespace evx

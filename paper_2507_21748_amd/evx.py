@@ -1,0 +1,193 @@
+"""Python binding of libevx (ctypes).  Argument marshalling only: every step of the path runs in
+the library's HIP kernels; PyTorch supplies device memory and the current stream.
+
+There is no CPU fallback: if the built library is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME"]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+BC = {"periodic": 0, "zero_flux": 1}
+SCHEME = {"spectral": 0, "stencil7": 1}
+
+OP_STEP, OP_DIAG, OP_ADJOINT = 1, 2, 4
+
+
+class EvxError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("M", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("A", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class CHParams:
+    dt: float = 0.1
+    M: float = 1.0
+    kappa: float = 1.0
+    A: float = 2.0
+
+    def c(self) -> _Params:
+        return _Params(self.dt, self.M, self.kappa, self.A)
+
+
+def lib_path() -> str:
+    return os.path.join(_PKG, "libevx.so")
+
+
+_PROTOS = {
+    "evx_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                        ctypes.c_int, ctypes.c_int, ctypes.c_double],
+    "evx_plan_destroy": [ctypes.c_void_p],
+    "evx_plan_workspace_bytes": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "evx_plan_set_workspace": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t],
+    "evx_plan_state": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                       ctypes.POINTER(ctypes.c_size_t)],
+    "evx_ch_begin": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "evx_ch_advance": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params), ctypes.c_void_p],
+    "evx_ch_end": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "evx_ch_restore": [ctypes.c_void_p, ctypes.c_void_p],
+    "evx_ch_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
+                    ctypes.c_void_p],
+    "evx_plan_enable_pass_timing": [ctypes.c_void_p, ctypes.c_int],
+    "evx_plan_read_pass_times": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_longlong)],
+    "evx_plan_set_xcd_remap": [ctypes.c_void_p, ctypes.c_int],
+}
+
+
+def load():
+    """Load libevx.so (built in-tree by build()); raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(there is no fallback path)")
+    lib = ctypes.CDLL(path)
+    for name, args in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.evx_status_string.argtypes = [ctypes.c_int]
+    lib.evx_status_string.restype = ctypes.c_char_p
+    lib.evx_last_error.argtypes = []
+    lib.evx_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        msg = _LIB.evx_last_error().decode(errors="replace")
+        raise EvxError(status, where, msg)
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype=torch.float32, numel=None):
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"tensor must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"tensor has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A grid (nz, ny, nx) with boundary condition and wavenumber scheme, plus its workspace."""
+
+    def __init__(self, shape, bc: str = "periodic", scheme: str = "spectral", dx: float = 1.0,
+                 ops: int = OP_STEP, device=None):
+        lib = load()
+        self.shape = tuple(int(s) for s in shape)
+        self.bc, self.scheme, self.dx = bc, scheme, float(dx)
+        nz, ny, nx = self.shape
+        self.voxels = nx * ny * nz
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.device = dev
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            _check(lib.evx_plan_create(ctypes.byref(h), nx, ny, nz, BC[bc], SCHEME[scheme],
+                                       self.dx), "evx_plan_create")
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(lib.evx_plan_workspace_bytes(h, ops, ctypes.byref(nb)), "evx_plan_workspace_bytes")
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        _check(lib.evx_plan_set_workspace(h, ctypes.c_void_p(base + self._ws_off), nb.value),
+               "evx_plan_set_workspace")
+        self.workspace_bytes = nb.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _LIB is not None:
+            _LIB.evx_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------ stepping
+    def step(self, c: torch.Tensor, nsteps: int, params: CHParams, stream=None):
+        """In place: c <- nsteps steps of c."""
+        p = params.c()
+        _check(_LIB.evx_ch_step(self._h, _dev_ptr(c, numel=self.voxels), int(nsteps),
+                                ctypes.byref(p), _stream_handle(stream)), "evx_ch_step")
+        return c
+
+    def begin(self, c: torch.Tensor, stream=None):
+        _check(_LIB.evx_ch_begin(self._h, _dev_ptr(c, numel=self.voxels), _stream_handle(stream)),
+               "evx_ch_begin")
+
+    def advance(self, nsteps: int, params: CHParams, stream=None):
+        p = params.c()
+        _check(_LIB.evx_ch_advance(self._h, int(nsteps), ctypes.byref(p), _stream_handle(stream)),
+               "evx_ch_advance")
+
+    def end(self, c: torch.Tensor, stream=None):
+        _check(_LIB.evx_ch_end(self._h, _dev_ptr(c, numel=self.voxels), _stream_handle(stream)),
+               "evx_ch_end")
+        return c
+
+    def restore(self, stream=None):
+        _check(_LIB.evx_ch_restore(self._h, _stream_handle(stream)), "evx_ch_restore")
+
+    def state(self) -> torch.Tensor:
+        """The spectral state S as a uint8 view of the workspace (for checkpoint/resume)."""
+        ptr, nb = ctypes.c_void_p(), ctypes.c_size_t()
+        _check(_LIB.evx_plan_state(self._h, ctypes.byref(ptr), ctypes.byref(nb)), "evx_plan_state")
+        off = ptr.value - self.workspace.data_ptr()
+        return self.workspace[off:off + nb.value]
+
+    # ------------------------------------------------------------------ measurement
+    def enable_pass_timing(self, on: bool = True):
+        _check(_LIB.evx_plan_enable_pass_timing(self._h, int(bool(on))),
+               "evx_plan_enable_pass_timing")
+
+    def read_pass_times(self):
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_longlong * 4)()
+        _check(_LIB.evx_plan_read_pass_times(self._h, ms, cnt), "evx_plan_read_pass_times")
+        return list(ms), list(cnt)
+
+    def set_xcd_remap(self, on: bool):
+        _check(_LIB.evx_plan_set_xcd_remap(self._h, int(bool(on))), "evx_plan_set_xcd_remap")

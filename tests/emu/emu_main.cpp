@@ -1,0 +1,145 @@
+// Host emulator of the HIP pass kernels (test infrastructure).  It compiles the very same pass
+// bodies and pass schedule as the GPU library, runs each workgroup as one std::thread per lane
+// with a std::barrier at every workgroup barrier, and is built with AddressSanitizer (every
+// global and LDS buffer is an exactly sized heap allocation) or ThreadSanitizer (a missing
+// barrier shows up as a data race on the LDS buffer).  LDS is filled with NaN before every
+// workgroup, so a read of a slot nobody wrote poisons the result.
+//
+// usage: evx_emu nx ny nz bc scheme dx dt M kappa A nsteps remap in.f32 out.f32
+//   bc 0 periodic / 1 zero flux; scheme 0 spectral / 1 stencil7.  nsteps < 0 runs |nsteps| steps
+//   in two halves with an end + restore between them (the resume path).
+#include <barrier>
+#include <cstdio>
+#include <cstdlib>
+#include <limits>
+#include <thread>
+#include <vector>
+
+#include "evx_schedule.hpp"
+
+namespace evx_emu {
+thread_local std::barrier<>* block_barrier = nullptr;
+}
+
+using namespace evx;
+
+template <class Body>
+static void run_grid(int nblk, int threads, int lds_slots, Body body) {
+  std::vector<float2> lds(lds_slots);
+  for (int bid = 0; bid < nblk; ++bid) {
+    const float nan = std::numeric_limits<float>::quiet_NaN();
+    for (auto& v : lds) v = make_float2(nan, nan);
+    std::barrier<> bar(threads);
+    std::vector<std::thread> th;
+    th.reserve(threads);
+    for (int tid = 0; tid < threads; ++tid) {
+      th.emplace_back([&, tid] {
+        evx_emu::block_barrier = &bar;
+        body(tid, bid, nblk, lds.data());
+      });
+    }
+    for (auto& x : th) x.join();
+  }
+}
+
+struct EmuLauncher {
+  template <int N, int BC, int MODE>
+  void col_t(const ColArgs& a) {
+    using C = ColCfg<N>;
+    const int nblk = int((a.nseq + C::B - 1) / C::B);
+    run_grid(nblk, C::THREADS, C::LDS, [&](int tid, int bid, int nb, float2* lds) {
+      colpass_body<N, BC, MODE>(a, tid, bid, nb, lds);
+    });
+  }
+  template <int NH, int BC, int MODE>
+  void row_t(const RowArgs& a) {
+    using C = RowCfg<NH, BC>;
+    const int nblk = int((a.nrows + C::ROWS - 1) / C::ROWS);
+    run_grid(nblk, C::THREADS, C::LDS, [&](int tid, int bid, int, float2* lds) {
+      rowpass_body<NH, BC, MODE>(a, tid, bid, lds);
+    });
+  }
+  template <int N, int BC>
+  void col_m(int mode, const ColArgs& a) {
+    switch (mode) {
+      case COL_FWD: col_t<N, BC, COL_FWD>(a); break;
+      case COL_INV: col_t<N, BC, COL_INV>(a); break;
+      case COL_Z_INIT: col_t<N, BC, COL_Z_INIT>(a); break;
+      case COL_Z_UPDATE: col_t<N, BC, COL_Z_UPDATE>(a); break;
+      default: col_t<N, BC, COL_Z_INV_STATE>(a); break;
+    }
+  }
+  template <int NH, int BC>
+  void row_m(int mode, const RowArgs& a) {
+    switch (mode) {
+      case ROW_FUSED: row_t<NH, BC, ROW_FUSED>(a); break;
+      case ROW_FWD: row_t<NH, BC, ROW_FWD>(a); break;
+      default: row_t<NH, BC, ROW_INV>(a); break;
+    }
+  }
+  void col(int n, int bc, int mode, const ColArgs& a) {
+    switch (n) {
+#define EVX_CASE(N)                                   \
+  case N:                                             \
+    if (bc == BC_PERIODIC) col_m<N, BC_PERIODIC>(mode, a); \
+    else col_m<N, BC_ZERO_FLUX>(mode, a);             \
+    return;
+      EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+      default: std::fprintf(stderr, "unsupported column length %d\n", n); std::exit(3);
+    }
+  }
+  void row(int n, int bc, int mode, const RowArgs& a) {
+    switch (n) {
+#define EVX_CASE(N)                                   \
+  case N:                                             \
+    if (bc == BC_PERIODIC) row_m<N, BC_PERIODIC>(mode, a); \
+    else row_m<N, BC_ZERO_FLUX>(mode, a);             \
+    return;
+      EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+      default: std::fprintf(stderr, "unsupported row length %d\n", n); std::exit(3);
+    }
+  }
+};
+
+int main(int argc, char** argv) {
+  if (argc != 15) {
+    std::fprintf(stderr, "usage: %s nx ny nz bc scheme dx dt M kappa A nsteps remap in out\n",
+                 argv[0]);
+    return 2;
+  }
+  const int nx = std::atoi(argv[1]), ny = std::atoi(argv[2]), nz = std::atoi(argv[3]);
+  const int bc = std::atoi(argv[4]), scheme = std::atoi(argv[5]);
+  const double dx = std::atof(argv[6]), dt = std::atof(argv[7]), M = std::atof(argv[8]);
+  const double kappa = std::atof(argv[9]), A = std::atof(argv[10]);
+  const int nsteps = std::atoi(argv[11]), remap = std::atoi(argv[12]);
+  const Geom g = make_geom(nx, ny, nz, bc, scheme, dx);
+  const HostTables h = make_tables(g);
+  TablePtrs t{h.tw_x.data(), h.tw_y.data(), h.tw_z.data(), h.post_x.data(),
+              h.mk_y.empty() ? nullptr : h.mk_y.data(), h.mk_z.empty() ? nullptr : h.mk_z.data(),
+              h.k2_x.data(), h.k2_y.data(), h.k2_z.data()};
+  std::vector<float> c(g.V);
+  FILE* f = std::fopen(argv[13], "rb");
+  if (!f || std::fread(c.data(), sizeof(float), g.V, f) != size_t(g.V)) return 4;
+  std::fclose(f);
+  std::vector<float2> S(g.spec), W(g.spec);
+  const StepCoef co{float(A * dt), float(dt * M * kappa), float(dt * M)};
+  EmuLauncher l;
+  sched_begin(l, g, t, c.data(), S.data(), W.data(), remap);
+  if (nsteps >= 0) {
+    sched_advance(l, g, t, S.data(), W.data(), co, nsteps, remap);
+  } else {
+    const int n1 = (-nsteps) / 2, n2 = -nsteps - n1;
+    std::vector<float> tmp(g.V);
+    sched_advance(l, g, t, S.data(), W.data(), co, n1, remap);
+    sched_end(l, g, t, tmp.data(), W.data(), remap);
+    sched_restore(l, g, t, S.data(), W.data(), remap);
+    sched_advance(l, g, t, S.data(), W.data(), co, n2, remap);
+  }
+  sched_end(l, g, t, c.data(), W.data(), remap);
+  f = std::fopen(argv[14], "wb");
+  if (!f || std::fwrite(c.data(), sizeof(float), g.V, f) != size_t(g.V)) return 5;
+  std::fclose(f);
+  return 0;
+}

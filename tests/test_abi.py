@@ -1,0 +1,74 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol include/evx.h declares, and
+rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "evx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(evx_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2507_21748_amd import evx
+    return evx.load()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for required in ("evx_plan_create", "evx_plan_destroy", "evx_ch_step", "evx_ch_begin",
+                     "evx_ch_advance", "evx_ch_end", "evx_status_string", "evx_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert lib.evx_status_string(s)
+    assert lib.evx_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("nx,ny,nz,bc", [
+    (14, 16, 16, 0),     # nx/2 = 7 not a supported length
+    (33, 16, 16, 0),     # odd nx with periodic boundaries
+    (16, 7, 16, 0),      # 7 not 2/3/5-smooth
+    (16, 16, 2048, 1),   # beyond the largest length
+    (18, 16, 16, 1),     # 18 not in the list (zero flux uses nx itself)
+])
+def test_plan_rejects_unsupported_sizes(lib, nx, ny, nz, bc):
+    h = ctypes.c_void_p()
+    st = lib.evx_plan_create(ctypes.byref(h), nx, ny, nz, bc, 0, 1.0)
+    assert st == 2, lib.evx_last_error()
+    assert h.value is None
+
+
+@pytest.mark.parametrize("args", [
+    (16, 16, 16, 5, 0, 1.0),     # bad bc
+    (16, 16, 16, 0, 9, 1.0),     # bad scheme
+    (16, 16, 16, 0, 0, 0.0),     # dx <= 0
+    (0, 16, 16, 0, 0, 1.0),      # empty grid
+    (16, -4, 16, 0, 0, 1.0),
+])
+def test_plan_rejects_bad_arguments(lib, args):
+    h = ctypes.c_void_p()
+    assert lib.evx_plan_create(ctypes.byref(h), *args) == 1
+    assert lib.evx_last_error()
+
+
+def test_null_arguments(lib):
+    assert lib.evx_plan_create(None, 16, 16, 16, 0, 0, 1.0) == 1
+    assert lib.evx_plan_destroy(None) == 1
+    assert lib.evx_ch_step(None, None, 1, None, None) == 1
+    assert lib.evx_ch_advance(None, 1, None, None) == 1
