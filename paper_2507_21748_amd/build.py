@@ -21,6 +21,9 @@ LIB = os.path.join(PKG, "libevx.so")
 ARCH = "gfx950"
 HIPFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # no FP contraction: every kernel that transforms the same data rounds identically, which
+    # makes resume from a stored state and checkpoint recomputation bit-exact
+    "-ffp-contract=off",
     # packed FP32 instructions stay off: the compiler must not emit v_pk_{add,mul,fma}_f32
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", CSRC,

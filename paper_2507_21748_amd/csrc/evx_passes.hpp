@@ -191,12 +191,9 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
 
   if constexpr (MODE == COL_Z_UPDATE) {
     // C' = G (P C - dt M K2 F), P = 1 + A dt K2, G = 1 / (1 + dt M kappa K2^2 + A dt K2).
-    // The rounded C' that is stored in the state must be the value the inverse transform
-    // consumes (resume from a stored state is then bit-exact), so the final product may not be
-    // contracted into a later add.
-#if defined(__clang__)
-#pragma clang fp contract(off)
-#endif
+    // The library is built without FP contraction, so the rounded C' stored in the state is
+    // exactly the value the inverse transform consumes, and every kernel that transforms the
+    // same data rounds identically (resume from a stored state is bit-exact).
     if (live) {
       const float ko = a.k2o[outer];
       float kca, kcb;
@@ -208,9 +205,6 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
         kcb = kca;
       }
       static_for<E>([&](auto e) {
-#if defined(__clang__)
-#pragma clang fp contract(off)
-#endif
         const int k = t + TPS * decltype(e)::value;
         const long long idx = base + (long long)k * a.row_stride;
         const float kr = a.k2r[k];
