@@ -24,6 +24,50 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PASS_NAMES = ["y_inverse", "x_fused_fprime", "y_forward", "z_fused_update"]
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; counter-based traffic figures are used only while it matches."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2507_21748_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hpp", ".hip")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (scaled by the copy-kernel calibration), or None if absent or stale."""
+    path = os.path.join(PROFILES, f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def copy_probe(torch, gib: float, reps: int = 3):
+    """A plain device-to-device copy of a known size (torch's copy kernel), for calibrating the
+    FETCH_SIZE / WRITE_SIZE counters and as a measured bandwidth ceiling."""
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    secs = (time.perf_counter() - t0) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_each_way": n * 4, "gbs": 2 * n * 4 / secs / 1e9}
 
 
 def pass_bytes(shape, bc):
@@ -106,6 +150,8 @@ def main():
     ap.add_argument("--workload", default="ch1024_periodic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=2.0,
+                    help="size of the calibration copy run before the workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the spectral stepper here runs on a single device "
@@ -119,12 +165,14 @@ def main():
     evx.load()
     torch.cuda.set_device(0)
     w = WORKLOADS[args.workload]
+    probe = copy_probe(torch, args.copy_probe_gib) if args.copy_probe_gib > 0 else None
     res = run_workload(evx, torch, w, args.steps, args.warmup)
     passes = res["passes"]
     dom = max(passes, key=lambda k: passes[k]["avg_ms"] * passes[k]["launches"])
     d = passes[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": d["gbs"] / HBM_PEAK_GBS,
+                "traffic": measured_traffic(w.name, dom),
                 "bytes_per_launch": d["algorithmic_bytes"]}
     step_bytes = sum(pass_bytes(w.shape, w.bc))
     line = {
@@ -146,6 +194,8 @@ def main():
         "roofline": roofline,
         "step_effective_gbs": step_bytes * res["voxel_steps_per_s"] / w.voxels / 1e9,
         "passes": passes,
+        "copy_probe": probe,
+        "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_extra:
         extra = {}

@@ -238,6 +238,32 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
 }
 
 // ------------------------------------------------------------------ row pass
+// Cooperative copies between the block's contiguous slice of global memory and LDS.  Every load
+// of a thread is issued before its first LDS write, so a wave waits on memory once per copy
+// rather than once per element.  `valid` is the number of in-range float2 (ragged last block).
+template <int COUNT, int T>
+EVX_DEV void copy_in(const float2* EVX_RESTRICT src, long long valid, float2* lds, int tid) {
+  constexpr int IT = (COUNT + T - 1) / T;
+  float2 r[IT];
+  static_for<IT>([&](auto I) {
+    const int i = tid + T * decltype(I)::value;
+    r[I] = (i < COUNT && i < valid) ? src[i] : make_float2(0.f, 0.f);
+  });
+  static_for<IT>([&](auto I) {
+    const int i = tid + T * decltype(I)::value;
+    if (i < COUNT) lds[i] = r[I];
+  });
+}
+
+template <int COUNT, int T>
+EVX_DEV void copy_out(float2* EVX_RESTRICT dst, long long valid, const float2* lds, int tid) {
+  constexpr int IT = (COUNT + T - 1) / T;
+  static_for<IT>([&](auto I) {
+    const int i = tid + T * decltype(I)::value;
+    if (i < COUNT && i < valid) dst[i] = lds[i];
+  });
+}
+
 // Periodic: template length NH = nx/2, the complex FFT length of the packed real row; the row
 // has NH+1 complex points.  Zero flux: NH = nx, one sequence carries two rows packed as a + i b.
 template <int NH, int BC>
@@ -265,20 +291,13 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     // ---------------------------------------------------------------- input
     if constexpr (MODE == ROW_FWD) {
       // real rows, read as pairs (c[2n], c[2n+1]) into stage[b*NH + n]
-      const float2* src = reinterpret_cast<const float2*>(a.in_r);
-      for (int i = tid; i < B * NH; i += T) {
-        const int rr = i / NH;
-        x[0] = (r0 + rr < a.nrows) ? src[r0 * NH + i] : make_float2(0.f, 0.f);
-        lds[i] = x[0];
-      }
+      copy_in<B * NH, T>(reinterpret_cast<const float2*>(a.in_r) + r0 * NH, (a.nrows - r0) * NH,
+                         lds, tid);
       evx_sync();
       static_for<E>([&](auto e) { x[e] = lds[b * NH + t + TPS * decltype(e)::value]; });
       evx_sync();
     } else {
-      for (int i = tid; i < B * W; i += T) {
-        const int rr = i / W;
-        lds[i] = (r0 + rr < a.nrows) ? a.in_c[r0 * W + i] : make_float2(0.f, 0.f);
-      }
+      copy_in<B * W, T>(a.in_c + r0 * W, (a.nrows - r0) * W, lds, tid);
       evx_sync();
       // C2R pre-processing: Z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) e^{+2pi i k/NX}
       static_for<E>([&](auto e) {
@@ -295,11 +314,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       if constexpr (MODE == ROW_INV) {
         static_for<E>([&](auto e) { lds[b * NH + t + TPS * decltype(e)::value] = x[e]; });
         evx_sync();
-        float2* dst = reinterpret_cast<float2*>(a.out_r);
-        for (int i = tid; i < B * NH; i += T) {
-          const int rr = i / NH;
-          if (r0 + rr < a.nrows) dst[r0 * NH + i] = lds[i];
-        }
+        copy_out<B * NH, T>(reinterpret_cast<float2*>(a.out_r) + r0 * NH, (a.nrows - r0) * NH,
+                            lds, tid);
         return;
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
@@ -324,23 +340,17 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     static_for<E>([&](auto e) { lds[b * W + t + TPS * decltype(e)::value] = y[e]; });
     if (t == 0) lds[b * W + NH] = ynyq;
     evx_sync();
-    for (int i = tid; i < B * W; i += T) {
-      const int rr = i / W;
-      if (r0 + rr < a.nrows) a.out_c[r0 * W + i] = lds[i];
-    }
+    copy_out<B * W, T>(a.out_c + r0 * W, (a.nrows - r0) * W, lds, tid);
     (void)NX;
   } else {
     // zero flux: rows ra = r0 + 2b, rb = ra + 1, stage as floats [2B][NH]
     constexpr int NX = NH;
     float* st = reinterpret_cast<float*>(lds);
     const float* in = (MODE == ROW_FWD) ? a.in_r : reinterpret_cast<const float*>(a.in_c);
-    if constexpr (MODE == ROW_FWD || MODE == ROW_FUSED || MODE == ROW_INV) {
-      for (int i = tid; i < 2 * B * NX; i += T) {
-        const int rr = i / NX;
-        st[i] = (r0 + rr < a.nrows) ? in[r0 * NX + i] : 0.f;
-      }
-      evx_sync();
-    }
+    // rows are NX floats (NX even) = NX/2 float2; r0 is even
+    copy_in<B * NX, T>(reinterpret_cast<const float2*>(in) + r0 * (NX / 2),
+                       (a.nrows - r0) * (NX / 2), lds, tid);
+    evx_sync();
     if constexpr (MODE == ROW_FWD) {
       static_for<E>([&](auto e) {
         const int n = t + TPS * decltype(e)::value;
@@ -370,10 +380,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
           st[(2 * b + 1) * NX + s] = x[e].y;
         });
         evx_sync();
-        for (int i = tid; i < 2 * B * NX; i += T) {
-          const int rr = i / NX;
-          if (r0 + rr < a.nrows) a.out_r[r0 * NX + i] = st[i];
-        }
+        copy_out<B * NX, T>(reinterpret_cast<float2*>(a.out_r) + r0 * (NX / 2),
+                            (a.nrows - r0) * (NX / 2), lds, tid);
         return;
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
@@ -398,11 +406,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       st[(2 * b + 1) * NX + k] = y[e].y;
     });
     evx_sync();
-    float* out = reinterpret_cast<float*>(a.out_c);
-    for (int i = tid; i < 2 * B * NX; i += T) {
-      const int rr = i / NX;
-      if (r0 + rr < a.nrows) out[r0 * NX + i] = st[i];
-    }
+    copy_out<B * NX, T>(a.out_c + r0 * (NX / 2), (a.nrows - r0) * (NX / 2), lds, tid);
   }
 }
 
