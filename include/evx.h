@@ -78,7 +78,9 @@ evx_status evx_plan_destroy(evx_plan* plan);
 
 /* Device bytes the caller must provide for the given EVX_OP_* mask.  EVX_OP_STEP needs two
  * spectral buffers (state S and work W) of nz*ny*(nx/2+1) complex64 (periodic) or nz*ny*nx float
- * (zero flux) each, i.e. about 8 bytes per voxel. */
+ * (zero flux) each, i.e. about 8 bytes per voxel; EVX_OP_DIAG adds one spectral buffer and 16 KB
+ * of partial sums; EVX_OP_ADJOINT adds three spectral buffers, one real field and the partial
+ * sums (about 24 bytes per voxel in total). */
 evx_status evx_plan_workspace_bytes(const evx_plan* plan, int ops, size_t* bytes);
 
 /* Hand the plan a device buffer of at least evx_plan_workspace_bytes(plan, ops) bytes,
@@ -108,6 +110,27 @@ evx_status evx_ch_restore(evx_plan* plan, void* hip_stream);
 /* In place: c <- nsteps steps of c (begin + advance + end). */
 evx_status evx_ch_step(evx_plan* plan, float* c, int nsteps, const evx_ch_params* params,
                        void* hip_stream);
+
+/* Adjoint of one step (gradients for inverse problems; the paper's Statement of Need names
+ * backpropagation through the solver for parameter estimation).  With
+ * c^{n+1} = A c^n - B f'(c^n), A = T^{-1} diag(G P) T, B = T^{-1} diag(dt M K2 G) T:
+ *   lam^n = A lam^{n+1} - f''(c^n) (B lam^{n+1}),
+ *   *dkappa += <lam^{n+1}, dc^{n+1}/dkappa>,  *dM += <lam^{n+1}, dc^{n+1}/dM>.
+ * c_n: device, V floats, the state the step started from (read).  lam: device, V floats,
+ * dL/dc^{n+1} on entry and dL/dc^n on return.  dkappa, dM: device doubles, accumulated (the
+ * caller zeroes them once per backward sweep).  Needs a workspace sized with EVX_OP_ADJOINT
+ * (EVX_ERR_NOMEM otherwise).  Results are bit-reproducible (fixed-order FP64 reductions). */
+evx_status evx_ch_adjoint_step(evx_plan* plan, const float* c_n, float* lam,
+                               const evx_ch_params* params, double* dkappa, double* dM,
+                               void* hip_stream);
+
+/* Mass and discrete free energy of a real field (paper: the interfacial free energy functional
+ * of the Appendix, here with the double well f):  out[0] = dx^3 sum c,
+ * out[1] = dx^3 [sum f(c) + (kappa/2) sum c (-L c)], L the plan's discrete Laplacian.
+ * c: device, V floats (read).  out: two device doubles (written).  Only params->kappa is used.
+ * Needs a workspace sized with EVX_OP_DIAG or EVX_OP_ADJOINT. */
+evx_status evx_ch_diagnostics(evx_plan* plan, const float* c, const evx_ch_params* params,
+                              double* out, void* hip_stream);
 
 /* Kernel timing for measurement: when enabled, advance records a HIP event pair around every
  * pass launch on the launch stream.  read synchronises those events and returns, per pass kind

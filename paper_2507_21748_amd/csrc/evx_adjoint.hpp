@@ -1,0 +1,103 @@
+// Pass schedules of the adjoint step and of the diagnostics (shared by the HIP launcher and the
+// host emulator).  A launcher L additionally provides spec(SpecArgs), realsum(RealSumArgs),
+// final(FinalArgs) and combine(CombineArgs).
+//
+// Adjoint of one step c^{n+1} = A c^n - B f'(c^n), A = T^{-1} diag(G P) T,
+// B = T^{-1} diag(dt M K2 G) T (both symmetric):
+//   lam^n = A lam^{n+1} - f''(c^n) (B lam^{n+1}),
+//   dL/dkappa += <lam^{n+1}, T^{-1}[-dt M K2^2 G C^{n+1}]>,
+//   dL/dM     += <lam^{n+1}, T^{-1}[-dt kappa K2^2 G C^{n+1} - dt K2 G F^n]>,
+// with C^{n+1} = G (P T[c^n] - dt M K2 T[f'(c^n)]) recomputed from c^n.
+#pragma once
+
+#include "evx_aux.hpp"
+#include "evx_schedule.hpp"
+
+namespace evx {
+
+// Full forward transform of a real field into a spectral buffer (optionally of f'(field)).
+template <class L>
+void sched_forward(L& l, const Geom& g, const TablePtrs& t, const float* c, float2* out,
+                   bool fprime_first, int remap) {
+  l.row(g.row_len, g.bc, fprime_first ? ROW_FWD_FP : ROW_FWD,
+        x_args(g, t, nullptr, c, out, nullptr));
+  l.col(g.ny, g.bc, COL_FWD, y_args(g, t, out, out, remap));
+  l.col(g.nz, g.bc, COL_FWD, z_args(g, t, out, out, nullptr, StepCoef{0, 0, 0}, remap));
+}
+
+// Full inverse transform of a spectral buffer (consumed) into a real field.
+template <class L>
+void sched_inverse(L& l, const Geom& g, const TablePtrs& t, float2* in, float* c, int remap) {
+  l.col(g.nz, g.bc, COL_INV, z_args(g, t, in, in, nullptr, StepCoef{0, 0, 0}, remap));
+  l.col(g.ny, g.bc, COL_INV, y_args(g, t, in, in, remap));
+  l.row(g.row_len, g.bc, ROW_INV, x_args(g, t, in, nullptr, nullptr, c));
+}
+
+struct AdjointBufs {
+  float2 *A, *B, *Lm;  // spectral scratch
+  float* v;            // real scratch
+  double* partial;     // 2 * AUX_BLOCKS
+};
+
+struct AdjointCoef {
+  StepCoef step;
+  float dt, dt_kappa;
+};
+
+inline SpecArgs spec_args(const Geom& g, const TablePtrs& t, const AdjointBufs& b,
+                          const AdjointCoef& c, int mode) {
+  SpecArgs a{};
+  a.C = b.A;
+  a.F = b.B;
+  a.L = b.Lm;
+  a.n = g.spec;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.ncols = g.ncols;
+  a.bc = g.bc;
+  a.k2x = t.k2_x;
+  a.k2y = t.k2_y;
+  a.k2z = t.k2_z;
+  a.a_dt = c.step.a_dt;
+  a.dt_m_kappa = c.step.dt_m_kappa;
+  a.dt_m = c.step.dt_m;
+  a.dt = c.dt;
+  a.dt_kappa = c.dt_kappa;
+  a.partial = b.partial;
+  a.mode = mode;
+  return a;
+}
+
+// lam (in: dL/dc^{n+1}, out: dL/dc^n); dk, dM accumulate (device doubles).
+template <class L>
+void sched_adjoint(L& l, const Geom& g, const TablePtrs& t, const float* c, float* lam,
+                   const AdjointBufs& b, const AdjointCoef& co, double* dk, double* dM,
+                   int remap) {
+  sched_forward(l, g, t, c, b.A, false, remap);
+  sched_forward(l, g, t, c, b.B, true, remap);
+  sched_forward(l, g, t, lam, b.Lm, false, remap);
+  l.spec(spec_args(g, t, b, co, 0));
+  const double norm = (g.bc == BC_PERIODIC) ? 1.0 / double(g.V) : 1.0;
+  l.final(FinalArgs{b.partial, AUX_BLOCKS, dk, dM, norm, norm, 1, 1});
+  sched_inverse(l, g, t, b.Lm, lam, remap);
+  sched_inverse(l, g, t, b.B, b.v, remap);
+  l.combine(CombineArgs{lam, c, b.v, g.V});
+}
+
+// out[0] = mass dx^3 sum c, out[1] = energy dx^3 [sum f(c) + (kappa/2) sum c (-L c)].
+template <class L>
+void sched_diagnostics(L& l, const Geom& g, const TablePtrs& t, const float* c, double kappa,
+                       const AdjointBufs& b, double* out, int remap) {
+  sched_forward(l, g, t, c, b.A, false, remap);
+  AdjointCoef co{};
+  l.spec(spec_args(g, t, b, co, 1));
+  const double norm = (g.bc == BC_PERIODIC) ? 1.0 / double(g.V) : 1.0;
+  const double dx3 = g.dx * g.dx * g.dx;
+  // out[1] <- dx^3 (kappa/2) sum w K2 |C|^2, then the real-space sums add f(c) and set the mass
+  l.final(FinalArgs{b.partial, AUX_BLOCKS, out + 1, nullptr, dx3 * 0.5 * kappa * norm, 0.0, 0, 0});
+  l.realsum(RealSumArgs{c, g.V, b.partial});
+  l.final(FinalArgs{b.partial, AUX_BLOCKS, out + 1, out, dx3, dx3, 1, 0});
+}
+
+}  // namespace evx

@@ -39,6 +39,9 @@ struct evx_plan {
   size_t ws_bytes = 0;
   float2* S = nullptr;
   float2* W = nullptr;
+  AdjointBufs aux{};      // diagnostics / adjoint scratch (inside the workspace)
+  bool has_diag = false;
+  bool has_adj = false;
   bool begun = false;     // S holds a state
   bool w_valid = false;   // W holds F_z^{-1} S
   int remap = 1;
@@ -54,6 +57,13 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t spec_bytes(const Geom& g) { return align256(size_t(g.spec) * sizeof(float2)); }
+size_t partial_bytes() { return align256(2 * AUX_BLOCKS * sizeof(double)); }
+size_t real_bytes(const Geom& g) { return align256(size_t(g.V) * sizeof(float)); }
+
+// Workspace layout: S, W | A, partial (diagnostics) | B, L, v (adjoint).
+size_t ws_step(const Geom& g) { return 2 * spec_bytes(g); }
+size_t ws_diag(const Geom& g) { return ws_step(g) + spec_bytes(g) + partial_bytes(); }
+size_t ws_adj(const Geom& g) { return ws_diag(g) + 2 * spec_bytes(g) + real_bytes(g); }
 
 evx_status check_plan(const evx_plan* p) {
   if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
@@ -230,8 +240,10 @@ evx_status evx_plan_destroy(evx_plan* p) {
 
 evx_status evx_plan_workspace_bytes(const evx_plan* p, int ops, size_t* bytes) {
   if (!p || !bytes) return fail(EVX_ERR_ARG, "NULL argument");
-  if (ops & ~(EVX_OP_STEP)) return fail(EVX_ERR_UNSUPPORTED, "workspace ops 0x%x", ops);
-  *bytes = 2 * spec_bytes(p->g);
+  if (ops & ~(EVX_OP_STEP | EVX_OP_DIAG | EVX_OP_ADJOINT))
+    return fail(EVX_ERR_ARG, "unknown workspace ops 0x%x", ops);
+  *bytes = (ops & EVX_OP_ADJOINT) ? ws_adj(p->g) : (ops & EVX_OP_DIAG) ? ws_diag(p->g)
+                                                                       : ws_step(p->g);
   return EVX_OK;
 }
 
@@ -243,8 +255,23 @@ evx_status evx_plan_set_workspace(evx_plan* p, void* dev, size_t bytes) {
     return fail(EVX_ERR_NOMEM, "workspace of %zu bytes, need %zu", bytes, 2 * spec_bytes(p->g));
   p->ws = static_cast<float2*>(dev);
   p->ws_bytes = bytes;
-  p->S = p->ws;
-  p->W = reinterpret_cast<float2*>(reinterpret_cast<unsigned char*>(p->ws) + spec_bytes(p->g));
+  unsigned char* base = static_cast<unsigned char*>(dev);
+  const size_t sb = spec_bytes(p->g);
+  p->S = reinterpret_cast<float2*>(base);
+  p->W = reinterpret_cast<float2*>(base + sb);
+  p->has_diag = bytes >= ws_diag(p->g);
+  p->has_adj = bytes >= ws_adj(p->g);
+  p->aux = AdjointBufs{};
+  if (p->has_diag) {
+    p->aux.A = reinterpret_cast<float2*>(base + 2 * sb);
+    p->aux.partial = reinterpret_cast<double*>(base + 3 * sb);
+  }
+  if (p->has_adj) {
+    unsigned char* q = base + 3 * sb + partial_bytes();
+    p->aux.B = reinterpret_cast<float2*>(q);
+    p->aux.Lm = reinterpret_cast<float2*>(q + sb);
+    p->aux.v = reinterpret_cast<float*>(q + 2 * sb);
+  }
   p->begun = false;
   p->w_valid = false;
   return EVX_OK;
@@ -319,6 +346,33 @@ evx_status evx_ch_step(evx_plan* p, float* c, int nsteps, const evx_ch_params* q
   if ((st = evx_ch_begin(p, c, s)) != EVX_OK) return st;
   if ((st = evx_ch_advance(p, nsteps, q, s)) != EVX_OK) return st;
   return evx_ch_end(p, c, s);
+}
+
+evx_status evx_ch_adjoint_step(evx_plan* p, const float* c_n, float* lam,
+                               const evx_ch_params* q, double* dkappa, double* dM, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if ((st = check_params(q)) != EVX_OK) return st;
+  if (!c_n || !lam || !dkappa || !dM) return fail(EVX_ERR_ARG, "NULL argument");
+  if (!p->has_adj)
+    return fail(EVX_ERR_NOMEM, "workspace too small for the adjoint (EVX_OP_ADJOINT)");
+  AdjointCoef co{coef_of(q), float(q->dt), float(q->dt * q->kappa)};
+  TimedLauncher l = launcher(p, s);
+  sched_adjoint(l, p->g, p->t, c_n, lam, p->aux, co, dkappa, dM, p->remap);
+  return finish(l, "adjoint step");
+}
+
+evx_status evx_ch_diagnostics(evx_plan* p, const float* c, const evx_ch_params* q, double* out,
+                              void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!q) return fail(EVX_ERR_ARG, "params is NULL");
+  if (!c || !out) return fail(EVX_ERR_ARG, "NULL argument");
+  if (!p->has_diag)
+    return fail(EVX_ERR_NOMEM, "workspace too small for diagnostics (EVX_OP_DIAG)");
+  TimedLauncher l = launcher(p, s);
+  sched_diagnostics(l, p->g, p->t, c, q->kappa, p->aux, out, p->remap);
+  return finish(l, "diagnostics");
 }
 
 evx_status evx_plan_enable_pass_timing(evx_plan* p, int on) {

@@ -1,0 +1,45 @@
+// __global__ wrappers of the element-wise / reduction passes (adjoint step, diagnostics).
+#include "evx_launch.hpp"
+
+namespace evx {
+
+__global__ __launch_bounds__(AUX_THREADS) void spec_kernel(SpecArgs a) {
+  __shared__ double red[2 * AUX_THREADS];
+  spec_body(a, threadIdx.x, blockIdx.x, gridDim.x, red);
+}
+
+__global__ __launch_bounds__(AUX_THREADS) void realsum_kernel(RealSumArgs a) {
+  __shared__ double red[2 * AUX_THREADS];
+  realsum_body(a, threadIdx.x, blockIdx.x, gridDim.x, red);
+}
+
+__global__ __launch_bounds__(AUX_THREADS) void final_kernel(FinalArgs a) {
+  __shared__ double red[2 * AUX_THREADS];
+  final_body(a, threadIdx.x, red);
+}
+
+__global__ __launch_bounds__(AUX_THREADS) void combine_kernel(CombineArgs a) {
+  combine_body(a, threadIdx.x, blockIdx.x, gridDim.x);
+}
+
+hipError_t evx_launch_spec(const SpecArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(spec_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t evx_launch_realsum(const RealSumArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(realsum_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t evx_launch_final(const FinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(final_kernel, dim3(1), dim3(AUX_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t evx_launch_combine(const CombineArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(combine_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace evx

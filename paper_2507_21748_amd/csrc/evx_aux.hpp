@@ -1,0 +1,184 @@
+// Element-wise and reduction passes used by the adjoint step and by the diagnostics.  Like the
+// transform passes, each body is the work of one workgroup (gfx950 kernel or host emulator).
+//
+// Inner products of real fields are evaluated in the spectral domain (Parseval):
+//   periodic, half spectrum:  sum_x a b = (1/V) sum_k w(kx) Re(A_k conj B_k),
+//                             w = 1 for kx = 0 and kx = nx/2, else 2;
+//   zero flux, DCT-II D_k = 2 sum_n x_n cos(pi k (2n+1) / 2N) per axis:
+//                             sum_x a b = sum_k prod_axes w(k) A_k B_k,
+//                             w(0) = 1/(4N), w(k > 0) = 1/(2N).
+// Partial sums are FP64 and reduced in a fixed order, so results are bit-reproducible.
+#pragma once
+
+#include "evx_passes.hpp"
+
+namespace evx {
+
+constexpr int AUX_THREADS = 256;
+// Fixed grid (fixed summation order).  The loops are grid-stride, so a test build may shrink it.
+#ifndef EVX_AUX_BLOCKS
+#define EVX_AUX_BLOCKS 1024
+#endif
+constexpr int AUX_BLOCKS = EVX_AUX_BLOCKS;
+
+struct SpecArgs {
+  const float2* C;  // T[c^n]
+  float2* F;        // in: T[f'(c^n)];  out: dt M K2 G Lam   (the B operator's multiplier)
+  float2* L;        // in: T[lam^{n+1}]; out: G P Lam        (the A operator's multiplier)
+  long long n;      // float2 elements of a spectral buffer
+  int nx, ny, nz, ncols, bc;
+  const float *k2x, *k2y, *k2z;
+  float a_dt, dt_m_kappa, dt_m, dt, dt_kappa;
+  double* partial;  // 2 per block: sum for dL/dkappa, sum for dL/dM (before the 1/V factor)
+  int mode;         // 0 adjoint, 1 energy (sum w K2 |C|^2 into partial[2b])
+};
+
+// Per-axis Parseval weight of the zero-flux (DCT-II) coefficient k on an axis of n cells.
+EVX_DEV double dct_weight(int k, int n) { return (k == 0 ? 0.25 : 0.5) / double(n); }
+
+template <int T>
+EVX_DEV void block_sum2(double& s0, double& s1, int tid, double* red) {
+  red[2 * tid] = s0;
+  red[2 * tid + 1] = s1;
+  evx_sync();
+  for (int h = T / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      red[2 * tid] += red[2 * (tid + h)];
+      red[2 * tid + 1] += red[2 * (tid + h) + 1];
+    }
+    evx_sync();
+  }
+  s0 = red[0];
+  s1 = red[1];
+}
+
+// adjoint (mode 0): with C1 = G (P C - dt M K2 F),
+//   dkappa += w Re(conj Lam (-dt M K2^2 G C1)),  dM += w Re(conj Lam (-dt kappa K2^2 G C1
+//   - dt K2 G F)),  L <- G P Lam,  F <- dt M K2 G Lam.
+// energy (mode 1): partial[2b] += w K2 |C|^2.
+EVX_DEV void spec_body(const SpecArgs& a, int tid, int bid, int nblk, double* red) {
+  double s0 = 0.0, s1 = 0.0;
+  const long long stride = (long long)nblk * AUX_THREADS;
+  for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
+    const long long r = i / a.ncols;
+    const int xc = int(i - r * a.ncols);
+    const int y = int(r % a.ny);
+    const int z = int(r / a.ny);
+    const float kyz = a.k2y[y] + a.k2z[z];
+    const float2 Cv = a.C[i];
+    float2 Fv = make_float2(0.f, 0.f), Lv = make_float2(0.f, 0.f);
+    if (a.mode == 0) {
+      Fv = a.F[i];
+      Lv = a.L[i];
+    }
+    float K2[2];
+    double w[2];
+    if (a.bc == BC_PERIODIC) {
+      K2[0] = K2[1] = a.k2x[xc] + kyz;
+      const double wx = (xc == 0 || 2 * xc == a.nx) ? 1.0 : 2.0;
+      w[0] = w[1] = wx;
+    } else {
+      K2[0] = a.k2x[2 * xc] + kyz;
+      K2[1] = a.k2x[2 * xc + 1] + kyz;
+      const double wyz = dct_weight(y, a.ny) * dct_weight(z, a.nz);
+      w[0] = dct_weight(2 * xc, a.nx) * wyz;
+      w[1] = dct_weight(2 * xc + 1, a.nx) * wyz;
+    }
+    if (a.mode == 1) {
+      if (a.bc == BC_PERIODIC) {
+        s0 += w[0] * double(K2[0]) * (double(Cv.x) * Cv.x + double(Cv.y) * Cv.y);
+      } else {
+        s0 += w[0] * double(K2[0]) * double(Cv.x) * Cv.x + w[1] * double(K2[1]) * double(Cv.y) * Cv.y;
+      }
+      continue;
+    }
+    const float cv[2] = {Cv.x, Cv.y}, fv[2] = {Fv.x, Fv.y}, lv[2] = {Lv.x, Lv.y};
+    float uo[2], vo[2];
+    for (int j = 0; j < 2; ++j) {
+      const float k2 = K2[j], k4 = k2 * k2;
+      const float P = 1.0f + a.a_dt * k2;
+      const float G = evx_rcp(1.0f + a.dt_m_kappa * k4 + a.a_dt * k2);
+      const float c1 = G * (P * cv[j] - a.dt_m * k2 * fv[j]);
+      // periodic: Re(conj(L) X) = L.x X.x + L.y X.y, summed over both components with the
+      // same weight; zero flux: two independent real coefficients
+      s0 += w[j] * double(-a.dt_m * k4 * G) * double(lv[j]) * double(c1);
+      s1 += w[j] * (double(-a.dt_kappa * k4 * G) * double(lv[j]) * double(c1)
+                    + double(-a.dt * k2 * G) * double(lv[j]) * double(fv[j]));
+      uo[j] = G * P * lv[j];
+      vo[j] = a.dt_m * k2 * G * lv[j];
+    }
+    a.L[i] = make_float2(uo[0], uo[1]);
+    a.F[i] = make_float2(vo[0], vo[1]);
+  }
+  block_sum2<AUX_THREADS>(s0, s1, tid, red);
+  if (tid == 0) {
+    a.partial[2 * bid] = s0;
+    a.partial[2 * bid + 1] = s1;
+  }
+}
+
+// Real-space sums for the diagnostics: partial[2b] = sum f(c), partial[2b+1] = sum c.
+struct RealSumArgs {
+  const float* c;
+  long long n;
+  double* partial;
+};
+
+EVX_DEV void realsum_body(const RealSumArgs& a, int tid, int bid, int nblk, double* red) {
+  double s0 = 0.0, s1 = 0.0;
+  const long long stride = (long long)nblk * AUX_THREADS;
+  for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
+    const double c = a.c[i];
+    const double q = c * c - 1.0;
+    s0 += 0.25 * q * q;
+    s1 += c;
+  }
+  block_sum2<AUX_THREADS>(s0, s1, tid, red);
+  if (tid == 0) {
+    a.partial[2 * bid] = s0;
+    a.partial[2 * bid + 1] = s1;
+  }
+}
+
+// Single block: out_j <- (add_j ? out_j : 0) + scale_j * sum_b partial[2b + j] (j = 0, 1),
+// summed in a fixed order.  add_j = 1 accumulates (gradients), 0 overwrites.  Null outputs are
+// skipped.
+struct FinalArgs {
+  const double* partial;
+  int nparts;
+  double* out0;
+  double* out1;
+  double scale0, scale1;
+  int add0, add1;
+};
+
+EVX_DEV void final_body(const FinalArgs& a, int tid, double* red) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int b = tid; b < a.nparts; b += AUX_THREADS) {
+    s0 += a.partial[2 * b];
+    s1 += a.partial[2 * b + 1];
+  }
+  block_sum2<AUX_THREADS>(s0, s1, tid, red);
+  if (tid == 0) {
+    if (a.out0) *a.out0 = (a.add0 ? *a.out0 : 0.0) + a.scale0 * s0;
+    if (a.out1) *a.out1 = (a.add1 ? *a.out1 : 0.0) + a.scale1 * s1;
+  }
+}
+
+// lam <- lam - f''(c) v  (f'' = 3c^2 - 1)
+struct CombineArgs {
+  float* lam;
+  const float* c;
+  const float* v;
+  long long n;
+};
+
+EVX_DEV void combine_body(const CombineArgs& a, int tid, int bid, int nblk) {
+  const long long stride = (long long)nblk * AUX_THREADS;
+  for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
+    const float c = a.c[i];
+    a.lam[i] = a.lam[i] - (3.0f * c * c - 1.0f) * a.v[i];
+  }
+}
+
+}  // namespace evx

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "evx_adjoint.hpp"
 #include "evx_schedule.hpp"
 
 namespace evx {
@@ -12,6 +13,11 @@ namespace evx {
   hipError_t evx_launch_row_##N(int bc, int mode, const RowArgs& a, hipStream_t s);
 EVX_FOR_EACH_N(EVX_DECL)
 #undef EVX_DECL
+
+hipError_t evx_launch_spec(const SpecArgs& a, hipStream_t s);
+hipError_t evx_launch_realsum(const RealSumArgs& a, hipStream_t s);
+hipError_t evx_launch_final(const FinalArgs& a, hipStream_t s);
+hipError_t evx_launch_combine(const CombineArgs& a, hipStream_t s);
 
 // Records the first launch error; the schedule keeps enqueuing nothing after one.
 struct HipLauncher {
@@ -28,6 +34,18 @@ struct HipLauncher {
 #undef EVX_CASE
       default: bad_len = true;
     }
+  }
+  void spec(const SpecArgs& a) {
+    if (err == hipSuccess && !bad_len) err = evx_launch_spec(a, stream);
+  }
+  void realsum(const RealSumArgs& a) {
+    if (err == hipSuccess && !bad_len) err = evx_launch_realsum(a, stream);
+  }
+  void final(const FinalArgs& a) {
+    if (err == hipSuccess && !bad_len) err = evx_launch_final(a, stream);
+  }
+  void combine(const CombineArgs& a) {
+    if (err == hipSuccess && !bad_len) err = evx_launch_combine(a, stream);
   }
   void row(int n, int bc, int mode, const RowArgs& a) {
     if (err != hipSuccess || bad_len) return;

@@ -30,7 +30,8 @@ enum : int {
 enum : int {
   ROW_FUSED = 0,  // complex row -> inverse x -> f' -> forward x -> complex row
   ROW_FWD = 1,    // real row -> forward x -> complex row
-  ROW_INV = 2     // complex row -> inverse x -> real row
+  ROW_INV = 2,    // complex row -> inverse x -> real row
+  ROW_FWD_FP = 3  // real row -> f'(c) -> forward x -> complex row (adjoint: T[f'(c)])
 };
 
 struct ColArgs {
@@ -289,12 +290,14 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
   if constexpr (BC == BC_PERIODIC) {
     constexpr int NX = 2 * NH, W = NH + 1;
     // ---------------------------------------------------------------- input
-    if constexpr (MODE == ROW_FWD) {
+    if constexpr (MODE == ROW_FWD || MODE == ROW_FWD_FP) {
       // real rows, read as pairs (c[2n], c[2n+1]) into stage[b*NH + n]
       copy_in<B * NH, T>(reinterpret_cast<const float2*>(a.in_r) + r0 * NH, (a.nrows - r0) * NH,
                          lds, tid);
       evx_sync();
       static_for<E>([&](auto e) { x[e] = lds[b * NH + t + TPS * decltype(e)::value]; });
+      if constexpr (MODE == ROW_FWD_FP)
+        static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
       evx_sync();
     } else {
       copy_in<B * W, T>(a.in_c + r0 * W, (a.nrows - r0) * W, lds, tid);
@@ -346,17 +349,20 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     // zero flux: rows ra = r0 + 2b, rb = ra + 1, stage as floats [2B][NH]
     constexpr int NX = NH;
     float* st = reinterpret_cast<float*>(lds);
-    const float* in = (MODE == ROW_FWD) ? a.in_r : reinterpret_cast<const float*>(a.in_c);
+    constexpr bool real_in = MODE == ROW_FWD || MODE == ROW_FWD_FP;
+    const float* in = real_in ? a.in_r : reinterpret_cast<const float*>(a.in_c);
     // rows are NX floats (NX even) = NX/2 float2; r0 is even
     copy_in<B * NX, T>(reinterpret_cast<const float2*>(in) + r0 * (NX / 2),
                        (a.nrows - r0) * (NX / 2), lds, tid);
     evx_sync();
-    if constexpr (MODE == ROW_FWD) {
+    if constexpr (real_in) {
       static_for<E>([&](auto e) {
         const int n = t + TPS * decltype(e)::value;
         const int s = makhoul_src<NX>(n);
         x[e] = make_float2(st[(2 * b) * NX + s], st[(2 * b + 1) * NX + s]);
       });
+      if constexpr (MODE == ROW_FWD_FP)
+        static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
       evx_sync();
     } else {
       static_for<E>([&](auto e) {

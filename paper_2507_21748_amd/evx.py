@@ -66,6 +66,11 @@ _PROTOS = {
     "evx_plan_read_pass_times": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_longlong)],
     "evx_plan_set_xcd_remap": [ctypes.c_void_p, ctypes.c_int],
+    "evx_ch_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_void_p],
+    "evx_ch_diagnostics": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Params),
+                           ctypes.c_void_p, ctypes.c_void_p],
 }
 
 
@@ -177,6 +182,29 @@ class Plan:
         _check(_LIB.evx_plan_state(self._h, ctypes.byref(ptr), ctypes.byref(nb)), "evx_plan_state")
         off = ptr.value - self.workspace.data_ptr()
         return self.workspace[off:off + nb.value]
+
+    # ------------------------------------------------------------------ adjoint, diagnostics
+    def adjoint_step(self, c_n: torch.Tensor, lam: torch.Tensor, params: CHParams,
+                     dkappa: torch.Tensor, dM: torch.Tensor, stream=None):
+        """lam <- dL/dc^n from dL/dc^{n+1}; dkappa, dM (1-element float64 device tensors)
+        accumulate the parameter gradients of this step."""
+        p = params.c()
+        _check(_LIB.evx_ch_adjoint_step(
+            self._h, _dev_ptr(c_n, numel=self.voxels), _dev_ptr(lam, numel=self.voxels),
+            ctypes.byref(p), _dev_ptr(dkappa, torch.float64, 1), _dev_ptr(dM, torch.float64, 1),
+            _stream_handle(stream)), "evx_ch_adjoint_step")
+        return lam
+
+    def diagnostics(self, c: torch.Tensor, params: CHParams, out: torch.Tensor = None,
+                    stream=None) -> torch.Tensor:
+        """(mass, energy) of the real field c as a 2-element float64 device tensor."""
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=c.device)
+        p = params.c()
+        _check(_LIB.evx_ch_diagnostics(self._h, _dev_ptr(c, numel=self.voxels), ctypes.byref(p),
+                                       _dev_ptr(out, torch.float64, 2), _stream_handle(stream)),
+               "evx_ch_diagnostics")
+        return out
 
     # ------------------------------------------------------------------ measurement
     def enable_pass_timing(self, on: bool = True):

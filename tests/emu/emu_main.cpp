@@ -8,6 +8,9 @@
 // usage: evx_emu nx ny nz bc scheme dx dt M kappa A nsteps remap in.f32 out.f32
 //   bc 0 periodic / 1 zero flux; scheme 0 spectral / 1 stencil7.  nsteps < 0 runs |nsteps| steps
 //   in two halves with an end + restore between them (the resume path).
+//        evx_emu adj nx ny nz bc scheme dx dt M kappa A c.f32 lam.f32 out_lam.f32 out_grad.f64
+//   one adjoint step (lam <- dL/dc^n, out_grad = [dL/dkappa, dL/dM] of the step).
+//        evx_emu diag nx ny nz bc scheme dx kappa c.f32 out.f64   (mass, energy)
 #include <barrier>
 #include <cstdio>
 #include <cstdlib>
@@ -15,7 +18,9 @@
 #include <thread>
 #include <vector>
 
-#include "evx_schedule.hpp"
+#include <cstring>
+
+#include "evx_adjoint.hpp"
 
 namespace evx_emu {
 thread_local std::barrier<>* block_barrier = nullptr;
@@ -74,6 +79,7 @@ struct EmuLauncher {
     switch (mode) {
       case ROW_FUSED: row_t<NH, BC, ROW_FUSED>(a); break;
       case ROW_FWD: row_t<NH, BC, ROW_FWD>(a); break;
+      case ROW_FWD_FP: row_t<NH, BC, ROW_FWD_FP>(a); break;
       default: row_t<NH, BC, ROW_INV>(a); break;
     }
   }
@@ -89,6 +95,26 @@ struct EmuLauncher {
       default: std::fprintf(stderr, "unsupported column length %d\n", n); std::exit(3);
     }
   }
+  void spec(const SpecArgs& a) {
+    run_grid(AUX_BLOCKS, AUX_THREADS, 2 * AUX_THREADS, [&](int tid, int bid, int nb, float2* lds) {
+      spec_body(a, tid, bid, nb, reinterpret_cast<double*>(lds));
+    });
+  }
+  void realsum(const RealSumArgs& a) {
+    run_grid(AUX_BLOCKS, AUX_THREADS, 2 * AUX_THREADS, [&](int tid, int bid, int nb, float2* lds) {
+      realsum_body(a, tid, bid, nb, reinterpret_cast<double*>(lds));
+    });
+  }
+  void final(const FinalArgs& a) {
+    run_grid(1, AUX_THREADS, 2 * AUX_THREADS, [&](int tid, int, int, float2* lds) {
+      final_body(a, tid, reinterpret_cast<double*>(lds));
+    });
+  }
+  void combine(const CombineArgs& a) {
+    run_grid(AUX_BLOCKS, AUX_THREADS, 1, [&](int tid, int bid, int nb, float2*) {
+      combine_body(a, tid, bid, nb);
+    });
+  }
   void row(int n, int bc, int mode, const RowArgs& a) {
     switch (n) {
 #define EVX_CASE(N)                                   \
@@ -103,7 +129,70 @@ struct EmuLauncher {
   }
 };
 
+static bool read_f32(const char* path, std::vector<float>& v) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return false;
+  const bool ok = std::fread(v.data(), sizeof(float), v.size(), f) == v.size();
+  std::fclose(f);
+  return ok;
+}
+
+template <class T>
+static bool write_all(const char* path, const T* p, size_t n) {
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return false;
+  const bool ok = std::fwrite(p, sizeof(T), n, f) == n;
+  std::fclose(f);
+  return ok;
+}
+
+struct Tabs {
+  HostTables h;
+  TablePtrs t;
+  explicit Tabs(const Geom& g) : h(make_tables(g)) {
+    t = TablePtrs{h.tw_x.data(), h.tw_y.data(), h.tw_z.data(), h.post_x.data(),
+                  h.mk_y.empty() ? nullptr : h.mk_y.data(),
+                  h.mk_z.empty() ? nullptr : h.mk_z.data(), h.k2_x.data(), h.k2_y.data(),
+                  h.k2_z.data()};
+  }
+};
+
+static int run_aux(int argc, char** argv) {
+  const bool adj = std::strcmp(argv[1], "adj") == 0;
+  if ((adj && argc != 16) || (!adj && argc != 11)) return 2;
+  const int nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
+  const int bc = std::atoi(argv[5]), scheme = std::atoi(argv[6]);
+  const double dx = std::atof(argv[7]);
+  const Geom g = make_geom(nx, ny, nz, bc, scheme, dx);
+  Tabs tb(g);
+  std::vector<float2> A(g.spec), B(g.spec), Lm(g.spec);
+  std::vector<float> v(g.V), c(g.V);
+  std::vector<double> partial(2 * AUX_BLOCKS);
+  AdjointBufs bufs{A.data(), B.data(), Lm.data(), v.data(), partial.data()};
+  EmuLauncher l;
+  if (adj) {
+    const double dt = std::atof(argv[8]), M = std::atof(argv[9]), kappa = std::atof(argv[10]);
+    const double Ast = std::atof(argv[11]);
+    std::vector<float> lam(g.V);
+    if (!read_f32(argv[12], c) || !read_f32(argv[13], lam)) return 4;
+    AdjointCoef co{StepCoef{float(Ast * dt), float(dt * M * kappa), float(dt * M)}, float(dt),
+                   float(dt * kappa)};
+    double grads[2] = {0.0, 0.0};
+    sched_adjoint(l, g, tb.t, c.data(), lam.data(), bufs, co, &grads[0], &grads[1], 1);
+    if (!write_all(argv[14], lam.data(), lam.size()) || !write_all(argv[15], grads, 2)) return 5;
+  } else {
+    const double kappa = std::atof(argv[8]);
+    if (!read_f32(argv[9], c)) return 4;
+    double out[2] = {0.0, 0.0};
+    sched_diagnostics(l, g, tb.t, c.data(), kappa, bufs, out, 1);
+    if (!write_all(argv[10], out, 2)) return 5;
+  }
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc > 1 && (std::strcmp(argv[1], "adj") == 0 || std::strcmp(argv[1], "diag") == 0))
+    return run_aux(argc, argv);
   if (argc != 15) {
     std::fprintf(stderr, "usage: %s nx ny nz bc scheme dx dt M kappa A nsteps remap in out\n",
                  argv[0]);

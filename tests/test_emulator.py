@@ -34,6 +34,7 @@ def _build(kind: str) -> str:
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
         if name.endswith(".hpp"):
+            h.update(name.encode())
             h.update(open(os.path.join(CSRC, name), "rb").read())
     h.update(open(MAIN, "rb").read())
     h.update((SIZES + SAN[kind]).encode())
@@ -41,7 +42,8 @@ def _build(kind: str) -> str:
     if not os.path.exists(exe):
         os.makedirs(OUT, exist_ok=True)
         cmd = [gxx, "-std=c++20", "-O1", "-g", SAN[kind], "-DEVX_HOST_EMULATION",
-               f"-DEVX_FOR_EACH_N(X)={SIZES}", "-I", CSRC, MAIN, "-o", exe + ".tmp", "-pthread"]
+               "-DEVX_AUX_BLOCKS=3", f"-DEVX_FOR_EACH_N(X)={SIZES}", "-I", CSRC, MAIN,
+               "-o", exe + ".tmp", "-pthread"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr[-4000:]
         os.replace(exe + ".tmp", exe)
@@ -140,3 +142,37 @@ def test_planted_missing_barrier_is_caught(tmp_path):
                             capture_output=True, text=True, timeout=600,
                             env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
     assert rr.returncode != 0 or "ThreadSanitizer" in rr.stderr
+
+
+@pytest.mark.parametrize("shape,bc,scheme", [((16, 12, 16), "periodic", "spectral"),
+                                             ((8, 24, 16), "zero_flux", "stencil7"),
+                                             ((12, 16, 20), "zero_flux", "spectral")])
+def test_emulated_adjoint_step_and_diagnostics(asan, shape, bc, scheme):
+    """One adjoint step (lam, dL/dkappa, dL/dM) and the mass/energy diagnostics of the emulated
+    kernels against the oracle's adjoint and energy."""
+    from oracle import adjoint
+    p = CHParams(dt=0.5, M=0.8, kappa=1.3, A=2.0)
+    c = quench_field(shape, 0.1, 0.4, seed=3)
+    lam = quench_field(shape, 0.0, 1.0, seed=4)
+    c1 = ch.ch_step(c.astype(np.float64), p, bc, scheme)
+    _, g, dk, dM = adjoint.adjoint_gradients(c, c1 - lam.astype(np.float64) / 2, 1, p, bc, scheme)
+    nz, ny, nx = shape
+    geo = [str(nx), str(ny), str(nz), str(int(bc == "zero_flux")), str(int(scheme == "stencil7")),
+           "1"]
+    with tempfile.TemporaryDirectory() as d:
+        c.tofile(os.path.join(d, "c"))
+        lam.tofile(os.path.join(d, "l"))
+        r = subprocess.run([asan, "adj", *geo, repr(p.dt), repr(p.M), repr(p.kappa), repr(p.A),
+                            os.path.join(d, "c"), os.path.join(d, "l"), os.path.join(d, "lo"),
+                            os.path.join(d, "g")], capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, r.stderr[-4000:]
+        lo = np.fromfile(os.path.join(d, "lo"), np.float32).reshape(shape)
+        gr = np.fromfile(os.path.join(d, "g"), np.float64)
+        r = subprocess.run([asan, "diag", *geo, repr(p.kappa), os.path.join(d, "c"),
+                            os.path.join(d, "o")], capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, r.stderr[-4000:]
+        o = np.fromfile(os.path.join(d, "o"), np.float64)
+    assert _rel(lo, g) <= 1e-6
+    assert abs(gr[0] / dk - 1) <= 2e-6 and abs(gr[1] / dM - 1) <= 2e-6
+    assert abs(o[0] - ch.mass(c.astype(np.float64))) <= 1e-9 * c.size
+    assert abs(o[1] / ch.energy(c.astype(np.float64), p, bc, scheme) - 1) <= 1e-6
