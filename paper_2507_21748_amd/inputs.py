@@ -14,7 +14,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["quench_field", "mode_field", "Workload", "WORKLOADS"]
+__all__ = ["quench_field", "mode_field", "surrogate_init", "SURROGATE_LAYERS", "Workload",
+           "WORKLOADS"]
 
 _CHUNK = 1 << 24
 
@@ -56,6 +57,26 @@ def mode_field(shape, mean: float, delta: float, m=(1, 0, 0), bc: str = "periodi
     else:
         raise ValueError(bc)
     return (mean + delta * mode).astype(np.float32)
+
+
+# Residual conv net of the learned coarse stepper: (Cin, Cout) per 3x3x3 layer.
+SURROGATE_LAYERS = [(1, 32), (32, 32), (32, 32), (32, 1)]
+
+
+def surrogate_init(seed: int, scale_last: float = 0.1) -> np.ndarray:
+    """Seeded initial parameters of the coarse-stepper network as one float32 vector, layer by
+    layer W[27, Cout, Cin] then b[Cout]: uniform(-sqrt(6/fan_in), sqrt(6/fan_in)) weights
+    (fan_in = 27 Cin), zero biases; the last layer is scaled by scale_last so that the initial
+    network is a small perturbation of the identity map."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for li, (ci, co) in enumerate(SURROGATE_LAYERS):
+        bound = float(np.sqrt(6.0 / (27 * ci)))
+        W = rng.uniform(-bound, bound, size=(27, co, ci))
+        if li == len(SURROGATE_LAYERS) - 1:
+            W = W * scale_last
+        parts += [W.reshape(-1), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
 
 
 @dataclass(frozen=True)
