@@ -132,6 +132,12 @@ evx_status evx_ch_adjoint_step(evx_plan* plan, const float* c_n, float* lam,
 evx_status evx_ch_diagnostics(evx_plan* plan, const float* c, const evx_ch_params* params,
                               double* out, void* hip_stream);
 
+/* Distance of two fields on the plan's grid (used to judge surrogate predictions against the
+ * solver): out[0] = sum (a - b)^2, out[1] = sum b^2, FP64, fixed-order reduction.  a, b: device,
+ * V floats (read).  out: two device doubles (written).  Needs EVX_OP_DIAG or EVX_OP_ADJOINT. */
+evx_status evx_ch_distance(evx_plan* plan, const float* a, const float* b, double* out,
+                           void* hip_stream);
+
 /* Kernel timing for measurement: when enabled, advance records a HIP event pair around every
  * pass launch on the launch stream.  read synchronises those events and returns, per pass kind
  * (0 inverse y, 1 fused x, 2 forward y, 3 fused z + update), the summed milliseconds and the
@@ -141,6 +147,47 @@ evx_status evx_plan_read_pass_times(evx_plan* plan, double ms[4], long long coun
 
 /* Block-order option: 1 (default) places consecutive column tiles on the same XCD. */
 evx_status evx_plan_set_xcd_remap(evx_plan* plan, int on);
+
+/* ---------------------------------------------------------------------------------------------
+ * Learned coarse stepper (the paper's Statement of Need: neural-surrogate training on solver
+ * data).  A periodic residual 3D CNN predicts c after 10 solver steps:
+ *   c_out = c + conv4(gelu(conv3(gelu(conv2(gelu(conv1(c))))))),
+ * 3x3x3 cross-correlations with circular padding, channels 1 -> 32 -> 32 -> 32 -> 1, exact-erf
+ * GELU.  BF16 weights and activations (round to nearest even), FP32 accumulation (the 32 -> 32
+ * layers on MFMA), FP32 residual add.  Parameters: one FP32 vector of 57121 values, layer by
+ * layer W[27][Cout][Cin] (offset d = 9 (dz+1) + 3 (dy+1) + (dx+1)) followed by b[Cout].
+ * Activations and grids are C order (nz, ny, nx); fields are FP32 device arrays. */
+typedef struct evx_net evx_net;
+
+evx_status evx_surrogate_param_count(size_t* n);
+/* Allocates the network's BF16 weight copies (about 230 KB) on the current device. */
+evx_status evx_surrogate_create(evx_net** out);
+evx_status evx_surrogate_destroy(evx_net* net);
+/* params: device, 57121 FP32 master values (read; copied).  Enqueued on the stream. */
+evx_status evx_surrogate_set_params(evx_net* net, const float* params, void* hip_stream);
+/* Device bytes of the caller-owned workspace for inference on an nx x ny x nz grid (train = 0,
+ * about 130 bytes per voxel) or for training on edge^3 windows (train = 1, nx = ny = nz = edge,
+ * about 600 bytes per voxel plus 8 MB). */
+evx_status evx_surrogate_workspace_bytes(int nx, int ny, int nz, int train, size_t* bytes);
+/* c_out <- c_in + net(c_in) on a periodic grid.  c_in, c_out: device, V floats (may not alias).
+ * ws: 256-byte aligned device workspace of at least the inference size.  EVX_ERR_STATE if no
+ * parameters were set. */
+evx_status evx_surrogate_infer(evx_net* net, const float* c_in, float* c_out, int nx, int ny,
+                               int nz, void* ws, size_t ws_bytes, void* hip_stream);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8, step >= 1 counts from 1) on the mean squared error
+ * over the interiors of `batch` windows of edge^3 voxels (halo cut from every face):
+ * x, y: device, batch * edge^3 floats (inputs and targets); params, adam_m, adam_v: device FP32
+ * vectors of 57121 values, updated in place (the network's BF16 copies are refreshed);
+ * loss: device double, written with the loss at the parameters before the update. */
+evx_status evx_surrogate_train_step(evx_net* net, const float* x, const float* y, int batch,
+                                    int edge, int halo, float* params, float* adam_m,
+                                    float* adam_v, int step, float lr, double* loss, void* ws,
+                                    size_t ws_bytes, void* hip_stream);
+/* Verification hook: device pointers into a training workspace, holding the last window of the
+ * last train step: [0] bf16(x), [1..6] z1 a1 z2 a2 z3 a3 (BF16 [V][32]), [7] dz1, [8] dz2
+ * (BF16 [V][32]; [7] first holds dz3 and is overwritten by dz1), [9] x + net(x) (FP32), [10]
+ * dL/dy (FP32), [11] the summed parameter gradient (FP32, 57121). */
+evx_status evx_surrogate_train_buffers(void* ws, size_t ws_bytes, int edge, void** ptrs);
 
 const char* evx_status_string(evx_status s);
 const char* evx_last_error(void);

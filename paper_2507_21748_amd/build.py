@@ -60,7 +60,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         obj = os.path.join(BUILD, f"evx_k{n}.o")
         cmds.append([cc, *HIPFLAGS, f"-DEVX_INST_N={n}", "-c",
                      os.path.join(CSRC, "evx_kernels.hip"), "-o", obj])
-    for src in ("evx_api.hip", "evx_aux.hip"):
+    for src in ("evx_api.hip", "evx_aux.hip", "evx_net.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmds.append([cc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

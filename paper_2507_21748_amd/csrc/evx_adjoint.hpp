@@ -96,8 +96,16 @@ void sched_diagnostics(L& l, const Geom& g, const TablePtrs& t, const float* c, 
   const double dx3 = g.dx * g.dx * g.dx;
   // out[1] <- dx^3 (kappa/2) sum w K2 |C|^2, then the real-space sums add f(c) and set the mass
   l.final(FinalArgs{b.partial, AUX_BLOCKS, out + 1, nullptr, dx3 * 0.5 * kappa * norm, 0.0, 0, 0});
-  l.realsum(RealSumArgs{c, g.V, b.partial});
+  l.realsum(RealSumArgs{c, g.V, b.partial, nullptr});
   l.final(FinalArgs{b.partial, AUX_BLOCKS, out + 1, out, dx3, dx3, 1, 0});
+}
+
+// out[0] = sum (a - b)^2, out[1] = sum b^2 (relative L2 distance = sqrt(out[0] / out[1])).
+template <class L>
+void sched_distance(L& l, const Geom& g, const float* a, const float* b, const AdjointBufs& bufs,
+                    double* out) {
+  l.realsum(RealSumArgs{a, g.V, bufs.partial, b});
+  l.final(FinalArgs{bufs.partial, AUX_BLOCKS, out, out + 1, 1.0, 1.0, 0, 0});
 }
 
 }  // namespace evx

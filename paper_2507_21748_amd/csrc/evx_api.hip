@@ -162,6 +162,9 @@ const char* evx_status_string(evx_status s) {
 
 const char* evx_last_error(void) { return g_last_error.c_str(); }
 
+// error channel shared with the surrogate translation unit
+void evx_internal_set_error(const char* msg) { g_last_error = msg; }
+
 evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, evx_scheme scheme,
                            double dx) {
   if (!out) return fail(EVX_ERR_ARG, "out is NULL");
@@ -373,6 +376,17 @@ evx_status evx_ch_diagnostics(evx_plan* p, const float* c, const evx_ch_params* 
   TimedLauncher l = launcher(p, s);
   sched_diagnostics(l, p->g, p->t, c, q->kappa, p->aux, out, p->remap);
   return finish(l, "diagnostics");
+}
+
+evx_status evx_ch_distance(evx_plan* p, const float* a, const float* b, double* out, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!a || !b || !out) return fail(EVX_ERR_ARG, "NULL argument");
+  if (!p->has_diag)
+    return fail(EVX_ERR_NOMEM, "workspace too small for diagnostics (EVX_OP_DIAG)");
+  TimedLauncher l = launcher(p, s);
+  sched_distance(l, p->g, a, b, p->aux, out);
+  return finish(l, "distance");
 }
 
 evx_status evx_plan_enable_pass_timing(evx_plan* p, int on) {

@@ -117,11 +117,13 @@ EVX_DEV void spec_body(const SpecArgs& a, int tid, int bid, int nblk, double* re
   }
 }
 
-// Real-space sums for the diagnostics: partial[2b] = sum f(c), partial[2b+1] = sum c.
+// Real-space sums.  Diagnostics (b == null): partial[2b] = sum f(c), partial[2b+1] = sum c.
+// Distance (b != null): partial[2b] = sum (c - b)^2, partial[2b+1] = sum b^2.
 struct RealSumArgs {
   const float* c;
   long long n;
   double* partial;
+  const float* b;
 };
 
 EVX_DEV void realsum_body(const RealSumArgs& a, int tid, int bid, int nblk, double* red) {
@@ -129,9 +131,15 @@ EVX_DEV void realsum_body(const RealSumArgs& a, int tid, int bid, int nblk, doub
   const long long stride = (long long)nblk * AUX_THREADS;
   for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
     const double c = a.c[i];
-    const double q = c * c - 1.0;
-    s0 += 0.25 * q * q;
-    s1 += c;
+    if (a.b) {
+      const double r = a.b[i];
+      s0 += (c - r) * (c - r);
+      s1 += r * r;
+    } else {
+      const double q = c * c - 1.0;
+      s0 += 0.25 * q * q;
+      s1 += c;
+    }
   }
   block_sum2<AUX_THREADS>(s0, s1, tid, red);
   if (tid == 0) {

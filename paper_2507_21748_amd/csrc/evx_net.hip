@@ -1,0 +1,730 @@
+// Learned coarse stepper: periodic residual 3D CNN c_out = c + net(c), 3x3x3 kernels, channels
+// 1 -> 32 -> 32 -> 32 -> 1, GELU between layers; BF16 weights and activations with FP32
+// accumulation; trained with Adam on FP32 master weights.
+//
+// Layout: activations are channels-last BF16 [V][C] (x fastest over the grid), weights W[27][Cout]
+// [Cin] with offset index d = 9 (dz+1) + 3 (dy+1) + (dx+1); conv(x)[v,o] = b[o] +
+// sum_{d,i} W[d,o,i] x[(v+d) mod grid, i] (cross-correlation, circular padding).
+//
+// Kernels:
+//   conv32_mfma   32 -> 32 layers as an implicit GEMM on v_mfma_f32_16x16x32_bf16: one MFMA per
+//                 (16 voxels, 16 output channels, one offset d, all 32 input channels).  A block
+//                 stages a 6x10x18-voxel halo tile (69 KB) and the layer's weights (55 KB) in LDS
+//                 and computes a 4x8x16 output tile with 8 waves.
+//   conv_small    1 -> 32 and 32 -> 1 layers on the VALU (27*32 MACs per voxel).
+//   wgrad         dW[d,o,i] = sum_v gz[v,o] x[v+d,i] and db, split over voxel chunks with a
+//                 fixed-order reduction (bit-reproducible).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/evx.h"
+
+namespace {
+
+typedef unsigned short bf16_t;
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int CH = 32;
+constexpr int NLAYER = 4;
+
+__host__ __device__ constexpr int cin_of(int l) { return l == 0 ? 1 : CH; }
+__host__ __device__ constexpr int cout_of(int l) { return l == NLAYER - 1 ? 1 : CH; }
+__host__ __device__ constexpr long long layer_w(int l) { return 27LL * cin_of(l) * cout_of(l); }
+// offset of layer l's weights in the flat parameter vector (each layer: W then b)
+__host__ __device__ constexpr long long layer_off(int l) {
+  long long o = 0;
+  for (int i = 0; i < l; ++i) o += layer_w(i) + cout_of(i);
+  return o;
+}
+// offset of layer l's weights in the packed bf16 weight arrays (no biases)
+__host__ __device__ constexpr long long w_off(int l) {
+  long long o = 0;
+  for (int i = 0; i < l; ++i) o += layer_w(i);
+  return o;
+}
+constexpr long long NPARAM = layer_off(NLAYER);  // 57121
+static_assert(NPARAM == 57121, "parameter count");
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return bf16_t(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
+
+__device__ __forceinline__ float gelu(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_prime(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// epilogues
+enum : int {
+  EPI_GELU_Z = 0,   // store zb = bf16(acc + b) and a = bf16(gelu(zb))
+  EPI_GELU = 1,     // store a only (inference)
+  EPI_DGELU = 2,    // store bf16(acc * gelu'(zprev))   (backward data, no bias)
+  EPI_RESID = 3     // out = c + (acc + b)  (last layer, FP32)
+};
+
+struct ConvArgs {
+  const void* in;        // bf16 [V][Cin] or float [V] (Cin == 1, FP32 input)
+  const bf16_t* w;       // bf16 [27][Cout][Cin]
+  const float* bias;     // [Cout] (fp32 master), null for EPI_DGELU
+  bf16_t* z_out;         // EPI_GELU_Z
+  bf16_t* a_out;         // EPI_GELU_Z, EPI_GELU, EPI_DGELU
+  const bf16_t* zprev;   // EPI_DGELU: pre-activation of the layer below [V][Cout]
+  const float* c;        // EPI_RESID: network input (fp32)
+  float* out;            // EPI_RESID
+  int nx, ny, nz;
+};
+
+// ----------------------------------------------------------------------------- MFMA 32 -> 32
+constexpr int TX = 16, TY = 8, TZ = 4;
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+constexpr int HALO_VOX = HX * HY * HZ;           // 1080
+constexpr int MFMA_THREADS = 512;                // 8 waves
+constexpr int HALO_CHUNKS = HALO_VOX * 4;        // 16-byte chunks (64 B per voxel)
+constexpr int W_CHUNKS = 27 * CH * CH * 2 / 16;  // 3456
+
+template <int EPI>
+__global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16_t s_in[HALO_VOX * CH];
+  __shared__ __attribute__((aligned(16))) bf16_t s_w[27 * CH * CH];
+  const int tid = threadIdx.x;
+  const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
+  int t = blockIdx.x;
+  const int x0 = (t % ntx) * TX;
+  t /= ntx;
+  const int y0 = (t % nty) * TY;
+  const int z0 = (t / nty) * TZ;
+
+  // Stage the halo tile and the weights in LDS, four 16-byte loads in flight per thread.
+  const u32x4* gin = static_cast<const u32x4*>(a.in);
+  const u32x4* gw = reinterpret_cast<const u32x4*>(a.w);
+  u32x4* sin4 = reinterpret_cast<u32x4*>(s_in);
+  u32x4* sw4 = reinterpret_cast<u32x4*>(s_w);
+  for (int i0 = tid; i0 < HALO_CHUNKS; i0 += 4 * MFMA_THREADS) {
+    u32x4 r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * MFMA_THREADS;
+      if (i < HALO_CHUNKS) {
+        const int vox = i >> 2, part = i & 3;
+        const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
+        // true modulo: a partial tile may reach up to TX (TY, TZ) points past the grid edge
+        const long long gx = ((x0 + hx - 1) % a.nx + a.nx) % a.nx,
+                        gy = ((y0 + hy - 1) % a.ny + a.ny) % a.ny,
+                        gz = ((z0 + hz - 1) % a.nz + a.nz) % a.nz;
+        r[k] = gin[((gz * a.ny + gy) * a.nx + gx) * 4 + part];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * MFMA_THREADS;
+      if (i < HALO_CHUNKS) sin4[i] = r[k];
+    }
+  }
+  for (int i0 = tid; i0 < W_CHUNKS; i0 += 4 * MFMA_THREADS) {
+    u32x4 r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * MFMA_THREADS;
+      if (i < W_CHUNKS) r[k] = gw[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k * MFMA_THREADS;
+      if (i < W_CHUNKS) sw4[i] = r[k];
+    }
+  }
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int zl = wave >> 1;          // output z within the tile
+  const int yb = (wave & 1) * 4;     // first of 4 output rows
+  const int li = lane & 15, lg = lane >> 4;
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) acc[m][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int d = 0; d < 27; ++d) {
+    const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
+    bf16x8 bw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      bw[h] = *reinterpret_cast<const bf16x8*>(&s_w[((d * CH) + 16 * h + li) * CH + 8 * lg]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int hidx = ((zl + 1 + dz) * HY + (yb + m + 1 + dy)) * HX + (li + 1 + dx);
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&s_in[hidx * CH + 8 * lg]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        acc[m][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[h], acc[m][h], 0, 0, 0);
+    }
+  }
+
+  // D[i][n]: lane holds voxel x offset 4*lg + r, output channel 16 h + li
+  const int z = z0 + zl;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int y = y0 + yb + m;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x = x0 + 4 * lg + r;
+      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+      const long long v = ((long long)z * a.ny + y) * a.nx + x;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int co = 16 * h + li;
+        const float s = acc[m][h][r];
+        if constexpr (EPI == EPI_DGELU) {
+          a.a_out[v * CH + co] = f2bf(s * gelu_prime(bf2f(a.zprev[v * CH + co])));
+        } else {
+          const bf16_t zb = f2bf(s + a.bias[co]);
+          if constexpr (EPI == EPI_GELU_Z) a.z_out[v * CH + co] = zb;
+          a.a_out[v * CH + co] = f2bf(gelu(bf2f(zb)));
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- VALU conv
+// One thread per voxel, all Cout outputs.  IN_F32: the input is FP32 [V] (Cin = 1).
+constexpr int SMALL_THREADS = 256;
+
+template <int CI, int CO, bool IN_F32, int EPI>
+__global__ __launch_bounds__(SMALL_THREADS) void conv_small(ConvArgs a) {
+  __shared__ float s_w[27 * CI * CO];
+  __shared__ float s_b[CO];
+  for (int i = threadIdx.x; i < 27 * CI * CO; i += SMALL_THREADS) s_w[i] = bf2f(a.w[i]);
+  if (EPI != EPI_DGELU)
+    for (int i = threadIdx.x; i < CO; i += SMALL_THREADS) s_b[i] = a.bias[i];
+  __syncthreads();
+  const long long V = (long long)a.nx * a.ny * a.nz;
+  const long long v = (long long)blockIdx.x * SMALL_THREADS + threadIdx.x;
+  if (v >= V) return;
+  const int x = int(v % a.nx), y = int((v / a.nx) % a.ny), z = int(v / ((long long)a.nx * a.ny));
+  float acc[CO];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) acc[o] = 0.f;
+  for (int d = 0; d < 27; ++d) {
+    const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
+    const long long u = ((long long)wrap(z + dz, a.nz) * a.ny + wrap(y + dy, a.ny)) * a.nx +
+                        wrap(x + dx, a.nx);
+    float xin[CI];
+    if constexpr (IN_F32) {
+      xin[0] = static_cast<const float*>(a.in)[u];
+    } else if constexpr (CI == 1) {
+      xin[0] = bf2f(static_cast<const bf16_t*>(a.in)[u]);
+    } else {
+      const uint4* p = reinterpret_cast<const uint4*>(static_cast<const bf16_t*>(a.in) + u * CI);
+#pragma unroll
+      for (int q = 0; q < CI / 8; ++q) {
+        const uint4 w4 = p[q];
+        const unsigned ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          xin[8 * q + 2 * k] = __uint_as_float(ww[k] << 16);
+          xin[8 * q + 2 * k + 1] = __uint_as_float(ww[k] & 0xFFFF0000u);
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < CO; ++o) {
+      float s = 0.f;
+#pragma unroll
+      for (int i = 0; i < CI; ++i) s += s_w[(d * CO + o) * CI + i] * xin[i];
+      acc[o] += s;
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < CO; ++o) {
+    if constexpr (EPI == EPI_RESID) {
+      a.out[v] = a.c[v] + (acc[o] + s_b[o]);
+    } else if constexpr (EPI == EPI_DGELU) {
+      a.a_out[v * CO + o] = f2bf(acc[o] * gelu_prime(bf2f(a.zprev[v * CO + o])));
+    } else {
+      const bf16_t zb = f2bf(acc[o] + s_b[o]);
+      if constexpr (EPI == EPI_GELU_Z) a.z_out[v * CO + o] = zb;
+      a.a_out[v * CO + o] = f2bf(gelu(bf2f(zb)));
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- weight gradient
+// Block (d, chunk): threads (o, i); partial[chunk][d][o][i] = sum_{v in chunk} gz[v,o] x[v+d,i].
+// d == 27 computes the bias gradient (x == 1).
+constexpr int WG_CHUNKS = 64;
+constexpr int WG_TILE = 64;  // voxels staged per iteration
+
+struct WgradArgs {
+  const void* gz;    // bf16 [V][Cout] or float [V] (Cout == 1)
+  const void* x;     // bf16 [V][Cin]
+  float* partial;    // [WG_CHUNKS][28][Cout][Cin]
+  int nx, ny, nz;
+};
+
+template <int CI, int CO, bool GZ_F32>
+__global__ __launch_bounds__(CI * CO) void wgrad(WgradArgs a) {
+  __shared__ float s_g[WG_TILE * CO];
+  __shared__ float s_x[WG_TILE * CI];
+  const int d = blockIdx.x % 28, chunk = blockIdx.x / 28;
+  const int tid = threadIdx.x, o = tid / CI, i = tid % CI;
+  const long long V = (long long)a.nx * a.ny * a.nz;
+  const long long per = (V + WG_CHUNKS - 1) / WG_CHUNKS;
+  const long long v0 = chunk * per, v1 = (v0 + per < V) ? v0 + per : V;
+  const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
+  float acc = 0.f;
+  for (long long vb = v0; vb < v1; vb += WG_TILE) {
+    __syncthreads();
+    for (int k = tid; k < WG_TILE * CO; k += CI * CO) {
+      const long long v = vb + k / CO;
+      float g = 0.f;
+      if (v < v1) {
+        if constexpr (GZ_F32) g = static_cast<const float*>(a.gz)[v];
+        else g = bf2f(static_cast<const bf16_t*>(a.gz)[v * CO + k % CO]);
+      }
+      s_g[k] = g;
+    }
+    for (int k = tid; k < WG_TILE * CI; k += CI * CO) {
+      const long long v = vb + k / CI;
+      float xv = 0.f;
+      if (v < v1) {
+        if (d == 27) {
+          xv = 1.f;
+        } else {
+          const int x = int(v % a.nx), y = int((v / a.nx) % a.ny),
+                    z = int(v / ((long long)a.nx * a.ny));
+          const long long u = ((long long)wrap(z + dz, a.nz) * a.ny + wrap(y + dy, a.ny)) * a.nx +
+                              wrap(x + dx, a.nx);
+          xv = bf2f(static_cast<const bf16_t*>(a.x)[u * CI + k % CI]);
+        }
+      }
+      s_x[k] = xv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < WG_TILE; ++k) acc += s_g[k * CO + o] * s_x[k * CI + i];
+  }
+  a.partial[(((long long)chunk * 28 + d) * CO + o) * CI + i] = acc;
+}
+
+// grad[param] (+)= sum over chunks in fixed order; maps (d, o, i) -> W offset, d == 27 -> bias
+// (only i == 0 of the bias rows is used).
+__global__ void wgrad_reduce(const float* partial, float* grad_w, float* grad_b, int ci, int co) {
+  const int n = 28 * co * ci;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < WG_CHUNKS; ++c) s += partial[(long long)c * n + k];
+  const int d = k / (co * ci), rem = k % (co * ci);
+  if (d < 27) {
+    grad_w[k] += s;
+  } else if (rem % ci == 0) {
+    grad_b[rem / ci] += s;
+  }
+}
+
+// ----------------------------------------------------------------------------- misc element-wise
+__global__ void cast_bf16(const float* c, bf16_t* out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f2bf(c[i]);
+}
+
+// master fp32 params -> bf16 weights in [d][o][i] and the flipped/transposed copy
+// wt[26 - d][i][o] used by the backward-data convolutions (grid.y = layer).
+__global__ void refresh_weights(const float* params, bf16_t* w, bf16_t* wt) {
+  const int l = blockIdx.y;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= layer_w(l)) return;
+  const bf16_t h = f2bf(params[layer_off(l) + k]);
+  w[w_off(l) + k] = h;
+  const int ci = cin_of(l), co = cout_of(l);
+  const int d = int(k / (ci * co)), o = int((k / ci) % co), i = int(k % ci);
+  wt[w_off(l) + ((long long)(26 - d) * ci + i) * co + o] = h;
+}
+
+struct LossArgs {
+  const float* out;     // c + net(c)
+  const float* target;
+  float* dy;            // (2 / n_total) (out - target) on the interior, 0 outside
+  double* partial;      // per block sum of squares
+  int n, halo;          // window edge (cubic) and halo
+  double inv_total;     // 1 / (batch * interior voxels)
+};
+
+constexpr int LOSS_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void loss_kernel(LossArgs a) {
+  __shared__ double red[256];
+  const long long V = (long long)a.n * a.n * a.n;
+  double s = 0.0;
+  for (long long v = (long long)blockIdx.x * 256 + threadIdx.x; v < V;
+       v += (long long)gridDim.x * 256) {
+    const int x = int(v % a.n), y = int((v / a.n) % a.n), z = int(v / ((long long)a.n * a.n));
+    const bool in = x >= a.halo && x < a.n - a.halo && y >= a.halo && y < a.n - a.halo &&
+                    z >= a.halo && z < a.n - a.halo;
+    const float d = in ? a.out[v] - a.target[v] : 0.f;
+    s += double(d) * d;
+    a.dy[v] = float(2.0 * a.inv_total) * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
+}
+
+__global__ void loss_final(const double* partial, int n, double scale, double* loss, int add) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += partial[i];
+  *loss = (add ? *loss : 0.0) + scale * s;
+}
+
+__global__ void adam_kernel(float* p, float* m, float* v, const float* g, long long n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void zero_f32(float* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+}  // namespace
+
+extern "C" void evx_internal_set_error(const char* msg);
+
+namespace {
+
+evx_status nfail(evx_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  evx_internal_set_error(buf);
+  return s;
+}
+
+size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct evx_net {
+  int device = 0;
+  bf16_t* w = nullptr;   // [sum layer_w] bf16
+  bf16_t* wt = nullptr;  // flipped/transposed copies
+  float* params = nullptr;  // device copy of the master weights last set (biases are read here)
+  bool have_params = false;
+};
+
+namespace {
+
+enum : int { K_MFMA = 0, K_IN1 = 1, K_OUT1 = 2, K_BWD_F32 = 3 };
+
+hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
+  const long long V = (long long)a.nx * a.ny * a.nz;
+  const unsigned small_grid = unsigned((V + SMALL_THREADS - 1) / SMALL_THREADS);
+  if (kind == K_MFMA) {
+    const long long nt = (long long)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY) *
+                         ((a.nz + TZ - 1) / TZ);
+    if (epi == EPI_GELU_Z)
+      hipLaunchKernelGGL(conv32_mfma<EPI_GELU_Z>, dim3(unsigned(nt)), dim3(MFMA_THREADS), 0, s, a);
+    else if (epi == EPI_GELU)
+      hipLaunchKernelGGL(conv32_mfma<EPI_GELU>, dim3(unsigned(nt)), dim3(MFMA_THREADS), 0, s, a);
+    else
+      hipLaunchKernelGGL(conv32_mfma<EPI_DGELU>, dim3(unsigned(nt)), dim3(MFMA_THREADS), 0, s, a);
+  } else if (kind == K_IN1) {
+    if (epi == EPI_GELU_Z)
+      hipLaunchKernelGGL((conv_small<1, CH, false, EPI_GELU_Z>), dim3(small_grid),
+                         dim3(SMALL_THREADS), 0, s, a);
+    else
+      hipLaunchKernelGGL((conv_small<1, CH, false, EPI_GELU>), dim3(small_grid),
+                         dim3(SMALL_THREADS), 0, s, a);
+  } else if (kind == K_OUT1) {
+    hipLaunchKernelGGL((conv_small<CH, 1, false, EPI_RESID>), dim3(small_grid),
+                       dim3(SMALL_THREADS), 0, s, a);
+  } else {  // backward data of the last layer: FP32 dY -> bf16 dZ
+    hipLaunchKernelGGL((conv_small<1, CH, true, EPI_DGELU>), dim3(small_grid),
+                       dim3(SMALL_THREADS), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(int layer, const void* gz, const void* x, float* partial, float* grads,
+                        int nx, int ny, int nz, hipStream_t s) {
+  WgradArgs w{gz, x, partial, nx, ny, nz};
+  const unsigned grid = 28 * WG_CHUNKS;
+  if (layer == 0)
+    hipLaunchKernelGGL((wgrad<1, CH, false>), dim3(grid), dim3(CH), 0, s, w);
+  else if (layer == NLAYER - 1)
+    hipLaunchKernelGGL((wgrad<CH, 1, true>), dim3(grid), dim3(CH), 0, s, w);
+  else
+    hipLaunchKernelGGL((wgrad<CH, CH, false>), dim3(grid), dim3(CH * CH), 0, s, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int ci = cin_of(layer), co = cout_of(layer), n = 28 * ci * co;
+  hipLaunchKernelGGL(wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial,
+                     grads + layer_off(layer), grads + layer_off(layer) + layer_w(layer), ci, co);
+  return hipGetLastError();
+}
+
+bool grid_ok(int nx, int ny, int nz) {
+  return nx >= 1 && ny >= 1 && nz >= 1 && (long long)nx * ny * nz * CH < (1LL << 40);
+}
+
+// Inference workspace: X0 (bf16 [V]) | A (bf16 [V][32]) | B (bf16 [V][32]).
+size_t infer_bytes(long long V) { return a256(V * 2) + 2 * a256(V * CH * 2); }
+
+// Training workspace for one n^3 window: X0 | Z1 A1 Z2 A2 Z3 A3 | G0 G1 (bf16 [V][32]) | out dY
+// (f32 [V]) | target (f32 [V]) | wgrad partials | grads (f32 NPARAM) | loss partials.
+struct TrainBufs {
+  bf16_t *x0, *z[3], *act[3], *g[2];
+  float *out, *dy, *partial, *grads;
+  double* lpart;
+};
+
+size_t train_bytes(long long V) {
+  return a256(V * 2) + 8 * a256(V * CH * 2) + 2 * a256(V * 4) +
+         a256(size_t(WG_CHUNKS) * 28 * CH * CH * 4) + a256(NPARAM * 4) +
+         a256(LOSS_BLOCKS * sizeof(double));
+}
+
+TrainBufs carve_train(void* ws, long long V) {
+  char* p = static_cast<char*>(ws);
+  TrainBufs b{};
+  auto take = [&](size_t n) { char* q = p; p += a256(n); return q; };
+  b.x0 = reinterpret_cast<bf16_t*>(take(V * 2));
+  for (int i = 0; i < 3; ++i) {
+    b.z[i] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
+    b.act[i] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
+  }
+  b.g[0] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
+  b.g[1] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
+  b.out = reinterpret_cast<float*>(take(V * 4));
+  b.dy = reinterpret_cast<float*>(take(V * 4));
+  b.partial = reinterpret_cast<float*>(take(size_t(WG_CHUNKS) * 28 * CH * CH * 4));
+  b.grads = reinterpret_cast<float*>(take(NPARAM * 4));
+  b.lpart = reinterpret_cast<double*>(take(LOSS_BLOCKS * sizeof(double)));
+  return b;
+}
+
+ConvArgs conv_args(const evx_net* n, int layer, bool transposed, const void* in, int nx, int ny,
+                   int nz) {
+  ConvArgs a{};
+  a.in = in;
+  a.w = (transposed ? n->wt : n->w) + w_off(layer);
+  a.bias = n->params + layer_off(layer) + layer_w(layer);
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  return a;
+}
+
+#define NET_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) return nfail(EVX_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+evx_status evx_surrogate_param_count(size_t* n) {
+  if (!n) return nfail(EVX_ERR_ARG, "n is NULL");
+  *n = size_t(NPARAM);
+  return EVX_OK;
+}
+
+evx_status evx_surrogate_create(evx_net** out) {
+  if (!out) return nfail(EVX_ERR_ARG, "out is NULL");
+  evx_net* n = new evx_net();
+  hipError_t e = hipGetDevice(&n->device);
+  const size_t wb = a256(size_t(w_off(NLAYER)) * sizeof(bf16_t));
+  if (e == hipSuccess) e = hipMalloc(&n->w, 2 * wb + a256(NPARAM * sizeof(float)));
+  if (e != hipSuccess) {
+    delete n;
+    return nfail(EVX_ERR_HIP, "evx_surrogate_create: %s", hipGetErrorString(e));
+  }
+  n->wt = reinterpret_cast<bf16_t*>(reinterpret_cast<char*>(n->w) + wb);
+  n->params = reinterpret_cast<float*>(reinterpret_cast<char*>(n->w) + 2 * wb);
+  *out = n;
+  return EVX_OK;
+}
+
+evx_status evx_surrogate_destroy(evx_net* n) {
+  if (!n) return nfail(EVX_ERR_ARG, "net is NULL");
+  if (n->w) (void)hipFree(n->w);
+  delete n;
+  return EVX_OK;
+}
+
+evx_status evx_surrogate_set_params(evx_net* n, const float* params, void* stream) {
+  if (!n || !params) return nfail(EVX_ERR_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(n->params, params, NPARAM * sizeof(float),
+                                hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return nfail(EVX_ERR_HIP, "set_params copy: %s", hipGetErrorString(e));
+  const long long nw = layer_w(1);  // the largest layer bounds the per-layer index range
+  hipLaunchKernelGGL(refresh_weights, dim3(unsigned((nw + 255) / 256), NLAYER), dim3(256), 0, s,
+                     n->params, n->w, n->wt);
+  e = hipGetLastError();
+  if (e != hipSuccess) return nfail(EVX_ERR_HIP, "set_params: %s", hipGetErrorString(e));
+  n->have_params = true;
+  return EVX_OK;
+}
+
+evx_status evx_surrogate_workspace_bytes(int nx, int ny, int nz, int train, size_t* bytes) {
+  if (!bytes) return nfail(EVX_ERR_ARG, "bytes is NULL");
+  if (!grid_ok(nx, ny, nz)) return nfail(EVX_ERR_SIZE, "grid %d x %d x %d", nx, ny, nz);
+  const long long V = (long long)nx * ny * nz;
+  *bytes = train ? train_bytes(V) : infer_bytes(V);
+  return EVX_OK;
+}
+
+evx_status evx_surrogate_infer(evx_net* n, const float* c_in, float* c_out, int nx, int ny,
+                               int nz, void* ws, size_t ws_bytes, void* stream) {
+  if (!n || !c_in || !c_out || !ws) return nfail(EVX_ERR_ARG, "NULL argument");
+  if (!n->have_params) return nfail(EVX_ERR_STATE, "parameters not set");
+  if (!grid_ok(nx, ny, nz)) return nfail(EVX_ERR_SIZE, "grid %d x %d x %d", nx, ny, nz);
+  const long long V = (long long)nx * ny * nz;
+  if (ws_bytes < infer_bytes(V)) return nfail(EVX_ERR_NOMEM, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return nfail(EVX_ERR_ARG, "workspace alignment");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* p = static_cast<char*>(ws);
+  bf16_t* x0 = reinterpret_cast<bf16_t*>(p);
+  bf16_t* A = reinterpret_cast<bf16_t*>(p + a256(V * 2));
+  bf16_t* B = reinterpret_cast<bf16_t*>(p + a256(V * 2) + a256(V * CH * 2));
+  hipLaunchKernelGGL(cast_bf16, dim3(unsigned((V + 255) / 256)), dim3(256), 0, s, c_in, x0, V);
+  NET_TRY(hipGetLastError());
+  ConvArgs a = conv_args(n, 0, false, x0, nx, ny, nz);
+  a.a_out = A;
+  NET_TRY(launch_conv(K_IN1, EPI_GELU, a, s));
+  a = conv_args(n, 1, false, A, nx, ny, nz);
+  a.a_out = B;
+  NET_TRY(launch_conv(K_MFMA, EPI_GELU, a, s));
+  a = conv_args(n, 2, false, B, nx, ny, nz);
+  a.a_out = A;
+  NET_TRY(launch_conv(K_MFMA, EPI_GELU, a, s));
+  a = conv_args(n, 3, false, A, nx, ny, nz);
+  a.c = c_in;
+  a.out = c_out;
+  NET_TRY(launch_conv(K_OUT1, EPI_RESID, a, s));
+  return EVX_OK;
+}
+
+evx_status evx_surrogate_train_step(evx_net* n, const float* x, const float* y, int batch,
+                                    int edge, int halo, float* params, float* adam_m,
+                                    float* adam_v, int step, float lr, double* loss,
+                                    void* ws, size_t ws_bytes, void* stream) {
+  if (!n || !x || !y || !params || !adam_m || !adam_v || !loss || !ws)
+    return nfail(EVX_ERR_ARG, "NULL argument");
+  if (batch < 1 || edge < 1 || halo < 0 || 2 * halo >= edge || step < 1 || !(lr > 0))
+    return nfail(EVX_ERR_ARG, "batch %d edge %d halo %d step %d lr %g", batch, edge, halo, step,
+                 double(lr));
+  if (!grid_ok(edge, edge, edge)) return nfail(EVX_ERR_SIZE, "window %d", edge);
+  const long long V = (long long)edge * edge * edge;
+  if (ws_bytes < train_bytes(V)) return nfail(EVX_ERR_NOMEM, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return nfail(EVX_ERR_ARG, "workspace alignment");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  evx_status st = evx_surrogate_set_params(n, params, stream);
+  if (st != EVX_OK) return st;
+  TrainBufs b = carve_train(ws, V);
+  hipLaunchKernelGGL(zero_f32, dim3(unsigned((NPARAM + 255) / 256)), dim3(256), 0, s, b.grads,
+                     NPARAM);
+  NET_TRY(hipGetLastError());
+  const long long inner = (long long)(edge - 2 * halo) * (edge - 2 * halo) * (edge - 2 * halo);
+  const double inv_total = 1.0 / (double(batch) * double(inner));
+  const unsigned vgrid = unsigned((V + 255) / 256);
+  for (int w = 0; w < batch; ++w) {
+    const float* xw = x + w * V;
+    const float* yw = y + w * V;
+    hipLaunchKernelGGL(cast_bf16, dim3(vgrid), dim3(256), 0, s, xw, b.x0, V);
+    NET_TRY(hipGetLastError());
+    // forward, keeping pre-activations
+    ConvArgs a = conv_args(n, 0, false, b.x0, edge, edge, edge);
+    a.z_out = b.z[0];
+    a.a_out = b.act[0];
+    NET_TRY(launch_conv(K_IN1, EPI_GELU_Z, a, s));
+    for (int l = 1; l <= 2; ++l) {
+      a = conv_args(n, l, false, b.act[l - 1], edge, edge, edge);
+      a.z_out = b.z[l];
+      a.a_out = b.act[l];
+      NET_TRY(launch_conv(K_MFMA, EPI_GELU_Z, a, s));
+    }
+    a = conv_args(n, 3, false, b.act[2], edge, edge, edge);
+    a.c = xw;
+    a.out = b.out;
+    NET_TRY(launch_conv(K_OUT1, EPI_RESID, a, s));
+    // loss and dL/dy
+    LossArgs la{b.out, yw, b.dy, b.lpart, edge, halo, inv_total};
+    hipLaunchKernelGGL(loss_kernel, dim3(LOSS_BLOCKS), dim3(256), 0, s, la);
+    NET_TRY(hipGetLastError());
+    hipLaunchKernelGGL(loss_final, dim3(1), dim3(1), 0, s, b.lpart, LOSS_BLOCKS, inv_total, loss,
+                       w > 0 ? 1 : 0);
+    NET_TRY(hipGetLastError());
+    // backward
+    NET_TRY(launch_wgrad(3, b.dy, b.act[2], b.partial, b.grads, edge, edge, edge, s));
+    a = conv_args(n, 3, true, b.dy, edge, edge, edge);
+    a.zprev = b.z[2];
+    a.a_out = b.g[0];
+    NET_TRY(launch_conv(K_BWD_F32, EPI_DGELU, a, s));                        // g0 = dZ3
+    NET_TRY(launch_wgrad(2, b.g[0], b.act[1], b.partial, b.grads, edge, edge, edge, s));
+    a = conv_args(n, 2, true, b.g[0], edge, edge, edge);
+    a.zprev = b.z[1];
+    a.a_out = b.g[1];
+    NET_TRY(launch_conv(K_MFMA, EPI_DGELU, a, s));                           // g1 = dZ2
+    NET_TRY(launch_wgrad(1, b.g[1], b.act[0], b.partial, b.grads, edge, edge, edge, s));
+    a = conv_args(n, 1, true, b.g[1], edge, edge, edge);
+    a.zprev = b.z[0];
+    a.a_out = b.g[0];
+    NET_TRY(launch_conv(K_MFMA, EPI_DGELU, a, s));                           // g0 = dZ1
+    NET_TRY(launch_wgrad(0, b.g[0], b.x0, b.partial, b.grads, edge, edge, edge, s));
+  }
+  const double c1 = 1.0 - std::pow(0.9, double(step)), c2 = 1.0 - std::pow(0.999, double(step));
+  hipLaunchKernelGGL(adam_kernel, dim3(unsigned((NPARAM + 255) / 256)), dim3(256), 0, s, params,
+                     adam_m, adam_v, b.grads, NPARAM, lr, 0.9f, 0.999f, 1e-8f, float(c1),
+                     float(c2));
+  NET_TRY(hipGetLastError());
+  return evx_surrogate_set_params(n, params, stream);
+}
+
+evx_status evx_surrogate_train_buffers(void* ws, size_t ws_bytes, int edge, void** ptrs) {
+  if (!ws || !ptrs) return nfail(EVX_ERR_ARG, "NULL argument");
+  if (!grid_ok(edge, edge, edge)) return nfail(EVX_ERR_SIZE, "window %d", edge);
+  const long long V = (long long)edge * edge * edge;
+  if (ws_bytes < train_bytes(V)) return nfail(EVX_ERR_NOMEM, "workspace too small");
+  TrainBufs b = carve_train(ws, V);
+  void* list[12] = {b.x0, b.z[0], b.act[0], b.z[1], b.act[1], b.z[2], b.act[2],
+                    b.g[0], b.g[1], b.out, b.dy, b.grads};
+  for (int i = 0; i < 12; ++i) ptrs[i] = list[i];
+  return EVX_OK;
+}
+
+}  // extern "C"

@@ -71,6 +71,8 @@ _PROTOS = {
                             ctypes.c_void_p],
     "evx_ch_diagnostics": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Params),
                            ctypes.c_void_p, ctypes.c_void_p],
+    "evx_ch_distance": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_void_p],
 }
 
 
@@ -204,6 +206,17 @@ class Plan:
         _check(_LIB.evx_ch_diagnostics(self._h, _dev_ptr(c, numel=self.voxels), ctypes.byref(p),
                                        _dev_ptr(out, torch.float64, 2), _stream_handle(stream)),
                "evx_ch_diagnostics")
+        return out
+
+    def distance(self, a: torch.Tensor, b: torch.Tensor, out: torch.Tensor = None,
+                 stream=None) -> torch.Tensor:
+        """(sum (a-b)^2, sum b^2) as a 2-element float64 device tensor."""
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=a.device)
+        _check(_LIB.evx_ch_distance(self._h, _dev_ptr(a, numel=self.voxels),
+                                    _dev_ptr(b, numel=self.voxels),
+                                    _dev_ptr(out, torch.float64, 2), _stream_handle(stream)),
+               "evx_ch_distance")
         return out
 
     # ------------------------------------------------------------------ measurement

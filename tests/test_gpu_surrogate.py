@@ -1,0 +1,151 @@
+"""GPU coarse-stepper network against the surrogate oracle.
+
+Layer checks use the GPU's own stored BF16 inputs of each layer, so the comparison isolates one
+kernel: a BF16 output may differ from the FP64 oracle's only where the FP32 accumulation lands on
+the other side of a rounding boundary (at most one BF16 ulp, on a small fraction of values)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate as S
+from paper_2507_21748_amd.inputs import quench_field, surrogate_init
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed=3):
+    th = surrogate_init(seed).astype(np.float64)
+    th += np.random.default_rng(seed).normal(0, 0.02, th.shape)  # non-zero biases
+    return th.astype(np.float32)
+
+
+def _bf(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def _ulp_close(got, ref, frac=2e-3):
+    """All values within one BF16 ulp of the reference, and at most `frac` of them not equal."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    ulp = np.maximum(np.abs(ref), 1e-30) * 2.0 ** -7
+    assert np.all(np.abs(got - ref) <= ulp + 1e-30), np.max(np.abs(got - ref) / ulp)
+    assert np.mean(got != ref) <= frac, np.mean(got != ref)
+
+
+def test_train_step_layers_match_oracle(evx_gpu):
+    from paper_2507_21748_amd.surrogate import Net
+    n, halo = 24, 4
+    theta = _params()
+    net = Net(theta)
+    c = quench_field((n, n, n), 0.1, 0.6, seed=21)
+    t = quench_field((n, n, n), 0.1, 0.6, seed=22)
+    x = torch.from_numpy(c).cuda()[None].contiguous()
+    y = torch.from_numpy(t).cuda()[None].contiguous()
+    loss = net.train_step(x, y, halo, lr=1e-30).item()
+    torch.cuda.synchronize()
+    b = net.train_buffers(n)
+    P = S.unpack(theta)
+    x0 = _bf(b["x0"])
+    assert np.array_equal(x0, S.bf16(c))
+    inp = x0[..., None]
+    for li, (zk, ak) in enumerate((("z1", "a1"), ("z2", "a2"), ("z3", "a3"))):
+        W, bias = P[li]
+        z_ref = S.bf16(S.conv3d(inp, S.bf16(W), bias))
+        z_gpu = _bf(b[zk])
+        _ulp_close(z_gpu, z_ref)
+        _ulp_close(_bf(b[ak]), S.bf16(S.gelu(z_gpu)))
+        inp = _bf(b[ak])
+    W4, b4 = P[3]
+    out_ref = c.astype(np.float64) + S.conv3d(inp, S.bf16(W4), b4)[..., 0]
+    out = b["out"].cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(out - out_ref) / np.linalg.norm(out_ref) <= 1e-6
+    inner = (n - 2 * halo) ** 3
+    d = np.zeros_like(out)
+    sl = slice(halo, n - halo)
+    d[sl, sl, sl] = (out - t)[sl, sl, sl]
+    assert abs(loss / (np.sum(d * d) / inner) - 1) <= 1e-5
+    dy_ref = 2.0 / inner * d
+    dy = b["dy"].cpu().numpy()
+    assert np.max(np.abs(dy - dy_ref)) <= 1e-6 * np.max(np.abs(dy_ref))
+    # backward on the GPU's stored activations
+    acts = [x0[..., None], _bf(b["a1"]), _bf(b["a2"]), _bf(b["a3"])]
+    pres = [_bf(b["z1"]), _bf(b["z2"]), _bf(b["z3"])]
+    g = dy[..., None].astype(np.float64)
+    grads = []
+    gpu_dz = {2: _bf(b["dz2"]), 1: _bf(b["dz1"])}
+    for li in range(3, -1, -1):
+        gW = S.conv3d_weight_grad(g, acts[li])
+        gb = g.reshape(-1, g.shape[-1]).sum(axis=0)
+        grads.append((li, gW, gb))
+        if li > 0:
+            g = S.bf16(S.conv3d_transpose(g, S.bf16(P[li][0])) * S.gelu_prime(pres[li - 1]))
+            if li in gpu_dz:
+                _ulp_close(gpu_dz[li], g, frac=5e-3)
+                g = gpu_dz[li]            # continue from the GPU's own rounding
+    gflat = b["grads"].cpu().numpy().astype(np.float64)
+    off = 0
+    offs = []
+    for (wshape, bshape) in S.layer_shapes():
+        offs.append(off)
+        off += int(np.prod(wshape)) + bshape[0]
+    for li, gW, gb in grads:
+        nw = gW.size
+        got_w = gflat[offs[li]:offs[li] + nw].reshape(gW.shape)
+        got_b = gflat[offs[li] + nw:offs[li] + nw + gb.size]
+        assert np.linalg.norm(got_w - gW) <= 1e-4 * np.linalg.norm(gW), li
+        assert np.linalg.norm(got_b - gb) <= 1e-4 * np.linalg.norm(gb) + 1e-12, li
+
+
+def test_infer_equals_training_forward(evx_gpu):
+    from paper_2507_21748_amd.surrogate import Net
+    n = 24
+    net = Net(_params())
+    c = torch.from_numpy(quench_field((n, n, n), 0.1, 0.6, seed=21)).cuda()
+    net.train_step(c[None].contiguous(), c[None].contiguous(), 4, lr=1e-30)
+    ref = net.train_buffers(n)["out"].clone()
+    net.set_params(net.params)
+    out = net.infer(c)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("shape", [(16, 24, 32), (20, 12, 40), (9, 10, 18)])
+def test_infer_matches_oracle(evx_gpu, shape):
+    """Full network on grids with partial MFMA tiles: the prediction net(c) within 5e-3 relative
+    L2 of the FP64 oracle (BF16 rounding flips propagate through three layers)."""
+    from paper_2507_21748_amd.surrogate import Net
+    theta = _params(4)
+    net = Net(theta)
+    c = quench_field(shape, 0.0, 0.6, seed=23)
+    out = net.infer(torch.from_numpy(c).cuda()).cpu().numpy().astype(np.float64)
+    ref = S.forward(c, theta)
+    dy = out - c
+    dy_ref = ref - c
+    assert np.linalg.norm(dy - dy_ref) / np.linalg.norm(dy_ref) <= 5e-3
+
+
+def test_translation_equivariance_on_gpu(evx_gpu):
+    from paper_2507_21748_amd.surrogate import Net
+    net = Net(_params(5))
+    c = torch.from_numpy(quench_field((32, 32, 48), 0.0, 0.5, seed=24)).cuda()
+    a = net.infer(torch.roll(c, (4, 8, 16), (0, 1, 2)).contiguous())
+    b = torch.roll(net.infer(c), (4, 8, 16), (0, 1, 2))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_training_on_solver_pairs_reduces_loss(evx_gpu):
+    from paper_2507_21748_amd import evx
+    from paper_2507_21748_amd.surrogate import Net, make_pairs, sample_windows
+    prm = evx.CHParams(dt=0.5)
+    pairs = make_pairs((64, 64, 64), [0.0, 0.2], [101], 200, 10, 10, prm)
+    rng = np.random.default_rng(0)
+    net = Net(seed=7)
+    first = last = None
+    for it in range(150):
+        x, y = sample_windows(pairs, 4, 40, rng)
+        L = net.train_step(x, y, 4, lr=1e-3).item()
+        first = L if first is None else first
+        last = L
+    print(f"surrogate training loss {first:.3e} -> {last:.3e}")
+    assert last < 0.5 * first
