@@ -183,10 +183,10 @@ evx_status evx_surrogate_train_step(evx_net* net, const float* x, const float* y
                                     int edge, int halo, float* params, float* adam_m,
                                     float* adam_v, int step, float lr, double* loss, void* ws,
                                     size_t ws_bytes, void* hip_stream);
-/* Verification hook: device pointers into a training workspace, holding the last window of the
- * last train step: [0] bf16(x), [1..6] z1 a1 z2 a2 z3 a3 (BF16 [V][32]), [7] dz1, [8] dz2
- * (BF16 [V][32]; [7] first holds dz3 and is overwritten by dz1), [9] x + net(x) (FP32), [10]
- * dL/dy (FP32), [11] the summed parameter gradient (FP32, 57121). */
+/* Verification hook: 13 device pointers into a training workspace, holding the last window of
+ * the last train step: [0] bf16(x), [1..6] z1 a1 z2 a2 z3 a3 (BF16 [V][32]), [7..9] dz1 dz2 dz3
+ * (BF16 [V][32]), [10] x + net(x) (FP32), [11] dL/dy (FP32), [12] the summed parameter gradient
+ * (FP32, 57121). */
 evx_status evx_surrogate_train_buffers(void* ws, size_t ws_bytes, int edge, void** ptrs);
 
 const char* evx_status_string(evx_status s);

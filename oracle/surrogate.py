@@ -97,14 +97,20 @@ def conv3d_weight_grad(g, x):
     return dW
 
 
+def _Phi(z):
+    """Standard normal CDF via erfc, accurate also in the far negative tail (1 + erf would
+    cancel there)."""
+    return 0.5 * np.vectorize(math.erfc)(-z / math.sqrt(2.0))
+
+
 def gelu(z):
     z = np.asarray(z, dtype=np.float64)
-    return 0.5 * z * (1.0 + np.vectorize(math.erf)(z / math.sqrt(2.0)))
+    return z * _Phi(z)
 
 
 def gelu_prime(z):
     z = np.asarray(z, dtype=np.float64)
-    Phi = 0.5 * (1.0 + np.vectorize(math.erf)(z / math.sqrt(2.0)))
+    Phi = _Phi(z)
     phi = np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
     return Phi + z * phi
 

@@ -59,12 +59,11 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
-__device__ __forceinline__ float gelu(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
-}
+// Phi(z) = erfc(-z / sqrt 2) / 2 (no cancellation in the negative tail, unlike 1 + erf)
+__device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfcf(-z * 0.70710678118654752f); }
+__device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
 __device__ __forceinline__ float gelu_prime(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return phi_cdf(z) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -501,16 +500,16 @@ bool grid_ok(int nx, int ny, int nz) {
 // Inference workspace: X0 (bf16 [V]) | A (bf16 [V][32]) | B (bf16 [V][32]).
 size_t infer_bytes(long long V) { return a256(V * 2) + 2 * a256(V * CH * 2); }
 
-// Training workspace for one n^3 window: X0 | Z1 A1 Z2 A2 Z3 A3 | G0 G1 (bf16 [V][32]) | out dY
+// Training workspace for one n^3 window: X0 | Z1 A1 Z2 A2 Z3 A3 | dZ3 dZ2 dZ1 (bf16 [V][32]) | out dY
 // (f32 [V]) | target (f32 [V]) | wgrad partials | grads (f32 NPARAM) | loss partials.
 struct TrainBufs {
-  bf16_t *x0, *z[3], *act[3], *g[2];
+  bf16_t *x0, *z[3], *act[3], *g[3];  // g[0] = dz3, g[1] = dz2, g[2] = dz1
   float *out, *dy, *partial, *grads;
   double* lpart;
 };
 
 size_t train_bytes(long long V) {
-  return a256(V * 2) + 8 * a256(V * CH * 2) + 2 * a256(V * 4) +
+  return a256(V * 2) + 9 * a256(V * CH * 2) + 2 * a256(V * 4) +
          a256(size_t(WG_CHUNKS) * 28 * CH * CH * 4) + a256(NPARAM * 4) +
          a256(LOSS_BLOCKS * sizeof(double));
 }
@@ -524,8 +523,7 @@ TrainBufs carve_train(void* ws, long long V) {
     b.z[i] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
     b.act[i] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
   }
-  b.g[0] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
-  b.g[1] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
+  for (int i = 0; i < 3; ++i) b.g[i] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
   b.out = reinterpret_cast<float*>(take(V * 4));
   b.dy = reinterpret_cast<float*>(take(V * 4));
   b.partial = reinterpret_cast<float*>(take(size_t(WG_CHUNKS) * 28 * CH * CH * 4));
@@ -703,9 +701,9 @@ evx_status evx_surrogate_train_step(evx_net* n, const float* x, const float* y, 
     NET_TRY(launch_wgrad(1, b.g[1], b.act[0], b.partial, b.grads, edge, edge, edge, s));
     a = conv_args(n, 1, true, b.g[1], edge, edge, edge);
     a.zprev = b.z[0];
-    a.a_out = b.g[0];
-    NET_TRY(launch_conv(K_MFMA, EPI_DGELU, a, s));                           // g0 = dZ1
-    NET_TRY(launch_wgrad(0, b.g[0], b.x0, b.partial, b.grads, edge, edge, edge, s));
+    a.a_out = b.g[2];
+    NET_TRY(launch_conv(K_MFMA, EPI_DGELU, a, s));                           // g2 = dZ1
+    NET_TRY(launch_wgrad(0, b.g[2], b.x0, b.partial, b.grads, edge, edge, edge, s));
   }
   const double c1 = 1.0 - std::pow(0.9, double(step)), c2 = 1.0 - std::pow(0.999, double(step));
   hipLaunchKernelGGL(adam_kernel, dim3(unsigned((NPARAM + 255) / 256)), dim3(256), 0, s, params,
@@ -721,9 +719,9 @@ evx_status evx_surrogate_train_buffers(void* ws, size_t ws_bytes, int edge, void
   const long long V = (long long)edge * edge * edge;
   if (ws_bytes < train_bytes(V)) return nfail(EVX_ERR_NOMEM, "workspace too small");
   TrainBufs b = carve_train(ws, V);
-  void* list[12] = {b.x0, b.z[0], b.act[0], b.z[1], b.act[1], b.z[2], b.act[2],
-                    b.g[0], b.g[1], b.out, b.dy, b.grads};
-  for (int i = 0; i < 12; ++i) ptrs[i] = list[i];
+  void* list[13] = {b.x0, b.z[0], b.act[0], b.z[1], b.act[1], b.z[2], b.act[2],
+                    b.g[2], b.g[1], b.g[0], b.out, b.dy, b.grads};
+  for (int i = 0; i < 13; ++i) ptrs[i] = list[i];
   return EVX_OK;
 }
 

@@ -145,7 +145,7 @@ class Net:
     def train_buffers(self, n: int) -> dict:
         """Views of the last train step's stored activations and gradients (verification)."""
         ws = self._workspace((n, n, n), True)
-        ptrs = (ctypes.c_void_p * 12)()
+        ptrs = (ctypes.c_void_p * 13)()
         evx._check(evx._LIB.evx_surrogate_train_buffers(ws.ptr, ws.nbytes, n, ptrs),
                    "evx_surrogate_train_buffers")
         V = n ** 3
@@ -158,8 +158,8 @@ class Net:
 
         return {"x0": bf(0, 1)[..., 0], "z1": bf(1, 32), "a1": bf(2, 32), "z2": bf(3, 32),
                 "a2": bf(4, 32), "z3": bf(5, 32), "a3": bf(6, 32), "dz1": bf(7, 32),
-                "dz2": bf(8, 32), "out": f32(9, V).reshape(n, n, n),
-                "dy": f32(10, V).reshape(n, n, n), "grads": f32(11, self.nparam)}
+                "dz2": bf(8, 32), "dz3": bf(9, 32), "out": f32(10, V).reshape(n, n, n),
+                "dy": f32(11, V).reshape(n, n, n), "grads": f32(12, self.nparam)}
 
 
 # ------------------------------------------------------------------------------ training data
