@@ -169,11 +169,14 @@ evx_status evx_surrogate_set_params(evx_net* net, const float* params, void* hip
  * about 130 bytes per voxel) or for training on edge^3 windows (train = 1, nx = ny = nz = edge,
  * about 600 bytes per voxel plus 8 MB). */
 evx_status evx_surrogate_workspace_bytes(int nx, int ny, int nz, int train, size_t* bytes);
-/* c_out <- c_in + net(c_in) on a periodic grid.  c_in, c_out: device, V floats (may not alias).
+/* c_out <- c_in + net(c_in) on a periodic grid.  With EVX_SURROGATE_CONSERVE_MASS in flags the
+ * predicted increment's spatial mean is removed (FP64 fixed-order sum), so the prediction
+ * conserves mass like the solver does.  c_in, c_out: device, V floats (may not alias).
  * ws: 256-byte aligned device workspace of at least the inference size.  EVX_ERR_STATE if no
  * parameters were set. */
+enum { EVX_SURROGATE_CONSERVE_MASS = 1 };
 evx_status evx_surrogate_infer(evx_net* net, const float* c_in, float* c_out, int nx, int ny,
-                               int nz, void* ws, size_t ws_bytes, void* hip_stream);
+                               int nz, int flags, void* ws, size_t ws_bytes, void* hip_stream);
 /* One Adam step (b1 0.9, b2 0.999, eps 1e-8, step >= 1 counts from 1) on the mean squared error
  * over the interiors of `batch` windows of edge^3 voxels (halo cut from every face):
  * x, y: device, batch * edge^3 floats (inputs and targets); params, adam_m, adam_v: device FP32

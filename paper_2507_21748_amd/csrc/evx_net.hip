@@ -21,6 +21,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 
 #include "../../include/evx.h"
 
@@ -79,6 +80,7 @@ enum : int {
 struct ConvArgs {
   const void* in;        // bf16 [V][Cin] or float [V] (Cin == 1, FP32 input)
   const bf16_t* w;       // bf16 [27][Cout][Cin]
+  const float* wf;       // the same weights as FP32 values (BF16-rounded), for the VALU layers
   const float* bias;     // [Cout] (fp32 master), null for EPI_DGELU
   bf16_t* z_out;         // EPI_GELU_Z
   bf16_t* a_out;         // EPI_GELU_Z, EPI_GELU, EPI_DGELU
@@ -96,10 +98,175 @@ constexpr int MFMA_THREADS = 512;                // 8 waves
 constexpr int HALO_CHUNKS = HALO_VOX * 4;        // 16-byte chunks (64 B per voxel)
 constexpr int W_CHUNKS = 27 * CH * CH * 2 / 16;  // 3456
 
+constexpr int HALO_IT = (HALO_CHUNKS + MFMA_THREADS - 1) / MFMA_THREADS;  // 9
+constexpr int ACC_STRIDE = CH + 1;  // floats per voxel row of the epilogue staging (bank spread)
+static_assert(TX * TY * TZ * ACC_STRIDE * 4 <= HALO_VOX * CH * 2, "epilogue staging fits");
+
+// Persistent: each block stages the weights once and walks tiles blockIdx.x, +gridDim.x, ...;
+// the next tile's halo is loaded into registers while the current one is computed.
 template <int EPI>
-__global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a) {
+__global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntiles) {
   __shared__ __attribute__((aligned(16))) bf16_t s_in[HALO_VOX * CH];
   __shared__ __attribute__((aligned(16))) bf16_t s_w[27 * CH * CH];
+  const int tid = threadIdx.x;
+  const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
+  const u32x4* gin = static_cast<const u32x4*>(a.in);
+  u32x4* sin4 = reinterpret_cast<u32x4*>(s_in);
+  {
+    const u32x4* gw = reinterpret_cast<const u32x4*>(a.w);
+    u32x4* sw4 = reinterpret_cast<u32x4*>(s_w);
+    for (int i0 = tid; i0 < W_CHUNKS; i0 += 4 * MFMA_THREADS) {
+      u32x4 r[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + k * MFMA_THREADS;
+        if (i < W_CHUNKS) r[k] = gw[i];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + k * MFMA_THREADS;
+        if (i < W_CHUNKS) sw4[i] = r[k];
+      }
+    }
+  }
+  u32x4 pre[HALO_IT];
+  auto fetch = [&](int tl) {
+    const int fx0 = (tl % ntx) * TX;
+    const int rest = tl / ntx;
+    const int fy0 = (rest % nty) * TY, fz0 = (rest / nty) * TZ;
+#pragma unroll
+    for (int k = 0; k < HALO_IT; ++k) {
+      const int i = tid + k * MFMA_THREADS;
+      if (i < HALO_CHUNKS) {
+        const int vox = i >> 2, part = i & 3;
+        const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
+        // true modulo: a partial tile may reach up to TX (TY, TZ) points past the grid edge
+        const long long gx = ((fx0 + hx - 1) % a.nx + a.nx) % a.nx,
+                        gy = ((fy0 + hy - 1) % a.ny + a.ny) % a.ny,
+                        gz = ((fz0 + hz - 1) % a.nz + a.nz) % a.nz;
+        pre[k] = gin[((gz * a.ny + gy) * a.nx + gx) * 4 + part];
+      }
+    }
+  };
+  int tile = blockIdx.x;
+  if (tile < ntiles) fetch(tile);
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int zl = wave >> 1;          // output z within the tile
+  const int yb = (wave & 1) * 4;     // first of the wave's 4 output rows
+  const int li = lane & 15, lg = lane >> 4;
+  float* s_acc = reinterpret_cast<float*>(s_in);
+
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int x0 = (tile % ntx) * TX;
+    const int rest = tile / ntx;
+    const int y0 = (rest % nty) * TY, z0 = (rest / nty) * TZ;
+    __syncthreads();  // the previous tile's epilogue is done with the LDS tile
+#pragma unroll
+    for (int k = 0; k < HALO_IT; ++k) {
+      const int i = tid + k * MFMA_THREADS;
+      if (i < HALO_CHUNKS) sin4[i] = pre[k];
+    }
+    __syncthreads();
+    if (tile + int(gridDim.x) < ntiles) fetch(tile + gridDim.x);
+
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) acc[m][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // For fixed (dz, dx) an input row yr of the halo feeds output rows m = yr - 1 - dy of the
+    // wave (dy in {-1, 0, 1}): load its A fragment once and apply it to each of them.
+    for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi) {
+        bf16x8 bw[3][2];
+#pragma unroll
+        for (int dyi = 0; dyi < 3; ++dyi)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int d = (dz + 1) * 9 + dyi * 3 + dxi;
+            bw[dyi][h] =
+                *reinterpret_cast<const bf16x8*>(&s_w[((d * CH) + 16 * h + li) * CH + 8 * lg]);
+          }
+#pragma unroll
+        for (int yr = 0; yr < 6; ++yr) {
+          const int hidx = ((zl + 1 + dz) * HY + (yb + yr)) * HX + (li + dxi);
+          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&s_in[hidx * CH + 8 * lg]);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int dyi = yr - m;  // dy + 1
+            if (dyi < 0 || dyi > 2) continue;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              acc[m][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dyi][h], acc[m][h], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // stage the FP32 accumulators as [voxel][channel] (D[i][n]: voxel x offset 4 lg + r,
+    // channel 16 h + li), then leave with 16-byte stores
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int vl = (zl * TY + yb + m) * TX + 4 * lg + r;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) s_acc[vl * ACC_STRIDE + 16 * h + li] = acc[m][h][r];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < (TX * TY * TZ * 4) / MFMA_THREADS; ++k) {
+      const int item = tid + k * MFMA_THREADS;
+      const int vl = item >> 2, g = item & 3;
+      const int x = x0 + vl % TX, y = y0 + (vl / TX) % TY, z = z0 + vl / (TX * TY);
+      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+      const long long v = ((long long)z * a.ny + y) * a.nx + x;
+      float val[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) val[j] = s_acc[vl * ACC_STRIDE + 8 * g + j];
+      unsigned aw[4], zw[4];
+      if constexpr (EPI == EPI_DGELU) {
+        const u32x4 zp = reinterpret_cast<const u32x4*>(a.zprev + v * CH)[g];
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+          const bf16_t lo = f2bf(val[2 * k2] * gelu_prime(__uint_as_float(zp[k2] << 16)));
+          const bf16_t hi =
+              f2bf(val[2 * k2 + 1] * gelu_prime(__uint_as_float(zp[k2] & 0xFFFF0000u)));
+          aw[k2] = unsigned(lo) | (unsigned(hi) << 16);
+        }
+      } else {
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+          const int o = 8 * g + 2 * k2;
+          const bf16_t zlo = f2bf(val[2 * k2] + a.bias[o]);
+          const bf16_t zhi = f2bf(val[2 * k2 + 1] + a.bias[o + 1]);
+          zw[k2] = unsigned(zlo) | (unsigned(zhi) << 16);
+          aw[k2] = unsigned(f2bf(gelu(bf2f(zlo)))) | (unsigned(f2bf(gelu(bf2f(zhi)))) << 16);
+        }
+        if constexpr (EPI == EPI_GELU_Z)
+          reinterpret_cast<u32x4*>(a.z_out + v * CH)[g] = u32x4{zw[0], zw[1], zw[2], zw[3]};
+      }
+      reinterpret_cast<u32x4*>(a.a_out + v * CH)[g] = u32x4{aw[0], aw[1], aw[2], aw[3]};
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- VALU conv
+// 1 -> 32 and 32 -> 1 layers on the VALU.  A block owns the same 4x8x16 output tile as the MFMA
+// kernel, stages its 6x10x18 halo (and the weights, as FP32) in LDS, and each thread computes one
+// voxel's Cout outputs; BF16 outputs leave as 16-byte stores (64 contiguous bytes per thread).
+// IN_F32: the input is FP32 [V] (Cin = 1).
+constexpr int SMALL_THREADS = TX * TY * TZ;  // 512
+
+template <int CI, int CO, bool IN_F32, int EPI>
+__global__ __launch_bounds__(SMALL_THREADS) void conv_small(ConvArgs a) {
+  constexpr int IN_BYTES = IN_F32 ? 4 : 2 * CI;              // per voxel
+  __shared__ __attribute__((aligned(16))) unsigned char s_in[HALO_VOX * IN_BYTES];
+  __shared__ float s_b[CO];
+  // block-uniform weight reads: served by the scalar cache, no LDS traffic per FMA
+  const float* __restrict__ W = a.wf;
   const int tid = threadIdx.x;
   const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
   int t = blockIdx.x;
@@ -107,159 +274,130 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a) {
   t /= ntx;
   const int y0 = (t % nty) * TY;
   const int z0 = (t / nty) * TZ;
-
-  // Stage the halo tile and the weights in LDS, four 16-byte loads in flight per thread.
-  const u32x4* gin = static_cast<const u32x4*>(a.in);
-  const u32x4* gw = reinterpret_cast<const u32x4*>(a.w);
-  u32x4* sin4 = reinterpret_cast<u32x4*>(s_in);
-  u32x4* sw4 = reinterpret_cast<u32x4*>(s_w);
-  for (int i0 = tid; i0 < HALO_CHUNKS; i0 += 4 * MFMA_THREADS) {
-    u32x4 r[4];
+  // stage the halo: every load of a thread is issued before its LDS writes
+  if constexpr (IN_BYTES % 16 == 0) {
+    constexpr int CPV = IN_BYTES / 16;  // 16-byte chunks per voxel
+    constexpr int IT = (HALO_VOX * CPV + SMALL_THREADS - 1) / SMALL_THREADS;
+    const u32x4* gin = static_cast<const u32x4*>(a.in);
+    u32x4* sv = reinterpret_cast<u32x4*>(s_in);
+    u32x4 r[IT];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k * MFMA_THREADS;
-      if (i < HALO_CHUNKS) {
-        const int vox = i >> 2, part = i & 3;
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * SMALL_THREADS;
+      if (i < HALO_VOX * CPV) {
+        const int vox = i / CPV, part = i % CPV;
         const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
-        // true modulo: a partial tile may reach up to TX (TY, TZ) points past the grid edge
         const long long gx = ((x0 + hx - 1) % a.nx + a.nx) % a.nx,
                         gy = ((y0 + hy - 1) % a.ny + a.ny) % a.ny,
                         gz = ((z0 + hz - 1) % a.nz + a.nz) % a.nz;
-        r[k] = gin[((gz * a.ny + gy) * a.nx + gx) * 4 + part];
+        r[k] = gin[((gz * a.ny + gy) * a.nx + gx) * CPV + part];
       }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k * MFMA_THREADS;
-      if (i < HALO_CHUNKS) sin4[i] = r[k];
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * SMALL_THREADS;
+      if (i < HALO_VOX * CPV) sv[i] = r[k];
     }
-  }
-  for (int i0 = tid; i0 < W_CHUNKS; i0 += 4 * MFMA_THREADS) {
-    u32x4 r[4];
+  } else {
+    // one element per voxel (2-byte BF16 or 4-byte FP32)
+    typedef typename std::conditional<IN_F32, unsigned, bf16_t>::type elem_t;
+    constexpr int IT = (HALO_VOX + SMALL_THREADS - 1) / SMALL_THREADS;
+    const elem_t* gin = static_cast<const elem_t*>(a.in);
+    elem_t* se = reinterpret_cast<elem_t*>(s_in);
+    elem_t r[IT];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k * MFMA_THREADS;
-      if (i < W_CHUNKS) r[k] = gw[i];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int i = i0 + k * MFMA_THREADS;
-      if (i < W_CHUNKS) sw4[i] = r[k];
-    }
-  }
-  __syncthreads();
-
-  const int wave = tid >> 6, lane = tid & 63;
-  const int zl = wave >> 1;          // output z within the tile
-  const int yb = (wave & 1) * 4;     // first of 4 output rows
-  const int li = lane & 15, lg = lane >> 4;
-  f32x4 acc[4][2];
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) acc[m][h] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  for (int d = 0; d < 27; ++d) {
-    const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
-    bf16x8 bw[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-      bw[h] = *reinterpret_cast<const bf16x8*>(&s_w[((d * CH) + 16 * h + li) * CH + 8 * lg]);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int hidx = ((zl + 1 + dz) * HY + (yb + m + 1 + dy)) * HX + (li + 1 + dx);
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&s_in[hidx * CH + 8 * lg]);
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        acc[m][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[h], acc[m][h], 0, 0, 0);
-    }
-  }
-
-  // D[i][n]: lane holds voxel x offset 4*lg + r, output channel 16 h + li
-  const int z = z0 + zl;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int y = y0 + yb + m;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int x = x0 + 4 * lg + r;
-      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-      const long long v = ((long long)z * a.ny + y) * a.nx + x;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int co = 16 * h + li;
-        const float s = acc[m][h][r];
-        if constexpr (EPI == EPI_DGELU) {
-          a.a_out[v * CH + co] = f2bf(s * gelu_prime(bf2f(a.zprev[v * CH + co])));
-        } else {
-          const bf16_t zb = f2bf(s + a.bias[co]);
-          if constexpr (EPI == EPI_GELU_Z) a.z_out[v * CH + co] = zb;
-          a.a_out[v * CH + co] = f2bf(gelu(bf2f(zb)));
-        }
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * SMALL_THREADS;
+      if (i < HALO_VOX) {
+        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+        const long long gx = ((x0 + hx - 1) % a.nx + a.nx) % a.nx,
+                        gy = ((y0 + hy - 1) % a.ny + a.ny) % a.ny,
+                        gz = ((z0 + hz - 1) % a.nz + a.nz) % a.nz;
+        r[k] = gin[(gz * a.ny + gy) * a.nx + gx];
       }
     }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * SMALL_THREADS;
+      if (i < HALO_VOX) se[i] = r[k];
+    }
   }
-}
-
-// ----------------------------------------------------------------------------- VALU conv
-// One thread per voxel, all Cout outputs.  IN_F32: the input is FP32 [V] (Cin = 1).
-constexpr int SMALL_THREADS = 256;
-
-template <int CI, int CO, bool IN_F32, int EPI>
-__global__ __launch_bounds__(SMALL_THREADS) void conv_small(ConvArgs a) {
-  __shared__ float s_w[27 * CI * CO];
-  __shared__ float s_b[CO];
-  for (int i = threadIdx.x; i < 27 * CI * CO; i += SMALL_THREADS) s_w[i] = bf2f(a.w[i]);
   if (EPI != EPI_DGELU)
-    for (int i = threadIdx.x; i < CO; i += SMALL_THREADS) s_b[i] = a.bias[i];
+    for (int i = tid; i < CO; i += SMALL_THREADS) s_b[i] = a.bias[i];
   __syncthreads();
-  const long long V = (long long)a.nx * a.ny * a.nz;
-  const long long v = (long long)blockIdx.x * SMALL_THREADS + threadIdx.x;
-  if (v >= V) return;
-  const int x = int(v % a.nx), y = int((v / a.nx) % a.ny), z = int(v / ((long long)a.nx * a.ny));
+
+  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
   float acc[CO];
 #pragma unroll
   for (int o = 0; o < CO; ++o) acc[o] = 0.f;
   for (int d = 0; d < 27; ++d) {
     const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
-    const long long u = ((long long)wrap(z + dz, a.nz) * a.ny + wrap(y + dy, a.ny)) * a.nx +
-                        wrap(x + dx, a.nx);
+    const int h = ((lz + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
     float xin[CI];
     if constexpr (IN_F32) {
-      xin[0] = static_cast<const float*>(a.in)[u];
+      xin[0] = reinterpret_cast<const float*>(s_in)[h];
     } else if constexpr (CI == 1) {
-      xin[0] = bf2f(static_cast<const bf16_t*>(a.in)[u]);
+      xin[0] = bf2f(reinterpret_cast<const bf16_t*>(s_in)[h]);
     } else {
-      const uint4* p = reinterpret_cast<const uint4*>(static_cast<const bf16_t*>(a.in) + u * CI);
+      const u32x4* p = reinterpret_cast<const u32x4*>(s_in + size_t(h) * IN_BYTES);
 #pragma unroll
       for (int q = 0; q < CI / 8; ++q) {
-        const uint4 w4 = p[q];
-        const unsigned ww[4] = {w4.x, w4.y, w4.z, w4.w};
+        const u32x4 w4 = p[q];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          xin[8 * q + 2 * k] = __uint_as_float(ww[k] << 16);
-          xin[8 * q + 2 * k + 1] = __uint_as_float(ww[k] & 0xFFFF0000u);
+          xin[8 * q + 2 * k] = __uint_as_float(w4[k] << 16);
+          xin[8 * q + 2 * k + 1] = __uint_as_float(w4[k] & 0xFFFF0000u);
         }
       }
     }
 #pragma unroll
     for (int o = 0; o < CO; ++o) {
+      // multiply-adds may fuse here (the library is otherwise built without contraction)
+#pragma clang fp contract(fast)
       float s = 0.f;
 #pragma unroll
-      for (int i = 0; i < CI; ++i) s += s_w[(d * CO + o) * CI + i] * xin[i];
+      for (int i = 0; i < CI; ++i) s += W[(d * CO + o) * CI + i] * xin[i];
       acc[o] += s;
     }
   }
+  if (x >= a.nx || y >= a.ny || z >= a.nz) return;
+  const long long v = ((long long)z * a.ny + y) * a.nx + x;
+  if constexpr (EPI == EPI_RESID) {
+    a.out[v] = a.c[v] + (acc[0] + s_b[0]);
+  } else {
+    // CO == 32: pack pairs of bf16 into words, 4 x 16-byte stores per output array
+    unsigned zw[CO / 2], aw[CO / 2];
+    if constexpr (EPI == EPI_DGELU) {
+      const u32x4* zp = reinterpret_cast<const u32x4*>(a.zprev + v * CO);
 #pragma unroll
-  for (int o = 0; o < CO; ++o) {
-    if constexpr (EPI == EPI_RESID) {
-      a.out[v] = a.c[v] + (acc[o] + s_b[o]);
-    } else if constexpr (EPI == EPI_DGELU) {
-      a.a_out[v * CO + o] = f2bf(acc[o] * gelu_prime(bf2f(a.zprev[v * CO + o])));
+      for (int q = 0; q < CO / 8; ++q) {
+        const u32x4 w4 = zp[q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int o = 8 * q + 2 * k;
+          const bf16_t lo = f2bf(acc[o] * gelu_prime(__uint_as_float(w4[k] << 16)));
+          const bf16_t hi = f2bf(acc[o + 1] * gelu_prime(__uint_as_float(w4[k] & 0xFFFF0000u)));
+          aw[o / 2] = unsigned(lo) | (unsigned(hi) << 16);
+        }
+      }
     } else {
-      const bf16_t zb = f2bf(acc[o] + s_b[o]);
-      if constexpr (EPI == EPI_GELU_Z) a.z_out[v * CO + o] = zb;
-      a.a_out[v * CO + o] = f2bf(gelu(bf2f(zb)));
+#pragma unroll
+      for (int o = 0; o < CO; o += 2) {
+        const bf16_t z0b = f2bf(acc[o] + s_b[o]), z1b = f2bf(acc[o + 1] + s_b[o + 1]);
+        zw[o / 2] = unsigned(z0b) | (unsigned(z1b) << 16);
+        aw[o / 2] = unsigned(f2bf(gelu(bf2f(z0b)))) | (unsigned(f2bf(gelu(bf2f(z1b)))) << 16);
+      }
+    }
+    u32x4* ap = reinterpret_cast<u32x4*>(a.a_out + v * CO);
+#pragma unroll
+    for (int q = 0; q < CO / 8; ++q)
+      ap[q] = u32x4{aw[4 * q], aw[4 * q + 1], aw[4 * q + 2], aw[4 * q + 3]};
+    if constexpr (EPI == EPI_GELU_Z) {
+      u32x4* zp = reinterpret_cast<u32x4*>(a.z_out + v * CO);
+#pragma unroll
+      for (int q = 0; q < CO / 8; ++q)
+        zp[q] = u32x4{zw[4 * q], zw[4 * q + 1], zw[4 * q + 2], zw[4 * q + 3]};
     }
   }
 }
@@ -346,15 +484,19 @@ __global__ void cast_bf16(const float* c, bf16_t* out, long long n) {
 
 // master fp32 params -> bf16 weights in [d][o][i] and the flipped/transposed copy
 // wt[26 - d][i][o] used by the backward-data convolutions (grid.y = layer).
-__global__ void refresh_weights(const float* params, bf16_t* w, bf16_t* wt) {
+__global__ void refresh_weights(const float* params, bf16_t* w, bf16_t* wt, float* wf,
+                                float* wtf) {
   const int l = blockIdx.y;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= layer_w(l)) return;
   const bf16_t h = f2bf(params[layer_off(l) + k]);
   w[w_off(l) + k] = h;
+  wf[w_off(l) + k] = bf2f(h);
   const int ci = cin_of(l), co = cout_of(l);
   const int d = int(k / (ci * co)), o = int((k / ci) % co), i = int(k % ci);
-  wt[w_off(l) + ((long long)(26 - d) * ci + i) * co + o] = h;
+  const long long kt = w_off(l) + ((long long)(26 - d) * ci + i) * co + o;
+  wt[kt] = h;
+  wtf[kt] = bf2f(h);
 }
 
 struct LossArgs {
@@ -409,6 +551,43 @@ __global__ void adam_kernel(float* p, float* m, float* v, const float* g, long l
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Mass projection of a prediction: partial[b] = sum over the block's voxels of (out - c).
+constexpr int MP_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void increment_sum(const float* out, const float* c, long long n,
+                                                     double* partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    s += double(out[i]) - double(c[i]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out -= (sum of partials) / n, the partial sums added in a fixed order by every block.
+__global__ __launch_bounds__(256) void remove_mean(float* out, long long n, const double* partial,
+                                                   int nparts) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) s += partial[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const float shift = float(red[0] / double(n));
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    out[i] -= shift;
+}
+
 __global__ void zero_f32(float* p, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
@@ -438,6 +617,8 @@ struct evx_net {
   int device = 0;
   bf16_t* w = nullptr;   // [sum layer_w] bf16
   bf16_t* wt = nullptr;  // flipped/transposed copies
+  float* wf = nullptr;   // BF16-rounded weights as FP32 (VALU layers)
+  float* wtf = nullptr;
   float* params = nullptr;  // device copy of the master weights last set (biases are read here)
   bool have_params = false;
 };
@@ -446,18 +627,22 @@ namespace {
 
 enum : int { K_MFMA = 0, K_IN1 = 1, K_OUT1 = 2, K_BWD_F32 = 3 };
 
+long long g_num_cus = 256;  // set from the device at evx_surrogate_create
+
 hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
-  const long long V = (long long)a.nx * a.ny * a.nz;
-  const unsigned small_grid = unsigned((V + SMALL_THREADS - 1) / SMALL_THREADS);
+  const long long nt = (long long)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY) *
+                       ((a.nz + TZ - 1) / TZ);
+  const unsigned small_grid = unsigned(nt);
   if (kind == K_MFMA) {
-    const long long nt = (long long)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY) *
-                         ((a.nz + TZ - 1) / TZ);
+    // one persistent block per CU (the LDS tile and weights take 124 KB)
+    const unsigned grid = unsigned(nt < g_num_cus ? nt : g_num_cus);
+    const int ntiles = int(nt);
     if (epi == EPI_GELU_Z)
-      hipLaunchKernelGGL(conv32_mfma<EPI_GELU_Z>, dim3(unsigned(nt)), dim3(MFMA_THREADS), 0, s, a);
+      hipLaunchKernelGGL(conv32_mfma<EPI_GELU_Z>, dim3(grid), dim3(MFMA_THREADS), 0, s, a, ntiles);
     else if (epi == EPI_GELU)
-      hipLaunchKernelGGL(conv32_mfma<EPI_GELU>, dim3(unsigned(nt)), dim3(MFMA_THREADS), 0, s, a);
+      hipLaunchKernelGGL(conv32_mfma<EPI_GELU>, dim3(grid), dim3(MFMA_THREADS), 0, s, a, ntiles);
     else
-      hipLaunchKernelGGL(conv32_mfma<EPI_DGELU>, dim3(unsigned(nt)), dim3(MFMA_THREADS), 0, s, a);
+      hipLaunchKernelGGL(conv32_mfma<EPI_DGELU>, dim3(grid), dim3(MFMA_THREADS), 0, s, a, ntiles);
   } else if (kind == K_IN1) {
     if (epi == EPI_GELU_Z)
       hipLaunchKernelGGL((conv_small<1, CH, false, EPI_GELU_Z>), dim3(small_grid),
@@ -497,8 +682,10 @@ bool grid_ok(int nx, int ny, int nz) {
   return nx >= 1 && ny >= 1 && nz >= 1 && (long long)nx * ny * nz * CH < (1LL << 40);
 }
 
-// Inference workspace: X0 (bf16 [V]) | A (bf16 [V][32]) | B (bf16 [V][32]).
-size_t infer_bytes(long long V) { return a256(V * 2) + 2 * a256(V * CH * 2); }
+// Inference workspace: X0 (bf16 [V]) | A (bf16 [V][32]) | B (bf16 [V][32]) | mass partials.
+size_t infer_bytes(long long V) {
+  return a256(V * 2) + 2 * a256(V * CH * 2) + a256(MP_BLOCKS * sizeof(double));
+}
 
 // Training workspace for one n^3 window: X0 | Z1 A1 Z2 A2 Z3 A3 | dZ3 dZ2 dZ1 (bf16 [V][32]) | out dY
 // (f32 [V]) | target (f32 [V]) | wgrad partials | grads (f32 NPARAM) | loss partials.
@@ -537,6 +724,7 @@ ConvArgs conv_args(const evx_net* n, int layer, bool transposed, const void* in,
   ConvArgs a{};
   a.in = in;
   a.w = (transposed ? n->wt : n->w) + w_off(layer);
+  a.wf = (transposed ? n->wtf : n->wf) + w_off(layer);
   a.bias = n->params + layer_off(layer) + layer_w(layer);
   a.nx = nx;
   a.ny = ny;
@@ -564,14 +752,22 @@ evx_status evx_surrogate_create(evx_net** out) {
   if (!out) return nfail(EVX_ERR_ARG, "out is NULL");
   evx_net* n = new evx_net();
   hipError_t e = hipGetDevice(&n->device);
+  int cus = 0;
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, n->device);
+  if (e == hipSuccess && cus > 0) g_num_cus = cus;
   const size_t wb = a256(size_t(w_off(NLAYER)) * sizeof(bf16_t));
-  if (e == hipSuccess) e = hipMalloc(&n->w, 2 * wb + a256(NPARAM * sizeof(float)));
+  const size_t wfb = a256(size_t(w_off(NLAYER)) * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&n->w, 2 * wb + 2 * wfb + a256(NPARAM * sizeof(float)));
   if (e != hipSuccess) {
     delete n;
     return nfail(EVX_ERR_HIP, "evx_surrogate_create: %s", hipGetErrorString(e));
   }
-  n->wt = reinterpret_cast<bf16_t*>(reinterpret_cast<char*>(n->w) + wb);
-  n->params = reinterpret_cast<float*>(reinterpret_cast<char*>(n->w) + 2 * wb);
+  char* base = reinterpret_cast<char*>(n->w);
+  n->wt = reinterpret_cast<bf16_t*>(base + wb);
+  n->wf = reinterpret_cast<float*>(base + 2 * wb);
+  n->wtf = reinterpret_cast<float*>(base + 2 * wb + wfb);
+  n->params = reinterpret_cast<float*>(base + 2 * wb + 2 * wfb);
   *out = n;
   return EVX_OK;
 }
@@ -591,7 +787,7 @@ evx_status evx_surrogate_set_params(evx_net* n, const float* params, void* strea
   if (e != hipSuccess) return nfail(EVX_ERR_HIP, "set_params copy: %s", hipGetErrorString(e));
   const long long nw = layer_w(1);  // the largest layer bounds the per-layer index range
   hipLaunchKernelGGL(refresh_weights, dim3(unsigned((nw + 255) / 256), NLAYER), dim3(256), 0, s,
-                     n->params, n->w, n->wt);
+                     n->params, n->w, n->wt, n->wf, n->wtf);
   e = hipGetLastError();
   if (e != hipSuccess) return nfail(EVX_ERR_HIP, "set_params: %s", hipGetErrorString(e));
   n->have_params = true;
@@ -607,7 +803,7 @@ evx_status evx_surrogate_workspace_bytes(int nx, int ny, int nz, int train, size
 }
 
 evx_status evx_surrogate_infer(evx_net* n, const float* c_in, float* c_out, int nx, int ny,
-                               int nz, void* ws, size_t ws_bytes, void* stream) {
+                               int nz, int flags, void* ws, size_t ws_bytes, void* stream) {
   if (!n || !c_in || !c_out || !ws) return nfail(EVX_ERR_ARG, "NULL argument");
   if (!n->have_params) return nfail(EVX_ERR_STATE, "parameters not set");
   if (!grid_ok(nx, ny, nz)) return nfail(EVX_ERR_SIZE, "grid %d x %d x %d", nx, ny, nz);
@@ -634,6 +830,14 @@ evx_status evx_surrogate_infer(evx_net* n, const float* c_in, float* c_out, int 
   a.c = c_in;
   a.out = c_out;
   NET_TRY(launch_conv(K_OUT1, EPI_RESID, a, s));
+  if (flags & EVX_SURROGATE_CONSERVE_MASS) {
+    double* partial = reinterpret_cast<double*>(p + a256(V * 2) + 2 * a256(V * CH * 2));
+    hipLaunchKernelGGL(increment_sum, dim3(MP_BLOCKS), dim3(256), 0, s, c_out, c_in, V, partial);
+    NET_TRY(hipGetLastError());
+    hipLaunchKernelGGL(remove_mean, dim3(MP_BLOCKS), dim3(256), 0, s, c_out, V, partial,
+                       MP_BLOCKS);
+    NET_TRY(hipGetLastError());
+  }
   return EVX_OK;
 }
 

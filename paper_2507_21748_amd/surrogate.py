@@ -27,8 +27,8 @@ _NET_PROTOS = {
     "evx_surrogate_workspace_bytes": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_size_t)],
     "evx_surrogate_infer": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
-                            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
-                            ctypes.c_void_p],
+                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_size_t, ctypes.c_void_p],
     "evx_surrogate_train_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_void_p,
@@ -118,14 +118,17 @@ class Net:
     def release_workspaces(self):
         self._ws.clear()
 
-    def infer(self, c: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
-        """out <- c + net(c) on the periodic grid of c (nz, ny, nx)."""
+    def infer(self, c: torch.Tensor, out: torch.Tensor = None,
+              conserve_mass: bool = False) -> torch.Tensor:
+        """out <- c + net(c) on the periodic grid of c (nz, ny, nx); with conserve_mass the
+        increment's mean is removed."""
         nz, ny, nx = c.shape
         out = torch.empty_like(c) if out is None else out
         ws = self._workspace(c.shape, False)
         evx._check(evx._LIB.evx_surrogate_infer(
-            self._h, evx._dev_ptr(c), evx._dev_ptr(out, numel=c.numel()), nx, ny, nz, ws.ptr,
-            ws.nbytes, evx._stream_handle()), "evx_surrogate_infer")
+            self._h, evx._dev_ptr(c), evx._dev_ptr(out, numel=c.numel()), nx, ny, nz,
+            int(bool(conserve_mass)), ws.ptr, ws.nbytes, evx._stream_handle()),
+            "evx_surrogate_infer")
         return out
 
     def train_step(self, x: torch.Tensor, y: torch.Tensor, halo: int, lr: float) -> torch.Tensor:
@@ -207,6 +210,7 @@ class RolloutConfig:
     mass_tol: float = 1e-5       # |mean(c_new) - mean(c)| allowed per application
     energy_rtol: float = 1e-6    # E(c_new) <= E(c) (1 + energy_rtol)
     spot_tol: float = 2e-3       # relative L2 to the solver's 10 steps on a spot check
+    conserve_mass: bool = True   # remove the mean of every predicted increment
 
 
 @dataclass
@@ -241,7 +245,7 @@ def rollout(net: Net, c0: torch.Tensor, napps: int, params: "evx.CHParams",
     d_cur = plan.diagnostics(c, params).cpu().numpy()
     for k in range(napps):
         st.applications += 1
-        net.infer(c, cand)
+        net.infer(c, cand, conserve_mass=cfg.conserve_mass)
         d_new = plan.diagnostics(cand, params, out=diag).cpu().numpy()
         ok = True
         if abs(d_new[0] - d_cur[0]) / V > cfg.mass_tol:

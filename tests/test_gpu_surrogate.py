@@ -157,3 +157,17 @@ def test_training_on_solver_pairs_reduces_loss(evx_gpu):
         last = L
     print(f"surrogate training loss {first:.3e} -> {last:.3e}")
     assert last < 0.5 * first
+
+
+def test_mass_projection(evx_gpu):
+    """With mass conservation on, the prediction's mean equals the input's (FP64 sum check) and
+    the increment differs from the plain one by a constant."""
+    from paper_2507_21748_amd.surrogate import Net
+    net = Net(_params(6))
+    c = torch.from_numpy(quench_field((32, 40, 48), 0.2, 0.3, seed=25)).cuda()
+    plain = net.infer(c)
+    cons = net.infer(c, conserve_mass=True)
+    torch.cuda.synchronize()
+    d = (cons.double() - plain.double())
+    assert abs(float(cons.double().mean() - c.double().mean())) <= 1e-7
+    assert float(d.max() - d.min()) <= 1e-6

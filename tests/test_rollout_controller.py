@@ -38,7 +38,7 @@ class MockNet:
     def __init__(self, plan, kind):
         self.plan, self.kind = plan, kind
 
-    def infer(self, c, out):
+    def infer(self, c, out, conserve_mass=False):
         exact = c.clone()
         self.plan.step(exact, 10, evx.CHParams(dt=0.5))
         if self.kind == "exact":
@@ -57,7 +57,7 @@ def _run(kind, napps=6):
     shape = (12, 12, 12)
     plan = FakePlan(shape)
     c0 = torch.from_numpy(quench_field(shape, 0.0, 0.05, seed=1))
-    cfg = RolloutConfig(check_every=2)
+    cfg = RolloutConfig(check_every=2, conserve_mass=False)
     c, st = rollout(MockNet(plan, kind), c0, napps, evx.CHParams(dt=0.5), cfg, plan=plan)
     ref = c0.clone()
     plan.step(ref, 10 * napps, evx.CHParams(dt=0.5))
