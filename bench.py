@@ -10,6 +10,10 @@ seed 3, dt 0.5, spectral wavenumbers).  The line also carries:
   extra        - the 256^3 off-critical quench (periodic spectral and zero-flux stencil).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+       python bench.py --summarize-profile DIR [--workload NAME]
+The second form turns the three rocprofv3 runs listed in PROFILE_COMMANDS (kernel trace, then
+FETCH_SIZE, then WRITE_SIZE, each writing under DIR) into profiles/kernels_<workload>.md and
+profiles/traffic_<workload>.json.
 """
 from __future__ import annotations
 
@@ -50,6 +54,103 @@ def measured_traffic(workload: str, kernel: str):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["bytes_per_launch"]
+
+
+# The rocprofv3 runs summarized by --summarize-profile (run from /tmp with TMPDIR=/tmp; {d} is
+# the output directory, {w} the workload).  Counters are taken in runs of their own.
+PROFILE_COMMANDS = [
+    ("kt", "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv -d {d}/kt -o kt "
+           "-- python3 {root}/bench.py --workload {w} --steps 20 --warmup 2 --no-cpu-baseline "
+           "--no-extra"),
+    ("fs", "timeout -s KILL 240 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/fs -o fs "
+           "-- python3 {root}/bench.py --workload {w} --steps 4 --warmup 1 --no-cpu-baseline "
+           "--no-extra"),
+    ("ws", "timeout -s KILL 240 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/ws -o ws "
+           "-- python3 {root}/bench.py --workload {w} --steps 4 --warmup 1 --no-cpu-baseline "
+           "--no-extra"),
+]
+
+
+def _pass_of_kernel(name: str):
+    """Pass of a stepper kernel from its template arguments (col_kernel<N, BC, MODE>: MODE 0 forward
+    y, 1 inverse y, 3 fused z update; row_kernel<NH, BC, MODE>: MODE 0 fused x with f')."""
+    import re
+    m = re.search(r"evx::(col|row)_kernel<(\d+), (\d+), (\d+)>", name)
+    if not m:
+        return None
+    kind, mode = m.group(1), int(m.group(4))
+    if kind == "col":
+        return {0: "y_forward", 1: "y_inverse", 3: "z_fused_update"}.get(mode)
+    return "x_fused_fprime" if mode == 0 else None
+
+
+def summarize_profile(d: str, workload: str):
+    """Kernel-trace statistics and calibrated HBM traffic per pass from the rocprofv3 CSVs."""
+    import csv
+    import glob
+    from paper_2507_21748_amd.inputs import WORKLOADS
+    w = WORKLOADS[workload]
+    nbytes = dict(zip(PASS_NAMES, pass_bytes(w.shape, w.bc)))
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(d, "kt", "*kernel_stats.csv"))[0])))
+
+    def counters(sub):
+        rows = csv.DictReader(open(glob.glob(os.path.join(d, sub, "*counter_collection.csv"))[0]))
+        per = {}
+        for r in rows:
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return per
+
+    fetch, write = counters("fs"), counters("ws")
+    # calibration: the probe's device-to-device copy of a known size (copy_probe, 2 GiB each way)
+    copy = [k for k in fetch if "copyBuffer" in k][0]
+    known = float(2 << 30)
+    big_f = [v for v in fetch[copy] if v > known / 8]
+    big_w = [v for v in write[copy] if v > known / 8]
+    f_scale = known / (sum(big_f) / len(big_f))
+    w_scale = known / (sum(big_w) / len(big_w))
+    by_pass = {}
+    for name in fetch:
+        p = _pass_of_kernel(name)
+        if p is None:
+            continue
+        f = sum(fetch[name]) / len(fetch[name]) * f_scale
+        wr = sum(write[name]) / len(write[name]) * w_scale
+        by_pass[p] = {"kernel": name, "fetch_bytes": f, "write_bytes": wr,
+                      "bytes_per_launch": f + wr,
+                      "algorithmic_bytes": nbytes[p], "ratio": (f + wr) / nbytes[p]}
+    cmds = [c.format(d=d, w=workload, root="$GRAFT_REPO_ROOT") for _, c in PROFILE_COMMANDS]
+    src = kernel_source_hash()
+    rec = {"workload": workload, "source_hash": src, "fetch_scale": f_scale,
+           "write_scale": w_scale, "commands": cmds, "kernels": by_pass}
+    os.makedirs(PROFILES, exist_ok=True)
+    json.dump(rec, open(os.path.join(PROFILES, f"traffic_{workload}.json"), "w"), indent=1)
+    lines = [f"# rocprofv3 summary: {workload}", "",
+             f"Grid {'x'.join(map(str, w.shape[::-1]))}, {w.bc}, {w.scheme}; kernel source "
+             f"hash {src}.", "", "Commands (from /tmp, TMPDIR=/tmp), then "
+             f"`python bench.py --summarize-profile {d} --workload {workload}`:", ""]
+    lines += [f"    {c}" for c in cmds]
+    lines += ["", "## Kernel trace (--stats)", "",
+              "| kernel | pass | calls | avg ms | % time | algorithmic GB/s |",
+              "|---|---|---|---|---|---|"]
+    for r in stats[:12]:
+        p = _pass_of_kernel(r["Name"])
+        avg = float(r["AverageNs"]) * 1e-6
+        gbs = f"{nbytes[p] / (avg * 1e-3) / 1e9:.0f}" if p else ""
+        lines.append(f"| `{r['Name'][:70]}` | {p or ''} | {r['Calls']} | {avg:.4f} | "
+                     f"{r['Percentage']} | {gbs} |")
+    lines += ["", "## HBM traffic per launch (FETCH_SIZE, WRITE_SIZE)", "",
+              f"Calibration on a 2 GiB device copy: FETCH_SIZE x {f_scale:.4f}, "
+              f"WRITE_SIZE x {w_scale:.4f}.", "",
+              "| pass | read GB | written GB | total GB | algorithmic GB | ratio |",
+              "|---|---|---|---|---|---|"]
+    for p in PASS_NAMES:
+        if p in by_pass:
+            b = by_pass[p]
+            lines.append(f"| {p} | {b['fetch_bytes'] / 1e9:.3f} | {b['write_bytes'] / 1e9:.3f} | "
+                         f"{b['bytes_per_launch'] / 1e9:.3f} | {b['algorithmic_bytes'] / 1e9:.3f}"
+                         f" | {b['ratio']:.3f} |")
+    open(os.path.join(PROFILES, f"kernels_{workload}.md"), "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def copy_probe(torch, gib: float, reps: int = 3):
@@ -152,7 +253,12 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-probe-gib", type=float, default=2.0,
                     help="size of the calibration copy run before the workload (0 = skip)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="summarize the rocprofv3 runs of PROFILE_COMMANDS found under DIR")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the spectral stepper here runs on a single device "
               f"(--gpus {args.gpus} is not supported; multi-GPU sharding is design-only)",

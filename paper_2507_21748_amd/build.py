@@ -51,26 +51,29 @@ def _run(cmd):
     return cmd[-1]
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, lib: str = LIB,
+          defines: tuple = (), build_dir: str = BUILD) -> str:
+    """Compile every object and link `lib`; `defines` are extra -D options for all objects."""
+    os.makedirs(build_dir, exist_ok=True)
     cc = hipcc()
+    flags = HIPFLAGS + [f"-D{d}" for d in defines]
     jobs = jobs or min(16, os.cpu_count() or 4)
     cmds = []
     for n in transform_lengths():
-        obj = os.path.join(BUILD, f"evx_k{n}.o")
-        cmds.append([cc, *HIPFLAGS, f"-DEVX_INST_N={n}", "-c",
+        obj = os.path.join(build_dir, f"evx_k{n}.o")
+        cmds.append([cc, *flags, f"-DEVX_INST_N={n}", "-c",
                      os.path.join(CSRC, "evx_kernels.hip"), "-o", obj])
     for src in ("evx_api.hip", "evx_aux.hip", "evx_net.hip"):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmds.append([cc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+        cmds.append([cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_run, cmds))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":

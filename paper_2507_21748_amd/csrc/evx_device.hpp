@@ -40,12 +40,14 @@ namespace evx {
 
 EVX_HD float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 EVX_HD float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Explicit fused multiply-adds (the library is built without automatic contraction, so every
+// kernel evaluates a complex product with the same roundings).
 EVX_HD float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 // a * conj(b)
 EVX_HD float2 cmulc(float2 a, float2 b) {
-  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return make_float2(__builtin_fmaf(a.x, b.x, a.y * b.y), __builtin_fmaf(a.y, b.x, -(a.x * b.y)));
 }
 EVX_HD float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 EVX_HD float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }

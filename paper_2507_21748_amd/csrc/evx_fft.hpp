@@ -97,7 +97,7 @@ EVX_DEV float2 twmul(float2 v) {
     constexpr ct::CS cs = ct::cossin_frac(a, D);
     constexpr float c = float(cs.c);
     constexpr float s = float(DIR * cs.s);
-    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+    return make_float2(__builtin_fmaf(v.x, c, -(v.y * s)), __builtin_fmaf(v.x, s, v.y * c));
   }
 }
 

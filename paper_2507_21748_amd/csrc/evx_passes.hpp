@@ -89,8 +89,36 @@ struct ColCfg {
   static constexpr int TPS = FftPlan<N>::TPS;
   static constexpr int B = seqs_per_block<N>();
   static constexpr int THREADS = B * TPS;
-  static constexpr int LDS = B * N;  // float2 slots
+  static constexpr int TW = B * N;             // twiddle table offset (after the exchange area)
+  static constexpr int K2 = TW + N;             // z update: K2 along the transform axis (floats)
+  static constexpr int LDS = K2 + (N + 1) / 2;  // float2 slots
 };
+
+// A block's copy of a small constant table (COUNT entries) staged in LDS: every lane issues its
+// table loads before the data loads (load) and writes them to LDS after (store), so the table
+// latency overlaps the data latency.  Readers come after a barrier.
+template <int COUNT, int T, class V>
+struct TableStage {
+  static constexpr int IT = (COUNT + T - 1) / T;
+  V r[IT > 0 ? IT : 1];
+  EVX_DEV void load(const V* EVX_RESTRICT src, int tid) {
+    static_for<IT>([&](auto I) {
+      const int i = tid + T * decltype(I)::value;
+      if (i < COUNT) r[I] = src[i];
+    });
+  }
+  EVX_DEV void store(V* dst, int tid) const {
+    static_for<IT>([&](auto I) {
+      const int i = tid + T * decltype(I)::value;
+      if (i < COUNT) dst[i] = r[I];
+    });
+  }
+};
+
+// The N-entry FFT twiddle table; a single-stage transform reads none (its first read is in the
+// second stage, which follows a barrier).
+template <int N, int T>
+using TwStage = TableStage<(FftPlan<N>::S > 1 ? N : 0), T, float2>;
 
 // Zero flux, after a forward FFT of packed columns (a + i b): x holds Z[k], k = t + TPS e.
 // Produces (Da[k], Db[k]) with D[k] = 2 sum_n x_n cos(pi k (2n+1) / 2N) (Makhoul).
@@ -149,6 +177,27 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   }
   const long long base = outer * a.outer_stride + col;
   float2 x[E];
+  float2* const twl = lds + C::TW;
+  TwStage<N, C::THREADS> tws;
+  tws.load(a.tw, tid);
+  // z update: the K2 tables are read before the data so that no table load waits behind the
+  // transforms (the axis table goes to LDS with the twiddles)
+  float* const k2l = reinterpret_cast<float*>(lds + C::K2);
+  TableStage<(MODE == COL_Z_UPDATE ? N : 0), C::THREADS, float> k2s;
+  float kca = 0.f, kcb = 0.f;
+  if constexpr (MODE == COL_Z_UPDATE) {
+    k2s.load(a.k2r, tid);
+    if (live) {
+      const float ko = a.k2o[outer];
+      if constexpr (BC == BC_ZERO_FLUX) {
+        kca = a.k2c[2 * col] + ko;
+        kcb = a.k2c[2 * col + 1] + ko;
+      } else {
+        kca = a.k2c[col] + ko;
+        kcb = kca;
+      }
+    }
+  }
 
   constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE;
   constexpr bool has_inv = MODE != COL_FWD;
@@ -165,9 +214,11 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
       x[e] = live ? a.in[base + (long long)row * a.row_stride] : make_float2(0.f, 0.f);
     });
   }
+  tws.store(twl, tid);
+  k2s.store(k2l, tid);
 
   if constexpr (has_fwd) {
-    fft_regs<N, -1, B>(x, lds, b, t, a.tw);
+    fft_regs<N, -1, B>(x, lds, b, t, twl);
     if constexpr (BC == BC_ZERO_FLUX) makhoul_post<N, B>(x, lds, b, t, a.mk);
   }
 
@@ -195,20 +246,12 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
     // The library is built without FP contraction, so the rounded C' stored in the state is
     // exactly the value the inverse transform consumes, and every kernel that transforms the
     // same data rounds identically (resume from a stored state is bit-exact).
+    evx_sync();  // K2 table visible (a single-stage periodic transform has no barrier of its own)
     if (live) {
-      const float ko = a.k2o[outer];
-      float kca, kcb;
-      if constexpr (BC == BC_ZERO_FLUX) {
-        kca = a.k2c[2 * col] + ko;
-        kcb = a.k2c[2 * col + 1] + ko;
-      } else {
-        kca = a.k2c[col] + ko;
-        kcb = kca;
-      }
       static_for<E>([&](auto e) {
         const int k = t + TPS * decltype(e)::value;
         const long long idx = base + (long long)k * a.row_stride;
-        const float kr = a.k2r[k];
+        const float kr = k2l[k];
         const float2 Cs = a.state[idx];
         const float2 F = x[e];
         const float K2a = kca + kr, K2b = kcb + kr;
@@ -227,7 +270,7 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
 
   if constexpr (has_inv) {
     if constexpr (BC == BC_ZERO_FLUX) makhoul_pre<N, B>(x, lds, b, t, a.mk);
-    fft_regs<N, +1, B>(x, lds, b, t, a.tw);
+    fft_regs<N, +1, B>(x, lds, b, t, twl);
     if (live) {
       static_for<E>([&](auto e) {
         const int n = t + TPS * decltype(e)::value;
@@ -275,8 +318,22 @@ struct RowCfg {
   static constexpr int THREADS = B * TPS;
   static constexpr int ROWS = (BC == BC_PERIODIC) ? B : 2 * B;  // rows per block
   static constexpr int STAGE = (BC == BC_PERIODIC) ? B * (NH + 1) : B * NH;  // float2 slots
-  static constexpr int LDS = STAGE > B * NH ? STAGE : B * NH;
+  static constexpr int TW = STAGE > B * NH ? STAGE : B * NH;  // twiddle table offset
+  static constexpr int PO = TW + NH;                            // post table offset
+  // post table entries: periodic keeps k <= NH/2 (the rest follows from
+  // exp(-2 pi i (NH - k) / nx) = -conj(exp(-2 pi i k / nx))); zero flux keeps all NH
+  static constexpr int NPOST = (BC == BC_PERIODIC) ? NH / 2 + 1 : NH;
+  static constexpr int LDS = PO + NPOST;
 };
+
+// Periodic post-processing twiddle exp(-2 pi i k / nx), nx = 2 NH, 0 <= k < NH, from the half
+// table held in LDS.
+template <int NH>
+EVX_DEV float2 post_tw(const float2* po, int k) {
+  if (k <= NH / 2) return po[k];
+  const float2 w = po[NH - k];
+  return make_float2(-w.x, w.y);
+}
 
 template <int NH, int BC, int MODE>
 EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
@@ -286,6 +343,12 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
   const int t = tid / B;
   const long long r0 = (long long)bid * C::ROWS;
   float2 x[E];
+  float2* const twl = lds + C::TW;
+  float2* const pol = lds + C::PO;
+  TwStage<NH, T> tws;
+  tws.load(a.tw, tid);
+  TableStage<C::NPOST, T, float2> pos;
+  pos.load(a.post, tid);
 
   if constexpr (BC == BC_PERIODIC) {
     constexpr int NX = 2 * NH, W = NH + 1;
@@ -294,6 +357,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       // real rows, read as pairs (c[2n], c[2n+1]) into stage[b*NH + n]
       copy_in<B * NH, T>(reinterpret_cast<const float2*>(a.in_r) + r0 * NH, (a.nrows - r0) * NH,
                          lds, tid);
+      tws.store(twl, tid);
+      pos.store(pol, tid);
       evx_sync();
       static_for<E>([&](auto e) { x[e] = lds[b * NH + t + TPS * decltype(e)::value]; });
       if constexpr (MODE == ROW_FWD_FP)
@@ -301,6 +366,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       evx_sync();
     } else {
       copy_in<B * W, T>(a.in_c + r0 * W, (a.nrows - r0) * W, lds, tid);
+      tws.store(twl, tid);
+      pos.store(pol, tid);
       evx_sync();
       // C2R pre-processing: Z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) e^{+2pi i k/NX}
       static_for<E>([&](auto e) {
@@ -308,11 +375,11 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         const float2 X = lds[b * W + k];
         const float2 Xr = cconj(lds[b * W + NH - k]);
         const float2 Ev = cadd(X, Xr);
-        const float2 Od = cmulc(csub(X, Xr), a.post[k]);
+        const float2 Od = cmulc(csub(X, Xr), post_tw<NH>(pol, k));
         x[e] = make_float2(Ev.x - Od.y, Ev.y + Od.x);
       });
       evx_sync();
-      fft_regs<NH, +1, B>(x, lds, b, t, a.tw);
+      fft_regs<NH, +1, B>(x, lds, b, t, twl);
       static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
       if constexpr (MODE == ROW_INV) {
         static_for<E>([&](auto e) { lds[b * NH + t + TPS * decltype(e)::value] = x[e]; });
@@ -324,7 +391,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
     }
     // ---------------------------------------------------------------- forward x (R2C)
-    fft_regs<NH, -1, B>(x, lds, b, t, a.tw);
+    fft_regs<NH, -1, B>(x, lds, b, t, twl);
     static_for<E>([&](auto e) { lds[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });
     evx_sync();
     float2 y[E];
@@ -336,7 +403,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       const float2 Ev = cscale(cadd(P, Q), 0.5f);
       const float2 dq = cscale(csub(P, Q), 0.5f);
       const float2 Od = make_float2(dq.y, -dq.x);  // -i (P - Q) / 2
-      y[e] = cadd(Ev, cmul(a.post[k], Od));
+      y[e] = cadd(Ev, cmul(post_tw<NH>(pol, k), Od));
       if (k == 0) ynyq = make_float2(Ev.x - Od.x, 0.f);
     });
     evx_sync();
@@ -354,6 +421,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     // rows are NX floats (NX even) = NX/2 float2; r0 is even
     copy_in<B * NX, T>(reinterpret_cast<const float2*>(in) + r0 * (NX / 2),
                        (a.nrows - r0) * (NX / 2), lds, tid);
+    tws.store(twl, tid);
+    pos.store(pol, tid);
     evx_sync();
     if constexpr (real_in) {
       static_for<E>([&](auto e) {
@@ -370,13 +439,13 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         const float Da = st[(2 * b) * NX + k], Db = st[(2 * b + 1) * NX + k];
         const float Dar = (k == 0) ? 0.f : st[(2 * b) * NX + NX - k];
         const float Dbr = (k == 0) ? 0.f : st[(2 * b + 1) * NX + NX - k];
-        const float2 w = cconj(a.post[k]);
+        const float2 w = cconj(pol[k]);
         const float2 va = cmul(w, make_float2(Da, -Dar));
         const float2 vb = cmul(w, make_float2(Db, -Dbr));
         x[e] = make_float2(va.x - vb.y, va.y + vb.x);
       });
       evx_sync();
-      fft_regs<NX, +1, B>(x, lds, b, t, a.tw);
+      fft_regs<NX, +1, B>(x, lds, b, t, twl);
       static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
       if constexpr (MODE == ROW_INV) {
         static_for<E>([&](auto e) {
@@ -392,7 +461,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
     }
-    fft_regs<NX, -1, B>(x, lds, b, t, a.tw);
+    fft_regs<NX, -1, B>(x, lds, b, t, twl);
     static_for<E>([&](auto e) { lds[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });
     evx_sync();
     float2 y[E];
@@ -400,7 +469,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       const int k = t + TPS * decltype(e)::value;
       const float2 P = x[e];
       const float2 Q = cconj(lds[lidx<B>(k == 0 ? 0 : NX - k, b)]);
-      const float2 w = a.post[k];
+      const float2 w = pol[k];
       const float2 sp = cmul(w, cadd(P, Q));
       const float2 sm = cmul(w, csub(P, Q));
       y[e] = make_float2(sp.x, sm.y);
