@@ -77,8 +77,9 @@ evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, ev
 evx_status evx_plan_destroy(evx_plan* plan);
 
 /* Device bytes the caller must provide for the given EVX_OP_* mask.  EVX_OP_STEP needs two
- * spectral buffers (state S and work W) of nz*ny*(nx/2+1) complex64 (periodic) or nz*ny*nx float
- * (zero flux) each, i.e. about 8 bytes per voxel; EVX_OP_DIAG adds one spectral buffer and 16 KB
+ * spectral buffers (state S and work W) of nz*ny rows of complex64 (periodic: nx/2+1 values per
+ * row, rows padded to a multiple of 8 values) or nz*ny*nx float (zero flux) each, i.e. about 8
+ * bytes per voxel; EVX_OP_DIAG adds one spectral buffer and 16 KB
  * of partial sums; EVX_OP_ADJOINT adds three spectral buffers, one real field and the partial
  * sums (about 24 bytes per voxel in total). */
 evx_status evx_plan_workspace_bytes(const evx_plan* plan, int ops, size_t* bytes);

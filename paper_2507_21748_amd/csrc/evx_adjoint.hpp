@@ -54,6 +54,7 @@ inline SpecArgs spec_args(const Geom& g, const TablePtrs& t, const AdjointBufs& 
   a.nx = g.nx;
   a.ny = g.ny;
   a.nz = g.nz;
+  a.pitch = g.pitch;
   a.ncols = g.ncols;
   a.bc = g.bc;
   a.k2x = t.k2_x;

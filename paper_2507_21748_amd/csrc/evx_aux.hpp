@@ -26,7 +26,7 @@ struct SpecArgs {
   float2* F;        // in: T[f'(c^n)];  out: dt M K2 G Lam   (the B operator's multiplier)
   float2* L;        // in: T[lam^{n+1}]; out: G P Lam        (the A operator's multiplier)
   long long n;      // float2 elements of a spectral buffer
-  int nx, ny, nz, ncols, bc;
+  int nx, ny, nz, pitch, ncols, bc;  // pitch: float2 per row; ncols: of them holding data
   const float *k2x, *k2y, *k2z;
   float a_dt, dt_m_kappa, dt_m, dt, dt_kappa;
   double* partial;  // 2 per block: sum for dL/dkappa, sum for dL/dM (before the 1/V factor)
@@ -60,8 +60,9 @@ EVX_DEV void spec_body(const SpecArgs& a, int tid, int bid, int nblk, double* re
   double s0 = 0.0, s1 = 0.0;
   const long long stride = (long long)nblk * AUX_THREADS;
   for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
-    const long long r = i / a.ncols;
-    const int xc = int(i - r * a.ncols);
+    const long long r = i / a.pitch;
+    const int xc = int(i - r * a.pitch);
+    if (xc >= a.ncols) continue;  // row padding
     const int y = int(r % a.ny);
     const int z = int(r / a.ny);
     const float kyz = a.k2y[y] + a.k2z[z];

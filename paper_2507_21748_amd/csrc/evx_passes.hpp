@@ -1,9 +1,12 @@
 // Pass bodies of the Cahn-Hilliard spectral step.  Each body is the work of one workgroup; it
 // is wrapped by a __global__ kernel for gfx950 and by a threaded host emulator in the CPU tests.
 //
-// Data layout (C order, x fastest).  Periodic: the half spectrum, nz x ny x (nx/2+1) complex.
-// Zero flux: the DCT-II spectrum is real, nz x ny x nx floats, handled as nx/2 float2 "column
-// pairs" by the y and z passes.  Two such buffers exist: S (spectral state) and W (work).
+// Data layout (C order, x fastest).  Periodic: the half spectrum, nz x ny rows of nx/2+1
+// complex values, each row padded to a pitch of spectral_pitch(nx/2) complex values (a multiple
+// of 8, so that every 8-column segment read by the y and z passes is one aligned 64-byte piece;
+// the padding is never read as data).  Zero flux: the DCT-II spectrum is real, nz x ny x nx
+// floats, handled as nx/2 float2 "column pairs" by the y and z passes (pitch nx/2).  Two such
+// buffers exist: S (spectral state) and W (work).
 //
 // One time step is four passes over W (and one over S):
 //   inverse y  ->  x: inverse x, f'(c) = c^3 - c, forward x  ->  forward y  ->
@@ -16,6 +19,9 @@
 namespace evx {
 
 enum : int { BC_PERIODIC = 0, BC_ZERO_FLUX = 1 };
+
+// Row pitch (complex values) of a periodic half spectrum whose rows hold nh + 1 values.
+EVX_HD constexpr int spectral_pitch(int nh) { return ((nh + 1 + 7) / 8) * 8; }
 
 // column (y or z) pass modes
 enum : int {
@@ -39,7 +45,8 @@ struct ColArgs {
   float2* out;
   float2* state;
   long long nseq;          // sequences = ncols * nouter
-  int ncols;               // float2 columns per row of the array
+  int ncols;               // float2 columns per row of the array (the row pitch)
+  int nlive;               // columns holding data (the rest is padding)
   long long row_stride;    // float2 stride between consecutive points of the transform axis
   long long outer_stride;  // float2 stride between consecutive outer indices
   const float2* tw;        // exp(-2 pi i j / N), j < N
@@ -169,12 +176,12 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   const int b = tid % B;
   const int t = tid / B;
   const long long seq = (long long)lb * B + b;
-  const bool live = seq < a.nseq;
   long long outer = 0, col = 0;
-  if (live) {
+  if (seq < a.nseq) {
     outer = seq / a.ncols;
     col = seq - outer * a.ncols;
   }
+  const bool live = seq < a.nseq && col < a.nlive;
   const long long base = outer * a.outer_stride + col;
   float2 x[E];
   float2* const twl = lds + C::TW;
@@ -308,6 +315,48 @@ EVX_DEV void copy_out(float2* EVX_RESTRICT dst, long long valid, const float2* l
   });
 }
 
+// Periodic complex rows: ROWS rows of NLIVE values at global pitch P are staged at LDS row
+// stride S.  T / ROWS consecutive lanes copy one row, so every global access is a contiguous run
+// within a row; the row padding is skipped on the way in and written as zeros on the way out.
+template <int ROWS, int P, int S, int NLIVE, int T>
+EVX_DEV void rows_in(const float2* EVX_RESTRICT src, long long valid_rows, float2* lds, int tid) {
+  static_assert(T % ROWS == 0, "rows must split the block evenly");
+  constexpr int TR = T / ROWS, IT = (NLIVE + TR - 1) / TR;
+  const int row = tid / TR, c0 = tid - row * TR;
+  const bool ok = row < valid_rows;
+  float2 r[IT];
+  static_for<IT>([&](auto I) {
+    const int c = c0 + TR * decltype(I)::value;
+    r[I] = (ok && c < NLIVE) ? src[row * P + c] : make_float2(0.f, 0.f);
+  });
+  static_for<IT>([&](auto I) {
+    const int c = c0 + TR * decltype(I)::value;
+    if (c < NLIVE) lds[row * S + c] = r[I];
+  });
+}
+
+template <int ROWS, int P, int S, int NLIVE, int T>
+EVX_DEV void rows_out(float2* EVX_RESTRICT dst, long long valid_rows, const float2* lds, int tid) {
+  static_assert(T % ROWS == 0, "rows must split the block evenly");
+  constexpr int TR = T / ROWS, IT = (P + TR - 1) / TR;
+  const int row = tid / TR, c0 = tid - row * TR;
+  if (row >= valid_rows) return;
+  static_for<IT>([&](auto I) {
+    const int c = c0 + TR * decltype(I)::value;
+    if (c < P) dst[row * P + c] = (c < NLIVE) ? lds[row * S + c] : make_float2(0.f, 0.f);
+  });
+}
+
+// LDS row stride for B rows read by lanes (t, b) at row b, column t + const: the smallest
+// S >= need with S = q (mod 2q), q = 32 / min(B, 32), so that the 32 lanes of a half wave touch
+// distinct 64-bit bank pairs.
+constexpr int row_lds_stride(int need, int b) {
+  const int q = 32 / (b < 32 ? b : 32);
+  int s = need;
+  while (s % (2 * q) != q % (2 * q)) ++s;
+  return s;
+}
+
 // Periodic: template length NH = nx/2, the complex FFT length of the packed real row; the row
 // has NH+1 complex points.  Zero flux: NH = nx, one sequence carries two rows packed as a + i b.
 template <int NH, int BC>
@@ -317,7 +366,10 @@ struct RowCfg {
   static constexpr int B = seqs_per_block<NH>();       // sequences per block
   static constexpr int THREADS = B * TPS;
   static constexpr int ROWS = (BC == BC_PERIODIC) ? B : 2 * B;  // rows per block
-  static constexpr int STAGE = (BC == BC_PERIODIC) ? B * (NH + 1) : B * NH;  // float2 slots
+  // staged rows: periodic rows at the spectral pitch (padding included), zero flux NH floats
+  static constexpr int PITCH = (BC == BC_PERIODIC) ? spectral_pitch(NH) : NH / 2;
+  static constexpr int SROW = row_lds_stride(NH + 1, B);  // periodic LDS row stride
+  static constexpr int STAGE = (BC == BC_PERIODIC) ? B * SROW : B * NH;  // float2 slots
   static constexpr int TW = STAGE > B * NH ? STAGE : B * NH;  // twiddle table offset
   static constexpr int PO = TW + NH;                            // post table offset
   // post table entries: periodic keeps k <= NH/2 (the rest follows from
@@ -351,7 +403,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
   pos.load(a.post, tid);
 
   if constexpr (BC == BC_PERIODIC) {
-    constexpr int NX = 2 * NH, W = NH + 1;
+    constexpr int NX = 2 * NH, P = C::PITCH, W = C::SROW;
     // ---------------------------------------------------------------- input
     if constexpr (MODE == ROW_FWD || MODE == ROW_FWD_FP) {
       // real rows, read as pairs (c[2n], c[2n+1]) into stage[b*NH + n]
@@ -365,7 +417,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
       evx_sync();
     } else {
-      copy_in<B * W, T>(a.in_c + r0 * W, (a.nrows - r0) * W, lds, tid);
+      rows_in<B, P, W, NH + 1, T>(a.in_c + r0 * P, a.nrows - r0, lds, tid);
       tws.store(twl, tid);
       pos.store(pol, tid);
       evx_sync();
@@ -410,7 +462,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     static_for<E>([&](auto e) { lds[b * W + t + TPS * decltype(e)::value] = y[e]; });
     if (t == 0) lds[b * W + NH] = ynyq;
     evx_sync();
-    copy_out<B * W, T>(a.out_c + r0 * W, (a.nrows - r0) * W, lds, tid);
+    rows_out<B, P, W, NH + 1, T>(a.out_c + r0 * P, a.nrows - r0, lds, tid);
     (void)NX;
   } else {
     // zero flux: rows ra = r0 + 2b, rb = ra + 1, stage as floats [2B][NH]

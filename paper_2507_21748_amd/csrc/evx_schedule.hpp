@@ -36,7 +36,8 @@ struct Geom {
   int scheme = 0;        // 0 spectral, 1 stencil7
   double dx = 1.0;       // grid spacing baked into the K2 tables
   long long V = 0;       // voxels
-  int ncols = 0;         // float2 columns per row of a spectral buffer
+  int ncols = 0;         // float2 columns per row of a spectral buffer holding data
+  int pitch = 0;         // float2 per row of a spectral buffer (ncols rounded up, periodic)
   int row_len = 0;       // x-pass FFT length: nx/2 (periodic) or nx (zero flux)
   long long spec = 0;    // float2 per spectral buffer
   long long nrows = 0;   // ny * nz
@@ -53,7 +54,8 @@ inline Geom make_geom(int nx, int ny, int nz, int bc, int scheme, double dx) {
   g.V = (long long)nx * ny * nz;
   g.ncols = (bc == BC_PERIODIC) ? nx / 2 + 1 : nx / 2;
   g.row_len = (bc == BC_PERIODIC) ? nx / 2 : nx;
-  g.spec = (long long)nz * ny * g.ncols;
+  g.pitch = (bc == BC_PERIODIC) ? spectral_pitch(nx / 2) : nx / 2;
+  g.spec = (long long)nz * ny * g.pitch;
   g.nrows = (long long)ny * nz;
   return g;
 }
@@ -143,10 +145,11 @@ inline ColArgs y_args(const Geom& g, const TablePtrs& t, const float2* in, float
   ColArgs a{};
   a.in = in;
   a.out = out;
-  a.nseq = (long long)g.ncols * g.nz;
-  a.ncols = g.ncols;
-  a.row_stride = g.ncols;
-  a.outer_stride = (long long)g.ncols * g.ny;
+  a.nseq = (long long)g.pitch * g.nz;
+  a.ncols = g.pitch;
+  a.nlive = g.ncols;
+  a.row_stride = g.pitch;
+  a.outer_stride = (long long)g.pitch * g.ny;
   a.tw = t.tw_y;
   a.mk = t.mk_y;
   a.remap = remap;
@@ -159,10 +162,11 @@ inline ColArgs z_args(const Geom& g, const TablePtrs& t, const float2* in, float
   a.in = in;
   a.out = out;
   a.state = state;
-  a.nseq = (long long)g.ncols * g.ny;
-  a.ncols = g.ncols;
-  a.row_stride = (long long)g.ncols * g.ny;
-  a.outer_stride = g.ncols;
+  a.nseq = (long long)g.pitch * g.ny;
+  a.ncols = g.pitch;
+  a.nlive = g.ncols;
+  a.row_stride = (long long)g.pitch * g.ny;
+  a.outer_stride = g.pitch;
   a.tw = t.tw_z;
   a.mk = t.mk_z;
   a.k2c = t.k2_x;
