@@ -9,24 +9,8 @@
 
 namespace evx {
 
-// Waves per SIMD that the LDS footprint allows (4 SIMDs and 160 KiB of LDS per CU, at most 8
-// waves per SIMD); the register budget is capped so that registers do not lower occupancy below it.
-constexpr int occupancy_waves(int threads, int lds_bytes) {
-  const int blocks = (160 * 1024) / lds_bytes;
-  const int waves = blocks * ((threads + 63) / 64);
-  const int per_simd = (waves + 3) / 4;
-  return per_simd < 1 ? 1 : per_simd > 8 ? 8 : per_simd;
-}
-
-#ifdef EVX_OCC
-#define EVX_COL_BOUNDS(N) __launch_bounds__(ColCfg<N>::THREADS, \
-    (occupancy_waves(ColCfg<N>::THREADS, ColCfg<N>::LDS * 8)))
-#else
-#define EVX_COL_BOUNDS(N) __launch_bounds__(ColCfg<N>::THREADS)
-#endif
-
 template <int N, int BC, int MODE>
-__global__ EVX_COL_BOUNDS(N) void col_kernel(ColArgs a) {
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void col_kernel(ColArgs a) {
   __shared__ float2 lds[ColCfg<N>::LDS];
   colpass_body<N, BC, MODE>(a, threadIdx.x, blockIdx.x, gridDim.x, lds);
 }
@@ -47,7 +31,12 @@ static hipError_t col_go(const ColArgs& a, hipStream_t s) {
   using C = ColCfg<N>;
   const long long nblk = (a.nseq + C::B - 1) / C::B;
   if (nblk <= 0) return hipSuccess;
-  if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  // ColTile works with 32-bit sequence numbers and 32-bit lane byte offsets
+  const long long qmax = (a.ncols - 1 + C::B - 1) / a.ncols;
+  const long long lane_span =
+      (qmax * a.outer_stride + a.ncols + (long long)(C::TPS - 1) * a.row_stride) * 8;
+  if (nblk > 0x7fffffffLL || a.nseq > 0x7fffffffLL || lane_span > 0xffffffffLL)
+    return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((col_kernel<N, BC, MODE>), dim3(unsigned(nblk)), dim3(C::THREADS), 0, s, a);
   return hipGetLastError();
 }

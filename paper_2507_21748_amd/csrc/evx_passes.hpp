@@ -168,61 +168,96 @@ EVX_DEV void makhoul_pre(float2 (&x)[FftPlan<N>::E], float2* lds, int b, int t,
   evx_sync();
 }
 
+// Addressing of one block's B sequences.  Point n of a lane's sequence sits at a uniform
+// (scalar) base for the block and n's multiple of TPS, plus a 32-bit lane byte offset, so all of a
+// lane's accesses share one offset register.  The block's first sequence is always a live column
+// (blocks start at multiples of B, the pitch is a multiple of 8 and exceeds the last live column by
+// less than 8), so a lane without data reads that column's points and discards the result: loads
+// need no branch.  The launcher guarantees that sequence numbers fit in 31 bits and lane offsets
+// in 32 bits.
+template <int B>
+struct ColTile {
+  long long tb = 0;  // float2 offset of the block's first sequence (uniform)
+  unsigned lo = 0;   // lane byte offset of point 0 relative to tb
+  int outer = 0, col = 0;
+  bool live = false;
+  EVX_DEV void locate(const ColArgs& a, long long tile, int b, int t) {
+    const unsigned ncols = unsigned(a.ncols);
+    const unsigned s0 = unsigned(tile) * unsigned(B);
+    const unsigned o0 = s0 / ncols, c0 = s0 - o0 * ncols;
+    tb = (long long)o0 * a.outer_stride + c0;
+    const unsigned d = c0 + unsigned(b);
+    const unsigned q = d / ncols;
+    outer = int(o0 + q);
+    col = int(d - q * ncols);
+    live = (long long)s0 + b < a.nseq && col < a.nlive;
+    const long long off = (long long)q * a.outer_stride + (col - (long long)c0) +
+                          (long long)t * a.row_stride;
+    lo = live ? unsigned(off * 8) : 0u;
+  }
+  // point t + TPS e, shifted by `rows` transform-axis rows (zero-flux reordering)
+  template <int TPS, class P>
+  EVX_DEV P* at(P* base, long long row_stride, int e, long long rows = 0) const {
+    P* pe = base + tb + (long long)(TPS * e) * row_stride;
+    return reinterpret_cast<P*>(reinterpret_cast<unsigned char*>(const_cast<float2*>(pe)) + lo +
+                                rows * row_stride * 8);
+  }
+};
+
 template <int N, int BC, int MODE>
 EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* lds) {
   using C = ColCfg<N>;
   constexpr int E = C::E, TPS = C::TPS, B = C::B;
-  const int lb = remap_block(bid, nblk, a.remap);
+  constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE;
+  constexpr bool has_inv = MODE != COL_FWD;
+  constexpr bool upd = MODE == COL_Z_UPDATE;
   const int b = tid % B;
   const int t = tid / B;
-  const long long seq = (long long)lb * B + b;
-  long long outer = 0, col = 0;
-  if (seq < a.nseq) {
-    outer = seq / a.ncols;
-    col = seq - outer * a.ncols;
-  }
-  const bool live = seq < a.nseq && col < a.nlive;
-  const long long base = outer * a.outer_stride + col;
-  float2 x[E];
+  ColTile<B> ct;
+  ct.locate(a, remap_block(bid, nblk, a.remap), b, t);
+  // Makhoul reordering of zero-flux inputs and outputs: point n <-> row makhoul_src(n)
+  auto mrow = [&](int e) -> long long {
+    const int n = t + TPS * e;
+    return ct.live ? (long long)(makhoul_src<N>(n) - n) : 0;
+  };
+
+  // Tables first (they go to LDS after the data loads), then the data and for the update the
+  // column K2, all in flight together.
   float2* const twl = lds + C::TW;
   TwStage<N, C::THREADS> tws;
   tws.load(a.tw, tid);
-  // z update: the K2 tables are read before the data so that no table load waits behind the
-  // transforms (the axis table goes to LDS with the twiddles)
   float* const k2l = reinterpret_cast<float*>(lds + C::K2);
-  TableStage<(MODE == COL_Z_UPDATE ? N : 0), C::THREADS, float> k2s;
-  float kca = 0.f, kcb = 0.f;
-  if constexpr (MODE == COL_Z_UPDATE) {
-    k2s.load(a.k2r, tid);
-    if (live) {
-      const float ko = a.k2o[outer];
-      if constexpr (BC == BC_ZERO_FLUX) {
-        kca = a.k2c[2 * col] + ko;
-        kcb = a.k2c[2 * col + 1] + ko;
-      } else {
-        kca = a.k2c[col] + ko;
-        kcb = kca;
-      }
-    }
-  }
+  TableStage<(upd ? N : 0), C::THREADS, float> k2s;
+  if constexpr (upd) k2s.load(a.k2r, tid);
 
-  constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE;
-  constexpr bool has_inv = MODE != COL_FWD;
-
+  float2 x[E];
   if constexpr (MODE == COL_Z_INV_STATE) {
-    static_for<E>([&](auto e) {
-      const int n = t + TPS * decltype(e)::value;
-      x[e] = live ? a.state[base + (long long)n * a.row_stride] : make_float2(0.f, 0.f);
-    });
+    static_for<E>([&](auto e) { x[e] = *ct.template at<TPS>(a.state, a.row_stride, e); });
   } else {
     static_for<E>([&](auto e) {
-      const int n = t + TPS * decltype(e)::value;
-      const int row = (BC == BC_ZERO_FLUX && has_fwd) ? makhoul_src<N>(n) : n;
-      x[e] = live ? a.in[base + (long long)row * a.row_stride] : make_float2(0.f, 0.f);
+      constexpr bool reorder = BC == BC_ZERO_FLUX && has_fwd;
+      x[e] = *ct.template at<TPS>(a.in, a.row_stride, e, reorder ? mrow(e) : 0);
     });
+  }
+  float2 cs[upd ? E : 1];
+  float kca = 0.f, kcb = 0.f;
+  if constexpr (upd) {
+    const int o = ct.live ? ct.outer : 0, cc = ct.live ? ct.col : 0;
+    const float ko = a.k2o[o];
+    if constexpr (BC == BC_ZERO_FLUX) {
+      kca = a.k2c[2 * cc] + ko;
+      kcb = a.k2c[2 * cc + 1] + ko;
+    } else {
+      kca = a.k2c[cc] + ko;
+      kcb = kca;
+    }
   }
   tws.store(twl, tid);
   k2s.store(k2l, tid);
+  // Every load of the block (a lane without data reads a live column) precedes every store,
+  // since the passes work in place; the transforms' barriers order them, except for a
+  // single-stage periodic transform, which has none.
+  if constexpr (FftPlan<N>::S == 1 && BC == BC_PERIODIC) evx_sync();
 
   if constexpr (has_fwd) {
     fft_regs<N, -1, B>(x, lds, b, t, twl);
@@ -230,59 +265,53 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   }
 
   if constexpr (MODE == COL_FWD) {
-    if (live) {
-      static_for<E>([&](auto e) {
-        const int k = t + TPS * decltype(e)::value;
-        a.out[base + (long long)k * a.row_stride] = x[e];
-      });
+    if (ct.live) {
+      static_for<E>([&](auto e) { *ct.template at<TPS>(a.out, a.row_stride, e) = x[e]; });
     }
     return;
   }
 
   if constexpr (MODE == COL_Z_INIT) {
-    if (live) {
-      static_for<E>([&](auto e) {
-        const int k = t + TPS * decltype(e)::value;
-        a.state[base + (long long)k * a.row_stride] = x[e];
-      });
+    if (ct.live) {
+      static_for<E>([&](auto e) { *ct.template at<TPS>(a.state, a.row_stride, e) = x[e]; });
     }
   }
 
-  if constexpr (MODE == COL_Z_UPDATE) {
+  if constexpr (upd) {
     // C' = G (P C - dt M K2 F), P = 1 + A dt K2, G = 1 / (1 + dt M kappa K2^2 + A dt K2).
     // The library is built without FP contraction, so the rounded C' stored in the state is
     // exactly the value the inverse transform consumes, and every kernel that transforms the
     // same data rounds identically (resume from a stored state is bit-exact).
     evx_sync();  // K2 table visible (a single-stage periodic transform has no barrier of its own)
-    if (live) {
-      static_for<E>([&](auto e) {
-        const int k = t + TPS * decltype(e)::value;
-        const long long idx = base + (long long)k * a.row_stride;
-        const float kr = k2l[k];
-        const float2 Cs = a.state[idx];
-        const float2 F = x[e];
-        const float K2a = kca + kr, K2b = kcb + kr;
-        const float Pa = 1.0f + a.a_dt * K2a, Pb = 1.0f + a.a_dt * K2b;
-        const float Ga = evx_rcp(1.0f + a.dt_m_kappa * K2a * K2a + a.a_dt * K2a);
-        const float Gb = evx_rcp(1.0f + a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
-        const float2 nv = make_float2(Ga * (Pa * Cs.x - a.dt_m * K2a * F.x),
-                                      Gb * (Pb * Cs.y - a.dt_m * K2b * F.y));
-        a.state[idx] = nv;
-        x[e] = nv;
-      });
-    } else {
-      static_for<E>([&](auto e) { x[e] = make_float2(0.f, 0.f); });
+    // The state is read only now: loading it with the data would hold 32 more registers
+    // through the forward transform and cost a block per compute unit.
+    static_for<E>([&](auto e) { cs[e] = *ct.template at<TPS>(a.state, a.row_stride, e); });
+    static_for<E>([&](auto e) {
+      const int k = t + TPS * decltype(e)::value;
+      const float kr = k2l[k];
+      const float2 Cs = cs[e];
+      const float2 F = x[e];
+      const float K2a = kca + kr, K2b = kcb + kr;
+      const float Pa = 1.0f + a.a_dt * K2a, Pb = 1.0f + a.a_dt * K2b;
+      const float Ga = evx_rcp(1.0f + a.dt_m_kappa * K2a * K2a + a.a_dt * K2a);
+      const float Gb = evx_rcp(1.0f + a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
+      x[e] = make_float2(Ga * (Pa * Cs.x - a.dt_m * K2a * F.x),
+                         Gb * (Pb * Cs.y - a.dt_m * K2b * F.y));
+    });
+    // lanes without data read a live column's state above: its store must come after (an
+    // unconditional barrier; a conditional one costs registers)
+    evx_sync();
+    if (ct.live) {
+      static_for<E>([&](auto e) { *ct.template at<TPS>(a.state, a.row_stride, e) = x[e]; });
     }
   }
 
   if constexpr (has_inv) {
     if constexpr (BC == BC_ZERO_FLUX) makhoul_pre<N, B>(x, lds, b, t, a.mk);
     fft_regs<N, +1, B>(x, lds, b, t, twl);
-    if (live) {
+    if (ct.live) {
       static_for<E>([&](auto e) {
-        const int n = t + TPS * decltype(e)::value;
-        const int row = (BC == BC_ZERO_FLUX) ? makhoul_src<N>(n) : n;
-        a.out[base + (long long)row * a.row_stride] = x[e];
+        *ct.template at<TPS>(a.out, a.row_stride, e, BC == BC_ZERO_FLUX ? mrow(e) : 0) = x[e];
       });
     }
   }
