@@ -118,7 +118,7 @@ def summarize_profile(d: str, workload: str):
         by_pass[p] = {"kernel": name, "fetch_bytes": f, "write_bytes": wr,
                       "bytes_per_launch": f + wr,
                       "algorithmic_bytes": nbytes[p], "ratio": (f + wr) / nbytes[p]}
-    cmds = [c.format(d=d, w=workload, root="$GRAFT_REPO_ROOT") for _, c in PROFILE_COMMANDS]
+    cmds = [c.format(d="$OUT", w=workload, root="$REPO") for _, c in PROFILE_COMMANDS]
     src = kernel_source_hash()
     rec = {"workload": workload, "source_hash": src, "fetch_scale": f_scale,
            "write_scale": w_scale, "commands": cmds, "kernels": by_pass}
@@ -126,8 +126,9 @@ def summarize_profile(d: str, workload: str):
     json.dump(rec, open(os.path.join(PROFILES, f"traffic_{workload}.json"), "w"), indent=1)
     lines = [f"# rocprofv3 summary: {workload}", "",
              f"Grid {'x'.join(map(str, w.shape[::-1]))}, {w.bc}, {w.scheme}; kernel source "
-             f"hash {src}.", "", "Commands (from /tmp, TMPDIR=/tmp), then "
-             f"`python bench.py --summarize-profile {d} --workload {workload}`:", ""]
+             f"hash {src}.", "", "Commands (REPO = repository root, OUT = an output directory; run "
+             "from /tmp with TMPDIR=/tmp), then "
+             f"`python bench.py --summarize-profile $OUT --workload {workload}`:", ""]
     lines += [f"    {c}" for c in cmds]
     lines += ["", "## Kernel trace (--stats)", "",
               "| kernel | pass | calls | avg ms | % time | algorithmic GB/s |",

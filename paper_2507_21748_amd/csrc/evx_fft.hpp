@@ -230,7 +230,7 @@ EVX_FFT_PLAN(256, 16, 16, 16)
 EVX_FFT_PLAN(320, 20, 20, 4, 4)
 EVX_FFT_PLAN(384, 12, 12, 4, 4, 2)
 EVX_FFT_PLAN(400, 20, 20, 20)
-EVX_FFT_PLAN(512, 16, 16, 16, 2)
+EVX_FFT_PLAN(512, 8, 8, 8, 8)
 EVX_FFT_PLAN(1024, 16, 16, 16, 4)
 
 #undef EVX_FFT_PLAN
