@@ -25,6 +25,26 @@ extern thread_local std::barrier<>* block_barrier;
 inline void evx_sync() { evx_emu::block_barrier->arrive_and_wait(); }
 inline float evx_rcp(float x) { return 1.0f / x; }
 
+// Buffer resource: a byte range [base, base + nbytes); accesses at or past nbytes read zero and
+// drop stores, as the hardware's range check does.
+struct evx_buf {
+  unsigned char* base;
+  unsigned nbytes;
+};
+inline evx_buf evx_make_buf(const void* base, unsigned nbytes) {
+  return evx_buf{static_cast<unsigned char*>(const_cast<void*>(base)), nbytes};
+}
+inline float2 evx_buf_load2(evx_buf r, unsigned off) {
+  if (off >= r.nbytes || r.nbytes - off < 8) return float2{0.f, 0.f};
+  float2 v;
+  __builtin_memcpy(&v, r.base + off, 8);
+  return v;
+}
+inline void evx_buf_store2(evx_buf r, unsigned off, float2 v) {
+  if (off >= r.nbytes || r.nbytes - off < 8) return;
+  __builtin_memcpy(r.base + off, &v, 8);
+}
+
 #else
 #include <hip/hip_runtime.h>
 
@@ -34,6 +54,25 @@ inline float evx_rcp(float x) { return 1.0f / x; }
 
 __device__ __forceinline__ void evx_sync() { __syncthreads(); }
 __device__ __forceinline__ float evx_rcp(float x) { return 1.0f / x; }
+
+// Buffer resource over [base, base + nbytes) (raw, stride 0; word 3 = 0x00020000, the gfx9
+// untyped-buffer format).  A uniform base lives in scalar registers and every access adds one
+// 32-bit vector offset; offsets at or past nbytes read zero and drop stores (hardware range check).
+typedef __amdgpu_buffer_rsrc_t evx_buf;
+typedef unsigned evx_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ evx_buf evx_make_buf(const void* base, unsigned nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(nbytes), 0x00020000);
+}
+__device__ __forceinline__ float2 evx_buf_load2(evx_buf r, unsigned off) {
+  const evx_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+__device__ __forceinline__ void evx_buf_store2(evx_buf r, unsigned off, float2 v) {
+  evx_u32x2 u;
+  u.x = __float_as_uint(v.x);
+  u.y = __float_as_uint(v.y);
+  __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, 0);
+}
 #endif
 
 namespace evx {

@@ -31,13 +31,13 @@ static hipError_t col_go(const ColArgs& a, hipStream_t s) {
   using C = ColCfg<N>;
   const long long nblk = (a.nseq + C::B - 1) / C::B;
   if (nblk <= 0) return hipSuccess;
-  // ColTile works with 32-bit sequence numbers and 32-bit lane byte offsets
-  const long long qmax = (a.ncols - 1 + C::B - 1) / a.ncols;
-  const long long lane_span =
-      (qmax * a.outer_stride + a.ncols + (long long)(C::TPS - 1) * a.row_stride) * 8;
-  if (nblk > 0x7fffffffLL || a.nseq > 0x7fffffffLL || lane_span > 0xffffffffLL)
+  // 32-bit sequence numbers and lane byte offsets (ColTile)
+  const long long lane_bytes = col_lane_bytes<N>(a);
+  if (nblk > 0x7fffffffLL || a.nseq > 0x7fffffffLL || lane_bytes >= (long long)kDeadLane)
     return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((col_kernel<N, BC, MODE>), dim3(unsigned(nblk)), dim3(C::THREADS), 0, s, a);
+  ColArgs b = a;
+  b.lane_bytes = unsigned(lane_bytes);
+  hipLaunchKernelGGL((col_kernel<N, BC, MODE>), dim3(unsigned(nblk)), dim3(C::THREADS), 0, s, b);
   return hipGetLastError();
 }
 

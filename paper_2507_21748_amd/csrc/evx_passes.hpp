@@ -58,6 +58,7 @@ struct ColArgs {
   float dt_m_kappa;        // dt M kappa
   float dt_m;              // dt M
   int remap;               // XCD-aware block order
+  unsigned lane_bytes;     // bytes addressable from a point's block base (col_lane_bytes)
 };
 
 struct RowArgs {
@@ -85,7 +86,7 @@ EVX_DEV float fprime(float c) { return c * c * c - c; }
 // Index of the cell-centred input point that becomes point n of Makhoul's reordered sequence
 // (v_n = x_{2n} for 2n < N, else x_{2N-2n-1}).
 template <int N>
-EVX_DEV int makhoul_src(int n) {
+constexpr int makhoul_src(int n) {
   return (2 * n < N) ? 2 * n : 2 * N - 2 * n - 1;
 }
 
@@ -168,20 +169,43 @@ EVX_DEV void makhoul_pre(float2 (&x)[FftPlan<N>::E], float2* lds, int b, int t,
   evx_sync();
 }
 
-// Addressing of one block's B sequences.  Point n of a lane's sequence sits at a uniform
-// (scalar) base for the block and n's multiple of TPS, plus a 32-bit lane byte offset, so all of a
-// lane's accesses share one offset register.  The block's first sequence is always a live column
-// (blocks start at multiples of B, the pitch is a multiple of 8 and exceeds the last live column by
-// less than 8), so a lane without data reads that column's points and discards the result: loads
-// need no branch.  The launcher guarantees that sequence numbers fit in 31 bits and lane offsets
-// in 32 bits.
-template <int B>
+// Addressing of one block's B sequences.  For each point index e the block has a uniform base
+// (scalar registers: a buffer resource) and every lane adds one 32-bit byte offset, the same for
+// all its points.  A lane without data gets an offset past the resource's range, so its loads
+// read zero and its stores are dropped without touching memory: no branches and no shared
+// addresses.  Zero-flux reordered accesses (row makhoul_src(n) for point n) use the lowest row of
+// the point group as base and a non-negative lane-dependent row shift.
+constexpr unsigned kDeadLane = 0xfffffff0u;
+
+// Bound on the bytes any lane addresses from a point base; the launchers check that it is below
+// kDeadLane and that sequence numbers fit in 31 bits.
+template <int N>
+inline long long col_lane_bytes(const ColArgs& a) {
+  constexpr int B = ColCfg<N>::B, TPS = ColCfg<N>::TPS;
+  const long long qmax = (a.ncols - 1 + B - 1) / a.ncols;
+  return (qmax * a.outer_stride + a.ncols + B + 2LL * TPS * a.row_stride + 1) * 8;
+}
+
+template <int N>
+constexpr int makhoul_group_min(int e) {
+  int m = N;
+  for (int t = 0; t < FftPlan<N>::TPS; ++t) {
+    const int r = makhoul_src<N>(t + FftPlan<N>::TPS * e);
+    m = r < m ? r : m;
+  }
+  return m;
+}
+
+template <int N, int B>
 struct ColTile {
+  static constexpr int TPS = FftPlan<N>::TPS;
   long long tb = 0;  // float2 offset of the block's first sequence (uniform)
-  unsigned lo = 0;   // lane byte offset of point 0 relative to tb
-  int outer = 0, col = 0;
+  unsigned lo = 0;   // lane byte offset of point 0 relative to tb, or kDeadLane
+  unsigned lc = 0;   // lane byte offset of its column (row 0) relative to tb
+  int outer = 0, col = 0, t = 0;
   bool live = false;
-  EVX_DEV void locate(const ColArgs& a, long long tile, int b, int t) {
+  EVX_DEV void locate(const ColArgs& a, long long tile, int b, int t_) {
+    t = t_;
     const unsigned ncols = unsigned(a.ncols);
     const unsigned s0 = unsigned(tile) * unsigned(B);
     const unsigned o0 = s0 / ncols, c0 = s0 - o0 * ncols;
@@ -191,16 +215,25 @@ struct ColTile {
     outer = int(o0 + q);
     col = int(d - q * ncols);
     live = (long long)s0 + b < a.nseq && col < a.nlive;
-    const long long off = (long long)q * a.outer_stride + (col - (long long)c0) +
-                          (long long)t * a.row_stride;
-    lo = live ? unsigned(off * 8) : 0u;
+    const long long cofs = (long long)q * a.outer_stride + (col - (long long)c0);
+    lc = unsigned(cofs * 8);
+    lo = live ? unsigned((cofs + (long long)t * a.row_stride) * 8) : kDeadLane;
   }
-  // point t + TPS e, shifted by `rows` transform-axis rows (zero-flux reordering)
-  template <int TPS, class P>
-  EVX_DEV P* at(P* base, long long row_stride, int e, long long rows = 0) const {
-    P* pe = base + tb + (long long)(TPS * e) * row_stride;
-    return reinterpret_cast<P*>(reinterpret_cast<unsigned char*>(const_cast<float2*>(pe)) + lo +
-                                rows * row_stride * 8);
+  // point t + TPS e (natural order)
+  EVX_DEV evx_buf res(const float2* base, long long row_stride, int e, unsigned nbytes) const {
+    return evx_make_buf(base + tb + (long long)(TPS * e) * row_stride, nbytes);
+  }
+  // point t + TPS e stored at row makhoul_src(t + TPS e): base row of the group and lane shift
+  template <int E_>
+  EVX_DEV evx_buf res_m(const float2* base, long long row_stride, unsigned nbytes) const {
+    constexpr int gmin = makhoul_group_min<N>(E_);
+    return evx_make_buf(base + tb + (long long)gmin * row_stride, nbytes);
+  }
+  template <int E_>
+  EVX_DEV unsigned off_m(long long row_stride) const {
+    constexpr int gmin = makhoul_group_min<N>(E_);
+    const int sh = makhoul_src<N>(t + TPS * E_) - gmin;
+    return live ? lc + unsigned((long long)sh * row_stride * 8) : kDeadLane;
   }
 };
 
@@ -211,15 +244,12 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE;
   constexpr bool has_inv = MODE != COL_FWD;
   constexpr bool upd = MODE == COL_Z_UPDATE;
+  constexpr bool zf = BC == BC_ZERO_FLUX;
   const int b = tid % B;
   const int t = tid / B;
-  ColTile<B> ct;
+  const unsigned nb = a.lane_bytes;
+  ColTile<N, B> ct;
   ct.locate(a, remap_block(bid, nblk, a.remap), b, t);
-  // Makhoul reordering of zero-flux inputs and outputs: point n <-> row makhoul_src(n)
-  auto mrow = [&](int e) -> long long {
-    const int n = t + TPS * e;
-    return ct.live ? (long long)(makhoul_src<N>(n) - n) : 0;
-  };
 
   // Tables first (they go to LDS after the data loads), then the data and for the update the
   // column K2, all in flight together.
@@ -232,19 +262,21 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
 
   float2 x[E];
   if constexpr (MODE == COL_Z_INV_STATE) {
-    static_for<E>([&](auto e) { x[e] = *ct.template at<TPS>(a.state, a.row_stride, e); });
-  } else {
+    static_for<E>([&](auto e) { x[e] = evx_buf_load2(ct.res(a.state, a.row_stride, e, nb), ct.lo); });
+  } else if constexpr (zf && has_fwd) {
     static_for<E>([&](auto e) {
-      constexpr bool reorder = BC == BC_ZERO_FLUX && has_fwd;
-      x[e] = *ct.template at<TPS>(a.in, a.row_stride, e, reorder ? mrow(e) : 0);
+      constexpr int ev = decltype(e)::value;
+      x[e] = evx_buf_load2(ct.template res_m<ev>(a.in, a.row_stride, nb),
+                           ct.template off_m<ev>(a.row_stride));
     });
+  } else {
+    static_for<E>([&](auto e) { x[e] = evx_buf_load2(ct.res(a.in, a.row_stride, e, nb), ct.lo); });
   }
-  float2 cs[upd ? E : 1];
   float kca = 0.f, kcb = 0.f;
   if constexpr (upd) {
     const int o = ct.live ? ct.outer : 0, cc = ct.live ? ct.col : 0;
     const float ko = a.k2o[o];
-    if constexpr (BC == BC_ZERO_FLUX) {
+    if constexpr (zf) {
       kca = a.k2c[2 * cc] + ko;
       kcb = a.k2c[2 * cc + 1] + ko;
     } else {
@@ -254,27 +286,21 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   }
   tws.store(twl, tid);
   k2s.store(k2l, tid);
-  // Every load of the block (a lane without data reads a live column) precedes every store,
-  // since the passes work in place; the transforms' barriers order them, except for a
-  // single-stage periodic transform, which has none.
-  if constexpr (FftPlan<N>::S == 1 && BC == BC_PERIODIC) evx_sync();
 
   if constexpr (has_fwd) {
     fft_regs<N, -1, B>(x, lds, b, t, twl);
-    if constexpr (BC == BC_ZERO_FLUX) makhoul_post<N, B>(x, lds, b, t, a.mk);
+    if constexpr (zf) makhoul_post<N, B>(x, lds, b, t, a.mk);
   }
 
   if constexpr (MODE == COL_FWD) {
-    if (ct.live) {
-      static_for<E>([&](auto e) { *ct.template at<TPS>(a.out, a.row_stride, e) = x[e]; });
-    }
+    static_for<E>([&](auto e) { evx_buf_store2(ct.res(a.out, a.row_stride, e, nb), ct.lo, x[e]); });
     return;
   }
 
   if constexpr (MODE == COL_Z_INIT) {
-    if (ct.live) {
-      static_for<E>([&](auto e) { *ct.template at<TPS>(a.state, a.row_stride, e) = x[e]; });
-    }
+    static_for<E>([&](auto e) {
+      evx_buf_store2(ct.res(a.state, a.row_stride, e, nb), ct.lo, x[e]);
+    });
   }
 
   if constexpr (upd) {
@@ -285,7 +311,10 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
     evx_sync();  // K2 table visible (a single-stage periodic transform has no barrier of its own)
     // The state is read only now: loading it with the data would hold 32 more registers
     // through the forward transform and cost a block per compute unit.
-    static_for<E>([&](auto e) { cs[e] = *ct.template at<TPS>(a.state, a.row_stride, e); });
+    float2 cs[E];
+    static_for<E>([&](auto e) {
+      cs[e] = evx_buf_load2(ct.res(a.state, a.row_stride, e, nb), ct.lo);
+    });
     static_for<E>([&](auto e) {
       const int k = t + TPS * decltype(e)::value;
       const float kr = k2l[k];
@@ -297,21 +326,22 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
       const float Gb = evx_rcp(1.0f + a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
       x[e] = make_float2(Ga * (Pa * Cs.x - a.dt_m * K2a * F.x),
                          Gb * (Pb * Cs.y - a.dt_m * K2b * F.y));
+      evx_buf_store2(ct.res(a.state, a.row_stride, e, nb), ct.lo, x[e]);
     });
-    // lanes without data read a live column's state above: its store must come after (an
-    // unconditional barrier; a conditional one costs registers)
-    evx_sync();
-    if (ct.live) {
-      static_for<E>([&](auto e) { *ct.template at<TPS>(a.state, a.row_stride, e) = x[e]; });
-    }
   }
 
   if constexpr (has_inv) {
-    if constexpr (BC == BC_ZERO_FLUX) makhoul_pre<N, B>(x, lds, b, t, a.mk);
+    if constexpr (zf) makhoul_pre<N, B>(x, lds, b, t, a.mk);
     fft_regs<N, +1, B>(x, lds, b, t, twl);
-    if (ct.live) {
+    if constexpr (zf) {
       static_for<E>([&](auto e) {
-        *ct.template at<TPS>(a.out, a.row_stride, e, BC == BC_ZERO_FLUX ? mrow(e) : 0) = x[e];
+        constexpr int ev = decltype(e)::value;
+        evx_buf_store2(ct.template res_m<ev>(a.out, a.row_stride, nb),
+                       ct.template off_m<ev>(a.row_stride), x[e]);
+      });
+    } else {
+      static_for<E>([&](auto e) {
+        evx_buf_store2(ct.res(a.out, a.row_stride, e, nb), ct.lo, x[e]);
       });
     }
   }

@@ -52,8 +52,15 @@ struct EmuLauncher {
   void col_t(const ColArgs& a) {
     using C = ColCfg<N>;
     const int nblk = int((a.nseq + C::B - 1) / C::B);
+    const long long lane_bytes = col_lane_bytes<N>(a);
+    if (lane_bytes >= (long long)kDeadLane) {
+      std::fprintf(stderr, "column pass offsets exceed 32 bits\n");
+      std::exit(3);
+    }
+    ColArgs b = a;
+    b.lane_bytes = unsigned(lane_bytes);
     run_grid(nblk, C::THREADS, C::LDS, [&](int tid, int bid, int nb, float2* lds) {
-      colpass_body<N, BC, MODE>(a, tid, bid, nb, lds);
+      colpass_body<N, BC, MODE>(b, tid, bid, nb, lds);
     });
   }
   template <int NH, int BC, int MODE>
