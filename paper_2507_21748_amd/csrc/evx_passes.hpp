@@ -428,7 +428,11 @@ struct RowCfg {
   // staged rows: periodic rows at the spectral pitch (padding included), zero flux NH floats
   static constexpr int PITCH = (BC == BC_PERIODIC) ? spectral_pitch(NH) : NH / 2;
   static constexpr int SROW = row_lds_stride(NH + 1, B);  // periodic LDS row stride
-  static constexpr int STAGE = (BC == BC_PERIODIC) ? B * SROW : B * NH;  // float2 slots
+  // zero flux: 2B rows of NH floats staged at a float stride ZS with ZS/2 odd (rows 2b of the
+  // lanes b then fall in distinct banks), when the rows split the block's lanes evenly
+  static constexpr bool ZPAD = (THREADS % (2 * B)) == 0;
+  static constexpr int ZS = (!ZPAD || NH % 4 == 2) ? NH : NH + 2;
+  static constexpr int STAGE = (BC == BC_PERIODIC) ? B * SROW : B * ZS;  // float2 slots
   static constexpr int TW = STAGE > B * NH ? STAGE : B * NH;  // twiddle table offset
   static constexpr int PO = TW + NH;                            // post table offset
   // post table entries: periodic keeps k <= NH/2 (the rest follows from
@@ -524,14 +528,19 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     rows_out<B, P, W, NH + 1, T>(a.out_c + r0 * P, a.nrows - r0, lds, tid);
     (void)NX;
   } else {
-    // zero flux: rows ra = r0 + 2b, rb = ra + 1, stage as floats [2B][NH]
-    constexpr int NX = NH;
+    // zero flux: rows ra = r0 + 2b, rb = ra + 1, staged as floats [2B][ZS]
+    constexpr int NX = NH, ZS = C::ZS;
     float* st = reinterpret_cast<float*>(lds);
     constexpr bool real_in = MODE == ROW_FWD || MODE == ROW_FWD_FP;
     const float* in = real_in ? a.in_r : reinterpret_cast<const float*>(a.in_c);
     // rows are NX floats (NX even) = NX/2 float2; r0 is even
-    copy_in<B * NX, T>(reinterpret_cast<const float2*>(in) + r0 * (NX / 2),
-                       (a.nrows - r0) * (NX / 2), lds, tid);
+    if constexpr (C::ZPAD) {
+      rows_in<2 * B, NX / 2, ZS / 2, NX / 2, T>(reinterpret_cast<const float2*>(in) + r0 * (NX / 2),
+                                                a.nrows - r0, lds, tid);
+    } else {
+      copy_in<B * NX, T>(reinterpret_cast<const float2*>(in) + r0 * (NX / 2),
+                         (a.nrows - r0) * (NX / 2), lds, tid);
+    }
     tws.store(twl, tid);
     pos.store(pol, tid);
     evx_sync();
@@ -539,7 +548,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       static_for<E>([&](auto e) {
         const int n = t + TPS * decltype(e)::value;
         const int s = makhoul_src<NX>(n);
-        x[e] = make_float2(st[(2 * b) * NX + s], st[(2 * b + 1) * NX + s]);
+        x[e] = make_float2(st[(2 * b) * ZS + s], st[(2 * b + 1) * ZS + s]);
       });
       if constexpr (MODE == ROW_FWD_FP)
         static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
@@ -547,9 +556,9 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     } else {
       static_for<E>([&](auto e) {
         const int k = t + TPS * decltype(e)::value;
-        const float Da = st[(2 * b) * NX + k], Db = st[(2 * b + 1) * NX + k];
-        const float Dar = (k == 0) ? 0.f : st[(2 * b) * NX + NX - k];
-        const float Dbr = (k == 0) ? 0.f : st[(2 * b + 1) * NX + NX - k];
+        const float Da = st[(2 * b) * ZS + k], Db = st[(2 * b + 1) * ZS + k];
+        const float Dar = (k == 0) ? 0.f : st[(2 * b) * ZS + NX - k];
+        const float Dbr = (k == 0) ? 0.f : st[(2 * b + 1) * ZS + NX - k];
         const float2 w = cconj(pol[k]);
         const float2 va = cmul(w, make_float2(Da, -Dar));
         const float2 vb = cmul(w, make_float2(Db, -Dbr));
@@ -562,12 +571,18 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         static_for<E>([&](auto e) {
           const int n = t + TPS * decltype(e)::value;
           const int s = makhoul_src<NX>(n);
-          st[(2 * b) * NX + s] = x[e].x;
-          st[(2 * b + 1) * NX + s] = x[e].y;
+          st[(2 * b) * ZS + s] = x[e].x;
+          st[(2 * b + 1) * ZS + s] = x[e].y;
         });
         evx_sync();
-        copy_out<B * NX, T>(reinterpret_cast<float2*>(a.out_r) + r0 * (NX / 2),
-                            (a.nrows - r0) * (NX / 2), lds, tid);
+        if constexpr (C::ZPAD) {
+          rows_out<2 * B, NX / 2, ZS / 2, NX / 2, T>(reinterpret_cast<float2*>(a.out_r) +
+                                                         r0 * (NX / 2),
+                                                     a.nrows - r0, lds, tid);
+        } else {
+          copy_out<B * NX, T>(reinterpret_cast<float2*>(a.out_r) + r0 * (NX / 2),
+                              (a.nrows - r0) * (NX / 2), lds, tid);
+        }
         return;
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
@@ -588,11 +603,15 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
     evx_sync();
     static_for<E>([&](auto e) {
       const int k = t + TPS * decltype(e)::value;
-      st[(2 * b) * NX + k] = y[e].x;
-      st[(2 * b + 1) * NX + k] = y[e].y;
+      st[(2 * b) * ZS + k] = y[e].x;
+      st[(2 * b + 1) * ZS + k] = y[e].y;
     });
     evx_sync();
-    copy_out<B * NX, T>(a.out_c + r0 * (NX / 2), (a.nrows - r0) * (NX / 2), lds, tid);
+    if constexpr (C::ZPAD) {
+      rows_out<2 * B, NX / 2, ZS / 2, NX / 2, T>(a.out_c + r0 * (NX / 2), a.nrows - r0, lds, tid);
+    } else {
+      copy_out<B * NX, T>(a.out_c + r0 * (NX / 2), (a.nrows - r0) * (NX / 2), lds, tid);
+    }
   }
 }
 
