@@ -222,6 +222,37 @@ def run_workload(evx, torch, w, steps, warmup, timing=True):
     return out
 
 
+def adjoint_workload(evx, torch, w, steps: int = 200, every: int = 20):
+    """The inverse-problem gradient: an nsteps rollout with spectral checkpoints every `every`
+    steps, then the backward sweep of hand-written adjoint steps (gradients for c0, kappa, M).
+    Returns wall times of the forward and backward halves."""
+    from paper_2507_21748_amd.autograd import ch_rollout
+    from paper_2507_21748_amd.inputs import quench_field
+    plan = evx.Plan(w.shape, w.bc, w.scheme, dx=w.dx, ops=evx.OP_STEP | evx.OP_ADJOINT)
+    c0 = torch.from_numpy(quench_field(w.shape, w.mean, w.amp, w.seed)).cuda().requires_grad_(True)
+    kappa = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    M = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    target = torch.zeros_like(c0)
+    out = {}
+    for rep in range(2):  # the first repetition warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cT = ch_rollout(c0, kappa, M, plan, steps, w.dt, w.A, every)
+        loss = ((cT - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = torch.autograd.grad(loss, (c0, kappa, M))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out = {"grid": list(w.shape[::-1]), "steps": steps, "checkpoint_every": every,
+               "forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1),
+               "backward_ms_per_step": 1e3 * (t2 - t1) / steps,
+               "finite": bool(all(torch.isfinite(x).all().item() for x in g))}
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline():
     """FP64 oracle on this host: 2 timed steps (after 1 untimed) of a 512^3 periodic quench with
     the same physics and IC recipe as the benchmark workload."""
@@ -306,7 +337,7 @@ def main():
     }
     if not args.no_extra:
         extra = {}
-        for name in ("ch256_periodic", "ch256_zeroflux", "ch400_zeroflux"):
+        for name in ("ch256_periodic", "ch256_zeroflux", "ch400_zeroflux", "inverse128"):
             if name == args.workload:
                 continue
             r = run_workload(evx, torch, WORKLOADS[name], 200, 10)
@@ -316,6 +347,7 @@ def main():
                            "step_effective_gbs": wb * r["voxel_steps_per_s"]
                            / WORKLOADS[name].voxels / 1e9,
                            "passes": {k: v["avg_ms"] for k, v in r["passes"].items()}}
+        extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
         line["extra"] = extra
     if not args.no_cpu_baseline:
         cb = cpu_baseline()
