@@ -253,6 +253,30 @@ def adjoint_workload(evx, torch, w, steps: int = 200, every: int = 20):
     return out
 
 
+def surrogate_workload(torch, w, reps: int = 5):
+    """One coarse-stepper application (4 convolution layers, residual, mass projection) on the
+    512^3 field: ms per application and the convolution flop rate (114,048 flop/voxel)."""
+    from paper_2507_21748_amd.inputs import quench_field
+    from paper_2507_21748_amd.surrogate import Net
+    net = Net(seed=w.seed)
+    c = torch.from_numpy(quench_field(w.shape, w.mean, w.amp, w.seed)).cuda()
+    out = torch.empty_like(c)
+    net.infer(c, out, conserve_mass=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.infer(c, out, conserve_mass=True)
+    torch.cuda.synchronize()
+    secs = (time.perf_counter() - t0) / reps
+    flop = 114048.0 * w.voxels
+    res = {"grid": list(w.shape[::-1]), "ms_per_application": 1e3 * secs,
+           "conv_tflops": flop / secs / 1e12, "bf16_dense_peak_tflops": 2500.0,
+           "finite": bool(torch.isfinite(out).all().item())}
+    del net, c, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline():
     """FP64 oracle on this host: 2 timed steps (after 1 untimed) of a 512^3 periodic quench with
     the same physics and IC recipe as the benchmark workload."""
@@ -348,6 +372,7 @@ def main():
                            / WORKLOADS[name].voxels / 1e9,
                            "passes": {k: v["avg_ms"] for k, v in r["passes"].items()}}
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
+        extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
         line["extra"] = extra
     if not args.no_cpu_baseline:
         cb = cpu_baseline()

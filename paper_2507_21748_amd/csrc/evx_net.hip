@@ -53,6 +53,8 @@ __host__ __device__ constexpr long long w_off(int l) {
 constexpr long long NPARAM = layer_off(NLAYER);  // 57121
 static_assert(NPARAM == 57121, "parameter count");
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ bf16_t f2bf(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
@@ -60,11 +62,46 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
-// Phi(z) = erfc(-z / sqrt 2) / 2 (no cancellation in the negative tail, unlike 1 + erf)
-__device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfcf(-z * 0.70710678118654752f); }
+// GELU(z) = z Phi(z) with Phi(z) = erfc(-z / sqrt 2) / 2, evaluated through erfc so that the
+// negative tail keeps its relative accuracy (1 + erf would cancel).  erfc(u), u >= 0, uses the
+// Chebyshev-fitted form published in Numerical Recipes (routine erfcc):
+//   erfc(u) ~= t exp(-u^2 + P(t)),  t = 1 / (1 + u / 2),
+// with relative error below 1.2e-7 for every u >= 0 -- far below the BF16 resolution (2^-8) of
+// the stored activations -- at a fraction of the cost of a library erfc.
+__device__ __forceinline__ float exp_fast(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+}
+__device__ __forceinline__ float erfc_poly(float t) {
+  float p = 0.17087277f;
+  p = __builtin_fmaf(p, t, -0.82215223f);
+  p = __builtin_fmaf(p, t, 1.48851587f);
+  p = __builtin_fmaf(p, t, -1.13520398f);
+  p = __builtin_fmaf(p, t, 0.27886807f);
+  p = __builtin_fmaf(p, t, -0.18628806f);
+  p = __builtin_fmaf(p, t, 0.09678418f);
+  p = __builtin_fmaf(p, t, 0.37409196f);
+  p = __builtin_fmaf(p, t, 1.00002368f);
+  return __builtin_fmaf(p, t, -1.26551223f);
+}
+// Phi(z) and, through *g, exp(-z^2 / 2) for the derivative
+__device__ __forceinline__ float phi_cdf(float z, float* g = nullptr) {
+  const float u = __builtin_fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.5f, u, 1.0f));
+  const float u2 = u * u;
+  float e;  // erfc(u)
+  if (g) {
+    *g = exp_fast(-u2);
+    e = t * *g * exp_fast(erfc_poly(t));
+  } else {
+    e = t * exp_fast(erfc_poly(t) - u2);
+  }
+  return z > 0.f ? 1.0f - 0.5f * e : 0.5f * e;
+}
 __device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
 __device__ __forceinline__ float gelu_prime(float z) {
-  return phi_cdf(z) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  float g;
+  const float p = phi_cdf(z, &g);
+  return p + z * 0.39894228040143268f * g;
 }
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -331,6 +368,33 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_small(ConvArgs a) {
   float acc[CO];
 #pragma unroll
   for (int o = 0; o < CO; ++o) acc[o] = 0.f;
+  if constexpr (!IN_F32 && CI % 8 == 0) {
+    // BF16 pairs straight from LDS into packed dot products (two MACs per instruction, FP32
+    // accumulation); block-uniform BF16 weight pairs come through the scalar cache
+    const unsigned* __restrict__ W2 = reinterpret_cast<const unsigned*>(a.w);
+    for (int d = 0; d < 27; ++d) {
+      const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
+      const int h = ((lz + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
+      const u32x4* p = reinterpret_cast<const u32x4*>(s_in + size_t(h) * IN_BYTES);
+      unsigned xw[CI / 2];
+#pragma unroll
+      for (int q = 0; q < CI / 8; ++q) {
+        const u32x4 w4 = p[q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xw[4 * q + k] = w4[k];
+      }
+#pragma unroll
+      for (int o = 0; o < CO; ++o) {
+        float s = acc[o];
+#pragma unroll
+        for (int i = 0; i < CI / 2; ++i)
+          s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, xw[i]),
+                                              __builtin_bit_cast(bf16x2_t, W2[(d * CO + o) * (CI / 2) + i]),
+                                              s, false);
+        acc[o] = s;
+      }
+    }
+  } else
   for (int d = 0; d < 27; ++d) {
     const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
     const int h = ((lz + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
