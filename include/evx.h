@@ -78,8 +78,9 @@ evx_status evx_plan_destroy(evx_plan* plan);
 
 /* Device bytes the caller must provide for the given EVX_OP_* mask.  EVX_OP_STEP needs two
  * spectral buffers (state S and work W) of nz*ny rows of complex64 (periodic: nx/2+1 values per
- * row, rows padded to a multiple of 8 values) or nz*ny*nx float (zero flux) each, i.e. about 8
- * bytes per voxel; EVX_OP_DIAG adds one spectral buffer and 16 KB
+ * row, rows padded to a multiple of 8 values) or nz*ny*nx float (zero flux) each, S rounded up to
+ * whole column blocks of the z transform, i.e. about 8 bytes per voxel; EVX_OP_DIAG adds one
+ * spectral buffer and 16 KB
  * of partial sums; EVX_OP_ADJOINT adds three spectral buffers, one real field and the partial
  * sums (about 24 bytes per voxel in total). */
 evx_status evx_plan_workspace_bytes(const evx_plan* plan, int ops, size_t* bytes);
@@ -90,7 +91,9 @@ evx_status evx_plan_workspace_bytes(const evx_plan* plan, int ops, size_t* bytes
 evx_status evx_plan_set_workspace(evx_plan* plan, void* dev, size_t bytes);
 
 /* Spectral state S (device pointer and size in bytes), for checkpoint/resume: copying S out and
- * later back in, followed by evx_ch_restore, resumes the trajectory bit-for-bit. */
+ * later back in, followed by evx_ch_restore, resumes the trajectory bit-for-bit.  The layout is
+ * the library's own (tile-major over the z transform's column blocks; its first element is the
+ * DC coefficient) and should be treated as opaque bytes. */
 evx_status evx_plan_state(const evx_plan* plan, void** dev, size_t* bytes);
 
 /* S <- T[c] and primes the work buffer (W <- F_z^{-1} S).  c: device, nx*ny*nz floats, read. */

@@ -57,11 +57,12 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t spec_bytes(const Geom& g) { return align256(size_t(g.spec) * sizeof(float2)); }
+size_t state_bytes(const Geom& g) { return align256(size_t(g.state) * sizeof(float2)); }
 size_t partial_bytes() { return align256(2 * AUX_BLOCKS * sizeof(double)); }
 size_t real_bytes(const Geom& g) { return align256(size_t(g.V) * sizeof(float)); }
 
 // Workspace layout: S, W | A, partial (diagnostics) | B, L, v (adjoint).
-size_t ws_step(const Geom& g) { return 2 * spec_bytes(g); }
+size_t ws_step(const Geom& g) { return state_bytes(g) + spec_bytes(g); }
 size_t ws_diag(const Geom& g) { return ws_step(g) + spec_bytes(g) + partial_bytes(); }
 size_t ws_adj(const Geom& g) { return ws_diag(g) + 2 * spec_bytes(g) + real_bytes(g); }
 
@@ -254,23 +255,23 @@ evx_status evx_plan_set_workspace(evx_plan* p, void* dev, size_t bytes) {
   if (!p || !dev) return fail(EVX_ERR_ARG, "NULL argument");
   if (reinterpret_cast<uintptr_t>(dev) % 256 != 0)
     return fail(EVX_ERR_ARG, "workspace must be 256-byte aligned");
-  if (bytes < 2 * spec_bytes(p->g))
-    return fail(EVX_ERR_NOMEM, "workspace of %zu bytes, need %zu", bytes, 2 * spec_bytes(p->g));
+  if (bytes < ws_step(p->g))
+    return fail(EVX_ERR_NOMEM, "workspace of %zu bytes, need %zu", bytes, ws_step(p->g));
   p->ws = static_cast<float2*>(dev);
   p->ws_bytes = bytes;
   unsigned char* base = static_cast<unsigned char*>(dev);
-  const size_t sb = spec_bytes(p->g);
+  const size_t sb = spec_bytes(p->g), stb = state_bytes(p->g);
   p->S = reinterpret_cast<float2*>(base);
-  p->W = reinterpret_cast<float2*>(base + sb);
+  p->W = reinterpret_cast<float2*>(base + stb);
   p->has_diag = bytes >= ws_diag(p->g);
   p->has_adj = bytes >= ws_adj(p->g);
   p->aux = AdjointBufs{};
   if (p->has_diag) {
-    p->aux.A = reinterpret_cast<float2*>(base + 2 * sb);
-    p->aux.partial = reinterpret_cast<double*>(base + 3 * sb);
+    p->aux.A = reinterpret_cast<float2*>(base + stb + sb);
+    p->aux.partial = reinterpret_cast<double*>(base + stb + 2 * sb);
   }
   if (p->has_adj) {
-    unsigned char* q = base + 3 * sb + partial_bytes();
+    unsigned char* q = base + stb + 2 * sb + partial_bytes();
     p->aux.B = reinterpret_cast<float2*>(q);
     p->aux.Lm = reinterpret_cast<float2*>(q + sb);
     p->aux.v = reinterpret_cast<float*>(q + 2 * sb);
@@ -284,7 +285,7 @@ evx_status evx_plan_state(const evx_plan* p, void** dev, size_t* bytes) {
   if (!p || !dev || !bytes) return fail(EVX_ERR_ARG, "NULL argument");
   if (!p->S) return fail(EVX_ERR_NOMEM, "no workspace set");
   *dev = p->S;
-  *bytes = size_t(p->g.spec) * sizeof(float2);
+  *bytes = size_t(p->g.state) * sizeof(float2);
   return EVX_OK;
 }
 

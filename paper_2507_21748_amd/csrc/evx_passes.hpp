@@ -203,9 +203,12 @@ struct ColTile {
   unsigned lo = 0;   // lane byte offset of point 0 relative to tb, or kDeadLane
   unsigned lc = 0;   // lane byte offset of its column (row 0) relative to tb
   int outer = 0, col = 0, t = 0;
+  long long tile = 0;
+  unsigned so = 0;   // lane byte offset in the tile-major state (or kDeadLane)
   bool live = false;
-  EVX_DEV void locate(const ColArgs& a, long long tile, int b, int t_) {
+  EVX_DEV void locate(const ColArgs& a, long long tile_, int b, int t_) {
     t = t_;
+    tile = tile_;
     const unsigned ncols = unsigned(a.ncols);
     const unsigned s0 = unsigned(tile) * unsigned(B);
     const unsigned o0 = s0 / ncols, c0 = s0 - o0 * ncols;
@@ -218,6 +221,14 @@ struct ColTile {
     const long long cofs = (long long)q * a.outer_stride + (col - (long long)c0);
     lc = unsigned(cofs * 8);
     lo = live ? unsigned((cofs + (long long)t * a.row_stride) * 8) : kDeadLane;
+    so = live ? unsigned((t * B + b) * 8) : kDeadLane;
+  }
+  // The spectral state is stored tile-major: tile, then transform point k, then column b, at
+  // (tile N + k) B + b, so that a block's state is one contiguous N B run (read and written only
+  // by the z pass).  Point t + TPS e of lane (t, b): uniform base plus the lane offset `so`.
+  EVX_DEV evx_buf sres(const float2* state, int e) const {
+    return evx_make_buf(state + tile * ((long long)N * B) + (long long)(TPS * e) * B,
+                        unsigned(TPS * B * 8));
   }
   // point t + TPS e (natural order)
   EVX_DEV evx_buf res(const float2* base, long long row_stride, int e, unsigned nbytes) const {
@@ -262,7 +273,7 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
 
   float2 x[E];
   if constexpr (MODE == COL_Z_INV_STATE) {
-    static_for<E>([&](auto e) { x[e] = evx_buf_load2(ct.res(a.state, a.row_stride, e, nb), ct.lo); });
+    static_for<E>([&](auto e) { x[e] = evx_buf_load2(ct.sres(a.state, e), ct.so); });
   } else if constexpr (zf && has_fwd) {
     static_for<E>([&](auto e) {
       constexpr int ev = decltype(e)::value;
@@ -299,7 +310,7 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
 
   if constexpr (MODE == COL_Z_INIT) {
     static_for<E>([&](auto e) {
-      evx_buf_store2(ct.res(a.state, a.row_stride, e, nb), ct.lo, x[e]);
+      evx_buf_store2(ct.sres(a.state, e), ct.so, x[e]);
     });
   }
 
@@ -313,7 +324,7 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
     // through the forward transform and cost a block per compute unit.
     float2 cs[E];
     static_for<E>([&](auto e) {
-      cs[e] = evx_buf_load2(ct.res(a.state, a.row_stride, e, nb), ct.lo);
+      cs[e] = evx_buf_load2(ct.sres(a.state, e), ct.so);
     });
     static_for<E>([&](auto e) {
       const int k = t + TPS * decltype(e)::value;
@@ -326,7 +337,7 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
       const float Gb = evx_rcp(1.0f + a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
       x[e] = make_float2(Ga * (Pa * Cs.x - a.dt_m * K2a * F.x),
                          Gb * (Pb * Cs.y - a.dt_m * K2b * F.y));
-      evx_buf_store2(ct.res(a.state, a.row_stride, e, nb), ct.lo, x[e]);
+      evx_buf_store2(ct.sres(a.state, e), ct.so, x[e]);
     });
   }
 

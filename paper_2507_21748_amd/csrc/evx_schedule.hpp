@@ -30,6 +30,19 @@ inline bool fft_len_supported(int n) {
   }
 }
 
+// Sequences per column-pass block for a transform length (0 if unsupported).
+inline int col_block_seqs(int n) {
+  switch (n) {
+#define EVX_CASE(N) \
+  case N:           \
+    return ColCfg<N>::B;
+    EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+    default:
+      return 0;
+  }
+}
+
 struct Geom {
   int nx = 0, ny = 0, nz = 0;
   int bc = BC_PERIODIC;
@@ -39,7 +52,8 @@ struct Geom {
   int ncols = 0;         // float2 columns per row of a spectral buffer holding data
   int pitch = 0;         // float2 per row of a spectral buffer (ncols rounded up, periodic)
   int row_len = 0;       // x-pass FFT length: nx/2 (periodic) or nx (zero flux)
-  long long spec = 0;    // float2 per spectral buffer
+  long long spec = 0;    // float2 per spectral buffer (work W)
+  long long state = 0;   // float2 of the state S (tile-major; whole z-pass tiles)
   long long nrows = 0;   // ny * nz
 };
 
@@ -56,6 +70,8 @@ inline Geom make_geom(int nx, int ny, int nz, int bc, int scheme, double dx) {
   g.row_len = (bc == BC_PERIODIC) ? nx / 2 : nx;
   g.pitch = (bc == BC_PERIODIC) ? spectral_pitch(nx / 2) : nx / 2;
   g.spec = (long long)nz * ny * g.pitch;
+  const long long bz = col_block_seqs(nz), nseq_z = (long long)ny * g.pitch;
+  g.state = bz > 0 ? (nseq_z + bz - 1) / bz * bz * nz : g.spec;
   g.nrows = (long long)ny * nz;
   return g;
 }

@@ -219,7 +219,7 @@ int main(int argc, char** argv) {
   FILE* f = std::fopen(argv[13], "rb");
   if (!f || std::fread(c.data(), sizeof(float), g.V, f) != size_t(g.V)) return 4;
   std::fclose(f);
-  std::vector<float2> S(g.spec), W(g.spec);
+  std::vector<float2> S(g.state), W(g.spec);
   const StepCoef co{float(A * dt), float(dt * M * kappa), float(dt * M)};
   EmuLauncher l;
   sched_begin(l, g, t, c.data(), S.data(), W.data(), remap);
