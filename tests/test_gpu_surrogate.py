@@ -171,3 +171,28 @@ def test_mass_projection(evx_gpu):
     d = (cons.double() - plain.double())
     assert abs(float(cons.double().mean() - c.double().mean())) <= 1e-7
     assert float(d.max() - d.min()) <= 1e-6
+
+
+def test_infer_512_sampled_voxels(evx_gpu):
+    """The full-size inference (512^3, the rollout grid) against the FP64 oracle on sampled voxels:
+    an output voxel depends only on the input within distance 4 (four 3x3x3 layers), so the
+    oracle's network on the periodic 9^3 neighbourhood gives that voxel exactly."""
+    from paper_2507_21748_amd.surrogate import Net
+    n = 512
+    theta = _params(8)
+    net = Net(theta)
+    c_np = quench_field((n, n, n), 0.0, 0.05, seed=7)
+    out = net.infer(torch.from_numpy(c_np).cuda()).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(9)
+    pts = rng.integers(0, n, size=(24, 3))
+    pts[0] = (0, 0, 0)              # periodic wrap on every axis
+    pts[1] = (n - 1, n - 1, n - 1)
+    got, ref, base = [], [], []
+    r = np.arange(-4, 5)
+    for z, y, x in pts:
+        patch = c_np[np.ix_((z + r) % n, (y + r) % n, (x + r) % n)]
+        ref.append(S.forward(patch, theta)[4, 4, 4])
+        got.append(out[z, y, x])
+        base.append(float(c_np[z, y, x]))
+    got, ref, base = map(np.asarray, (got, ref, base))
+    assert np.linalg.norm((got - base) - (ref - base)) <= 1e-2 * np.linalg.norm(ref - base)
