@@ -252,13 +252,16 @@ constexpr bool plan_ok() {
   return prod == N && P::E * P::TPS == N;
 }
 
-// Sequences per workgroup for a length-N transform: enough lanes for >= 256 threads, at least
-// 8 sequences (64-byte row segments) and LDS for the exchange area at most 64 KiB.
+// Sequences per workgroup for a length-N transform: up to 256 threads, at least 8 sequences
+// (64-byte row segments) and LDS for the exchange area at most 64 KiB.
 template <int N>
 constexpr int seqs_per_block() {
   constexpr int tps = FftPlan<N>::TPS;
   int b = 8;
-  while (b * tps < 256 && b < 256) b *= 2;
+  // grow to at most 256 threads: for lane counts that are not powers of two (radix-5 plans) this
+  // stops below 256 rather than above, which keeps the LDS per block small enough for more
+  // resident waves (400^3 zero flux: 22% faster than 320-thread blocks)
+  while (2 * b * tps <= 256 && b < 256) b *= 2;
   while (b > 8 && b * N * 8 > 65536) b /= 2;
   return b;
 }
