@@ -272,7 +272,23 @@ def surrogate_workload(torch, w, reps: int = 5):
     res = {"grid": list(w.shape[::-1]), "ms_per_application": 1e3 * secs,
            "conv_tflops": flop / secs / 1e12, "bf16_dense_peak_tflops": 2500.0,
            "finite": bool(torch.isfinite(out).all().item())}
-    del net, c, out
+    # one training step: batch 4 of 72^3 windows (64^3 interior, halo 4), forward, backward and
+    # Adam; about 3x the forward flops per window voxel
+    batch, edge, halo = 4, 72, 4
+    x = torch.stack([torch.from_numpy(quench_field((edge,) * 3, 0.0, 0.5, 100 + i))
+                     for i in range(batch)]).cuda()
+    y = x.roll(1, dims=1).contiguous()
+    net.train_step(x, y, halo, lr=1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(x, y, halo, lr=1e-4)
+    torch.cuda.synchronize()
+    tsecs = (time.perf_counter() - t0) / reps
+    res["train_step_ms"] = 1e3 * tsecs
+    res["train_window"] = [batch, edge, halo]
+    res["train_conv_tflops"] = 3 * 114048.0 * batch * edge ** 3 / tsecs / 1e12
+    del net, c, out, x, y
     torch.cuda.empty_cache()
     return res
 

@@ -12,8 +12,9 @@
 //                 stages a 6x10x18-voxel halo tile (69 KB) and the layer's weights (55 KB) in LDS
 //                 and computes a 4x8x16 output tile with 8 waves.
 //   conv_small    1 -> 32 and 32 -> 1 layers on the VALU (27*32 MACs per voxel).
-//   wgrad         dW[d,o,i] = sum_v gz[v,o] x[v+d,i] and db, split over voxel chunks with a
-//                 fixed-order reduction (bit-reproducible).
+//   wgrad32_mfma  dW[d,o,i] = sum_v gz[v,o] x[v+d,i] and db of the 32 -> 32 layers as MFMA GEMMs
+//   wgrad1_mfma   over voxels; wgrad1_mfma the same for the 1 -> 32 and 32 -> 1 layers; per-block
+//                 partial sums with a fixed-order reduction (bit-reproducible).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -467,76 +468,352 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_small(ConvArgs a) {
 }
 
 // ----------------------------------------------------------------------------- weight gradient
-// Block (d, chunk): threads (o, i); partial[chunk][d][o][i] = sum_{v in chunk} gz[v,o] x[v+d,i].
-// d == 27 computes the bias gradient (x == 1).
-constexpr int WG_CHUNKS = 64;
-constexpr int WG_TILE = 64;  // voxels staged per iteration
+// All three kinds are GEMMs whose reduction index is the voxel, run on v_mfma_f32_16x16x32_bf16:
+// one MFMA contracts 32 voxels (4 rows of 8 along x).  Blocks walk tiles of 8 x 16 x 1 voxels
+// (x, y, z), keep their sums in registers across tiles and leave one partial set each, which
+// wgrad_reduce adds in a fixed order (bit-reproducible).  Voxels past the grid edge of a ragged
+// tile are zero in the staged operand that is not shifted, so they contribute nothing.
+constexpr int WT_X = 8, WT_Y = 16, WT_KS = WT_Y / 4;
+constexpr int WG_MAXBLK = 512;   // partial sets of the 32 -> 32 kernel
+constexpr int WG1_MAXBLK = 512;  // partial sets of the one-channel kernel
 
-struct WgradArgs {
-  const void* gz;    // bf16 [V][Cout] or float [V] (Cout == 1)
-  const void* x;     // bf16 [V][Cin]
-  float* partial;    // [WG_CHUNKS][28][Cout][Cin]
-  int nx, ny, nz;
-};
-
-template <int CI, int CO, bool GZ_F32>
-__global__ __launch_bounds__(CI * CO) void wgrad(WgradArgs a) {
-  __shared__ float s_g[WG_TILE * CO];
-  __shared__ float s_x[WG_TILE * CI];
-  const int d = blockIdx.x % 28, chunk = blockIdx.x / 28;
-  const int tid = threadIdx.x, o = tid / CI, i = tid % CI;
-  const long long V = (long long)a.nx * a.ny * a.nz;
-  const long long per = (V + WG_CHUNKS - 1) / WG_CHUNKS;
-  const long long v0 = chunk * per, v1 = (v0 + per < V) ? v0 + per : V;
-  const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
-  float acc = 0.f;
-  for (long long vb = v0; vb < v1; vb += WG_TILE) {
-    __syncthreads();
-    for (int k = tid; k < WG_TILE * CO; k += CI * CO) {
-      const long long v = vb + k / CO;
-      float g = 0.f;
-      if (v < v1) {
-        if constexpr (GZ_F32) g = static_cast<const float*>(a.gz)[v];
-        else g = bf2f(static_cast<const bf16_t*>(a.gz)[v * CO + k % CO]);
-      }
-      s_g[k] = g;
-    }
-    for (int k = tid; k < WG_TILE * CI; k += CI * CO) {
-      const long long v = vb + k / CI;
-      float xv = 0.f;
-      if (v < v1) {
-        if (d == 27) {
-          xv = 1.f;
-        } else {
-          const int x = int(v % a.nx), y = int((v / a.nx) % a.ny),
-                    z = int(v / ((long long)a.nx * a.ny));
-          const long long u = ((long long)wrap(z + dz, a.nz) * a.ny + wrap(y + dy, a.ny)) * a.nx +
-                              wrap(x + dx, a.nx);
-          xv = bf2f(static_cast<const bf16_t*>(a.x)[u * CI + k % CI]);
-        }
-      }
-      s_x[k] = xv;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < WG_TILE; ++k) acc += s_g[k * CO + o] * s_x[k * CI + i];
+__device__ __forceinline__ int pmod(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+// channel j of two voxels' 8-channel chunks as one dword (voxel a in the low half)
+__device__ __forceinline__ unsigned pack_pair(const u32x4& qa, const u32x4& qb, int j) {
+  const unsigned a = qa[j >> 1], b = qb[j >> 1];
+  return (j & 1) ? ((a >> 16) | (b & 0xFFFF0000u)) : ((a & 0xFFFFu) | (b << 16));
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+// BF16 ones at the k-slots of lane group lg whose voxel is inside the grid
+__device__ __forceinline__ bf16x8 ones_mask(int x0, int nx, bool row_ok) {
+  u32x4 m;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const unsigned lo = (row_ok && x0 + 2 * h < nx) ? 0x3F80u : 0u;
+    const unsigned hi = (row_ok && x0 + 2 * h + 1 < nx) ? 0x3F80u : 0u;
+    m[h] = lo | (hi << 16);
   }
-  a.partial[(((long long)chunk * 28 + d) * CO + o) * CI + i] = acc;
+  return as_bf16x8(m);
 }
 
-// grad[param] (+)= sum over chunks in fixed order; maps (d, o, i) -> W offset, d == 27 -> bias
-// (only i == 0 of the bias rows is used).
-__global__ void wgrad_reduce(const float* partial, float* grad_w, float* grad_b, int ci, int co) {
+// 32 -> 32 layers.  With the x part of the offset moved onto gz,
+//   dW[d,o,i] = sum_u gz[u - dx e_x, o] x[u + dy e_y + dz e_z, i],
+// the x operand is read unshifted and one gz fragment, with its three x shifts, feeds the three
+// dx offsets of a wave; wave w of the 9-wave block takes (dz, dy) = (w / 3 - 1, w % 3 - 1), 48
+// accumulators per lane.  LDS holds both fields channel-major: x with a y/z halo of one (54 rows of 8 voxels), gz
+// with an x halo of one (16 rows of 10).  Channel strides are 8 mod 16 bf16 so that the 16-byte
+// fragment reads of 8 consecutive channels fall in distinct banks.
+constexpr int WG_THREADS = 576;
+constexpr int SX_ROWS = 3 * (WT_Y + 2);     // 54
+constexpr int SX_CS = SX_ROWS * WT_X + 8;   // 440
+constexpr int SG_P = 16;                    // row pitch; x' in [0, 10) is x0 - 1 .. x0 + 8
+constexpr int SG_CS = WT_Y * SG_P + 8;      // 264
+constexpr int SX_UNITS = SX_ROWS * 4 * 4;   // (row, voxel pair, 8-channel group)
+constexpr int SG_UNITS = WT_Y * 5 * 4;
+static_assert(SX_CS % 16 == 8 && SG_CS % 16 == 8, "conflict-free fragment reads");
+
+struct WgradArgs {
+  const void* s;      // 32->32: gz bf16 [V][32]; one channel: the scalar field (see wgrad1)
+  const bf16_t* t;    // 32->32: x bf16 [V][32]; one channel: the 32-channel field
+  float* partial;     // [gridDim.x][28][Cout][Cin]; row 27 holds db at [27][o][0]
+  int nx, ny, nz, ntiles;
+};
+
+__global__ __launch_bounds__(WG_THREADS, 5) void wgrad32_mfma(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16_t s_x[CH * SX_CS];
+  __shared__ __attribute__((aligned(16))) bf16_t s_g[CH * SG_CS];
+  unsigned* sx32 = reinterpret_cast<unsigned*>(s_x);
+  unsigned* sg32 = reinterpret_cast<unsigned*>(s_g);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int ntx = (a.nx + WT_X - 1) / WT_X, nty = (a.ny + WT_Y - 1) / WT_Y;
+  const u32x4* g4 = static_cast<const u32x4*>(a.s);
+  const u32x4* x4 = reinterpret_cast<const u32x4*>(a.t);
+  const int dzi = w / 3, dyi = w % 3;
+  f32x4 acc[3][2][2];  // [dx + 1][o half][i half]
+  f32x4 accb[2];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) acc[j][h][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  accb[0] = accb[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const int x0 = (t % ntx) * WT_X, rest = t / ntx;
+    const int y0 = (rest % nty) * WT_Y, z0 = rest / nty;
+    __syncthreads();  // the previous tile's fragment reads are done
+    for (int q = tid; q < SX_UNITS; q += WG_THREADS) {
+      const int cg = q & 3, p = (q >> 2) & 3, row = q >> 4;
+      const int hz = row / (WT_Y + 2), hy = row % (WT_Y + 2);
+      const long long rowv =
+          ((long long)pmod(z0 + hz - 1, a.nz) * a.ny + pmod(y0 + hy - 1, a.ny)) * a.nx;
+      const int xa = x0 + 2 * p;
+      u32x4 qa = u32x4{0u, 0u, 0u, 0u}, qb = qa;
+      if (xa < a.nx) qa = x4[(rowv + xa) * 4 + cg];
+      if (xa + 1 < a.nx) qb = x4[(rowv + xa + 1) * 4 + cg];
+      unsigned* dst = sx32 + (8 * cg * SX_CS + row * WT_X + 2 * p) / 2;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[j * (SX_CS / 2)] = pack_pair(qa, qb, j);
+    }
+    for (int q = tid; q < SG_UNITS; q += WG_THREADS) {
+      const int cg = q & 3, p = (q >> 2) % 5, r = (q >> 2) / 5;
+      u32x4 qa = u32x4{0u, 0u, 0u, 0u}, qb = qa;
+      if (y0 + r < a.ny) {  // rows past the grid edge stay zero: they mask out their voxels
+        const long long rowv = ((long long)z0 * a.ny + y0 + r) * a.nx;
+        qa = g4[(rowv + pmod(x0 - 1 + 2 * p, a.nx)) * 4 + cg];
+        qb = g4[(rowv + pmod(x0 + 2 * p, a.nx)) * 4 + cg];
+      }
+      unsigned* dst = sg32 + (8 * cg * SG_CS + r * SG_P + 2 * p) / 2;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[j * (SG_CS / 2)] = pack_pair(qa, qb, j);
+    }
+    __syncthreads();
+    const bf16x8 ones = ones_mask(x0, a.nx, true);
+    for (int ks = 0; ks < WT_KS; ++ks) {
+      if (y0 + 4 * ks >= a.ny) break;
+      const int r = 4 * ks + lg;
+      u32x4 q[2];
+      unsigned q4[2];
+#pragma unroll
+      for (int hm = 0; hm < 2; ++hm) {
+        const unsigned* src = sg32 + ((16 * hm + li) * SG_CS + r * SG_P) / 2;
+        q[hm] = *reinterpret_cast<const u32x4*>(src);
+        q4[hm] = src[4];
+      }
+      bf16x8 B[2];
+#pragma unroll
+      for (int hn = 0; hn < 2; ++hn)
+        B[hn] = *reinterpret_cast<const bf16x8*>(
+            &s_x[(16 * hn + li) * SX_CS + (dzi * (WT_Y + 2) + r + dyi) * WT_X]);
+      // gz fragment for shift dx: elements x' = j + 1 - dx of the staged row
+      auto frag = [&](int hm, int dxi) {
+        const u32x4 v = q[hm];
+        if (dxi == 0) return as_bf16x8(u32x4{v[1], v[2], v[3], q4[hm]});
+        if (dxi == 2) return as_bf16x8(v);
+        return as_bf16x8(u32x4{__builtin_amdgcn_alignbyte(v[1], v[0], 2),
+                               __builtin_amdgcn_alignbyte(v[2], v[1], 2),
+                               __builtin_amdgcn_alignbyte(v[3], v[2], 2),
+                               __builtin_amdgcn_alignbyte(q4[hm], v[3], 2)});
+      };
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+        for (int hm = 0; hm < 2; ++hm) {
+          const bf16x8 A = frag(hm, dxi);
+#pragma unroll
+          for (int hn = 0; hn < 2; ++hn)
+            acc[dxi][hm][hn] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[hn], acc[dxi][hm][hn], 0, 0, 0);
+        }
+      if (w == 4) {  // db[o] = sum_u gz[u, o]
+#pragma unroll
+        for (int hm = 0; hm < 2; ++hm)
+          accb[hm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag(hm, 1), ones, accb[hm], 0, 0, 0);
+      }
+    }
+  }
+  // D[m][n] of lane (li, lg), element r: o = 16 hm + 4 lg + r, i = 16 hn + li
+  float* P = a.partial + (long long)blockIdx.x * 28 * CH * CH;
+#pragma unroll
+  for (int dxi = 0; dxi < 3; ++dxi) {
+    const int d = 3 * w + dxi;  // 9 (dz + 1) + 3 (dy + 1) + dx + 1
+#pragma unroll
+    for (int hm = 0; hm < 2; ++hm)
+#pragma unroll
+      for (int hn = 0; hn < 2; ++hn)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          P[(d * CH + 16 * hm + 4 * lg + r) * CH + 16 * hn + li] = acc[dxi][hm][hn][r];
+  }
+  if (w == 4) {
+#pragma unroll
+    for (int hm = 0; hm < 2; ++hm)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int hn = 0; hn < 2; ++hn)
+          P[(27 * CH + 16 * hm + 4 * lg + r) * CH + 16 * hn + li] = accb[hm][r];
+  }
+}
+
+// 1 -> 32 and 32 -> 1 layers.  With one scalar field s and one 32-channel field T,
+//   dW[d, c] = sum_u s[u + SIGMA d] T[u, c],
+// SIGMA = +1: s = X0 (BF16), T = dZ1, c = o;  SIGMA = -1: s = dY (FP32), T = A3, c = i (after
+// substituting u = v + d).  That is a 32 x 32 GEMM per K-step with rows m = d (27 used): the A
+// fragment gathers s at u + SIGMA d from an FP32 halo tile, B is T channel-major.  FP32 dY enters
+// as three BF16 terms (hi + mid + lo equals it exactly barring underflow), so every MFMA product
+// is exact.  Wave w of the 4-wave block takes K-step w of each tile; the block sums its waves in
+// LDS in a fixed order before leaving its partial set.
+constexpr int WG1_THREADS = 256;
+constexpr int ST_CS = WT_Y * WT_X + 8;          // 136 bf16 per channel (8 mod 16)
+constexpr int SS_P = 12, SS_H = WT_Y + 2;       // scalar halo tile [3][18][12], x' in [0, 10)
+constexpr int SS_N = 3 * SS_H * 10;
+static_assert(ST_CS % 16 == 8, "conflict-free fragment reads");
+
+template <int SIGMA>
+__global__ __launch_bounds__(WG1_THREADS) void wgrad1_mfma(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16_t s_t[CH * ST_CS];
+  __shared__ float s_s[3 * SS_H * SS_P];
+  __shared__ float s_red[4 * 28 * CH];
+  unsigned* st32 = reinterpret_cast<unsigned*>(s_t);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int ntx = (a.nx + WT_X - 1) / WT_X, nty = (a.ny + WT_Y - 1) / WT_Y;
+  const u32x4* t4 = reinterpret_cast<const u32x4*>(a.t);
+  constexpr int NT = SIGMA > 0 ? 1 : 3;  // BF16 terms of the scalar
+  f32x4 acc[2][2];
+  f32x4 accb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    accb[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) acc[h][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  // this lane's two A rows: offset d = 16 hm + li (rows 27..31 are zero)
+  int soff[2];
+  bool dok[2];
+#pragma unroll
+  for (int hm = 0; hm < 2; ++hm) {
+    const int d = 16 * hm + li;
+    dok[hm] = d < 27;
+    const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
+    soff[hm] = dok[hm] ? ((1 + SIGMA * dz) * SS_H + 1 + SIGMA * dy) * SS_P + 1 + SIGMA * dx : 0;
+  }
+
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const int x0 = (t % ntx) * WT_X, rest = t / ntx;
+    const int y0 = (rest % nty) * WT_Y, z0 = rest / nty;
+    __syncthreads();
+    {  // T tile: 16 rows x 4 voxel pairs x 4 channel groups, one unit per thread
+      const int cg = tid & 3, p = (tid >> 2) & 3, r = tid >> 4;
+      const int xa = x0 + 2 * p;
+      u32x4 qa = u32x4{0u, 0u, 0u, 0u}, qb = qa;
+      if (y0 + r < a.ny) {
+        const long long rowv = ((long long)z0 * a.ny + y0 + r) * a.nx;
+        if (xa < a.nx) qa = t4[(rowv + xa) * 4 + cg];
+        if (xa + 1 < a.nx) qb = t4[(rowv + xa + 1) * 4 + cg];
+      }
+      unsigned* dst = st32 + (8 * cg * ST_CS + r * WT_X + 2 * p) / 2;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[j * (ST_CS / 2)] = pack_pair(qa, qb, j);
+    }
+    for (int q = tid; q < SS_N; q += WG1_THREADS) {
+      const int xq = q % 10, hy = (q / 10) % SS_H, hz = q / (10 * SS_H);
+      const long long v =
+          ((long long)pmod(z0 + hz - 1, a.nz) * a.ny + pmod(y0 + hy - 1, a.ny)) * a.nx +
+          pmod(x0 + xq - 1, a.nx);
+      float sv;
+      if constexpr (SIGMA > 0) sv = bf2f(static_cast<const bf16_t*>(a.s)[v]);
+      else sv = static_cast<const float*>(a.s)[v];
+      s_s[(hz * SS_H + hy) * SS_P + xq] = sv;
+    }
+    __syncthreads();
+    if (y0 + 4 * w < a.ny) {
+      const int r = 4 * w + lg;
+      bf16x8 B[2];
+#pragma unroll
+      for (int hn = 0; hn < 2; ++hn)
+        B[hn] = *reinterpret_cast<const bf16x8*>(&s_t[(16 * hn + li) * ST_CS + r * WT_X]);
+      bf16x8 A[2][NT];
+#pragma unroll
+      for (int hm = 0; hm < 2; ++hm) {
+        u32x4 part[NT];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          unsigned lo[NT], hi[NT];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            float v = dok[hm] ? s_s[soff[hm] + r * SS_P + 2 * k + e] : 0.f;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+              const bf16_t h = f2bf(v);
+              v -= bf2f(h);  // exact: the remainder of a round-to-nearest fits in FP32
+              (e ? hi : lo)[n] = h;
+            }
+          }
+#pragma unroll
+          for (int n = 0; n < NT; ++n) part[n][k] = lo[n] | (hi[n] << 16);
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) A[hm][n] = as_bf16x8(part[n]);
+      }
+#pragma unroll
+      for (int hm = 0; hm < 2; ++hm)
+#pragma unroll
+        for (int hn = 0; hn < 2; ++hn)
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[hm][hn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[hm][n], B[hn], acc[hm][hn],
+                                                                  0, 0, 0);
+      if constexpr (SIGMA > 0) {  // db[o] = sum_u dZ1[u, o]: all-ones A
+        const bf16x8 one = as_bf16x8(u32x4{0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u});
+#pragma unroll
+        for (int hn = 0; hn < 2; ++hn)
+          accb[hn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(one, B[hn], accb[hn], 0, 0, 0);
+      } else {  // db = sum_u dY[u]: row d = 13 (no offset) against the in-grid mask
+        const bf16x8 msk = ones_mask(x0, a.nx, y0 + r < a.ny);
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          accb[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0][n], msk, accb[0], 0, 0, 0);
+      }
+    }
+  }
+  // D[m][n] of lane (li, lg), element r: d = 16 hm + 4 lg + r, c = 16 hn + li
+  float* red = s_red + w * 28 * CH;
+#pragma unroll
+  for (int hm = 0; hm < 2; ++hm)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int d = 16 * hm + 4 * lg + r;
+      if (d < 27) {
+#pragma unroll
+        for (int hn = 0; hn < 2; ++hn) red[d * CH + 16 * hn + li] = acc[hm][hn][r];
+      }
+    }
+  if (lg == 0) {  // SIGMA > 0: every row of D holds db[c]; SIGMA < 0: zeros, db set below
+#pragma unroll
+    for (int hn = 0; hn < 2; ++hn) red[27 * CH + 16 * hn + li] = SIGMA > 0 ? accb[hn][0] : 0.f;
+  }
+  if constexpr (SIGMA < 0) {
+    __syncthreads();  // the zero fill of row 27 lands before lane (0, 3) writes db
+    if (lg == 3 && li == 0) red[27 * CH] = accb[0][1];  // D[13][0]: 4 * 3 + 1 = 13
+  }
+  __syncthreads();
+  float* P = a.partial + (long long)blockIdx.x * 28 * CH;
+  for (int k = tid; k < 28 * CH; k += WG1_THREADS)
+    P[k] = ((s_red[k] + s_red[28 * CH + k]) + s_red[2 * 28 * CH + k]) + s_red[3 * 28 * CH + k];
+}
+
+// grad[param] (+)= sum over the partial sets; maps (d, o, i) -> W offset, d == 27 -> bias (only
+// i == 0 of the bias rows is used).  A block takes 64 consecutive outputs; its 16 thread groups
+// sum interleaved subsets of the sets (group g: sets g, g + 16, ...), and the groups are added in
+// a fixed order: bit-reproducible.
+constexpr int RED_K = 64, RED_G = 16;
+
+__global__ __launch_bounds__(RED_K * RED_G) void wgrad_reduce(const float* partial, int nsets,
+                                                              float* grad_w, float* grad_b,
+                                                              int ci, int co) {
+  __shared__ float s_sum[RED_G * RED_K];
   const int n = 28 * co * ci;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  float s = 0.f;
-  for (int c = 0; c < WG_CHUNKS; ++c) s += partial[(long long)c * n + k];
+  const int kk = threadIdx.x % RED_K, g = threadIdx.x / RED_K;
+  const int k = blockIdx.x * RED_K + kk;
+  float acc = 0.f;
+  if (k < n)
+    for (int c = g; c < nsets; c += RED_G) acc += partial[(long long)c * n + k];
+  s_sum[g * RED_K + kk] = acc;
+  __syncthreads();
+  if (g != 0 || k >= n) return;
+  float t = 0.f;
+#pragma unroll
+  for (int j = 0; j < RED_G; ++j) t += s_sum[j * RED_K + kk];
   const int d = k / (co * ci), rem = k % (co * ci);
   if (d < 27) {
-    grad_w[k] += s;
+    grad_w[k] += t;
   } else if (rem % ci == 0) {
-    grad_b[rem / ci] += s;
+    grad_b[rem / ci] += t;
   }
 }
 
@@ -596,11 +873,17 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a) {
   if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
 }
 
-__global__ void loss_final(const double* partial, int n, double scale, double* loss, int add) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < n; ++i) s += partial[i];
-  *loss = (add ? *loss : 0.0) + scale * s;
+// one block of LOSS_BLOCKS threads: fixed-order tree over the per-block sums
+__global__ __launch_bounds__(LOSS_BLOCKS) void loss_final(const double* partial, double scale,
+                                                          double* loss, int add) {
+  __shared__ double red[LOSS_BLOCKS];
+  red[threadIdx.x] = partial[threadIdx.x];
+  __syncthreads();
+  for (int h = LOSS_BLOCKS / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (add ? *loss : 0.0) + scale * red[0];
 }
 
 __global__ void adam_kernel(float* p, float* m, float* v, const float* g, long long n, float lr,
@@ -726,18 +1009,37 @@ hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
 
 hipError_t launch_wgrad(int layer, const void* gz, const void* x, float* partial, float* grads,
                         int nx, int ny, int nz, hipStream_t s) {
-  WgradArgs w{gz, x, partial, nx, ny, nz};
-  const unsigned grid = 28 * WG_CHUNKS;
-  if (layer == 0)
-    hipLaunchKernelGGL((wgrad<1, CH, false>), dim3(grid), dim3(CH), 0, s, w);
-  else if (layer == NLAYER - 1)
-    hipLaunchKernelGGL((wgrad<CH, 1, true>), dim3(grid), dim3(CH), 0, s, w);
-  else
-    hipLaunchKernelGGL((wgrad<CH, CH, false>), dim3(grid), dim3(CH * CH), 0, s, w);
+  const long long nt =
+      (long long)((nx + WT_X - 1) / WT_X) * ((ny + WT_Y - 1) / WT_Y) * (long long)nz;
+  if (nt >= (1LL << 31)) return hipErrorInvalidValue;
+  const bool wide = layer == 1 || layer == 2;
+  const long long maxblk = wide ? WG_MAXBLK : WG1_MAXBLK;
+  const long long per = (nt + maxblk - 1) / maxblk;  // tiles per block, balanced
+  const int grid = int((nt + per - 1) / per);
+  WgradArgs w{};
+  w.partial = partial;
+  w.nx = nx;
+  w.ny = ny;
+  w.nz = nz;
+  w.ntiles = int(nt);
+  if (wide) {
+    w.s = gz;
+    w.t = static_cast<const bf16_t*>(x);
+    hipLaunchKernelGGL(wgrad32_mfma, dim3(grid), dim3(WG_THREADS), 0, s, w);
+  } else if (layer == 0) {  // s = X0 (shifted), T = dZ1
+    w.s = x;
+    w.t = static_cast<const bf16_t*>(gz);
+    hipLaunchKernelGGL(wgrad1_mfma<1>, dim3(grid), dim3(WG1_THREADS), 0, s, w);
+  } else {                  // s = dY, T = A3 (shifted, moved onto dY)
+    w.s = gz;
+    w.t = static_cast<const bf16_t*>(x);
+    hipLaunchKernelGGL(wgrad1_mfma<-1>, dim3(grid), dim3(WG1_THREADS), 0, s, w);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int ci = cin_of(layer), co = cout_of(layer), n = 28 * ci * co;
-  hipLaunchKernelGGL(wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial,
+  hipLaunchKernelGGL(wgrad_reduce, dim3((n + RED_K - 1) / RED_K), dim3(RED_K * RED_G), 0, s,
+                     partial, grid,
                      grads + layer_off(layer), grads + layer_off(layer) + layer_w(layer), ci, co);
   return hipGetLastError();
 }
@@ -761,7 +1063,7 @@ struct TrainBufs {
 
 size_t train_bytes(long long V) {
   return a256(V * 2) + 9 * a256(V * CH * 2) + 2 * a256(V * 4) +
-         a256(size_t(WG_CHUNKS) * 28 * CH * CH * 4) + a256(NPARAM * 4) +
+         a256(size_t(WG_MAXBLK) * 28 * CH * CH * 4) + a256(NPARAM * 4) +
          a256(LOSS_BLOCKS * sizeof(double));
 }
 
@@ -777,7 +1079,7 @@ TrainBufs carve_train(void* ws, long long V) {
   for (int i = 0; i < 3; ++i) b.g[i] = reinterpret_cast<bf16_t*>(take(V * CH * 2));
   b.out = reinterpret_cast<float*>(take(V * 4));
   b.dy = reinterpret_cast<float*>(take(V * 4));
-  b.partial = reinterpret_cast<float*>(take(size_t(WG_CHUNKS) * 28 * CH * CH * 4));
+  b.partial = reinterpret_cast<float*>(take(size_t(WG_MAXBLK) * 28 * CH * CH * 4));
   b.grads = reinterpret_cast<float*>(take(NPARAM * 4));
   b.lpart = reinterpret_cast<double*>(take(LOSS_BLOCKS * sizeof(double)));
   return b;
@@ -952,7 +1254,7 @@ evx_status evx_surrogate_train_step(evx_net* n, const float* x, const float* y, 
     LossArgs la{b.out, yw, b.dy, b.lpart, edge, halo, inv_total};
     hipLaunchKernelGGL(loss_kernel, dim3(LOSS_BLOCKS), dim3(256), 0, s, la);
     NET_TRY(hipGetLastError());
-    hipLaunchKernelGGL(loss_final, dim3(1), dim3(1), 0, s, b.lpart, LOSS_BLOCKS, inv_total, loss,
+    hipLaunchKernelGGL(loss_final, dim3(1), dim3(LOSS_BLOCKS), 0, s, b.lpart, inv_total, loss,
                        w > 0 ? 1 : 0);
     NET_TRY(hipGetLastError());
     // backward
