@@ -32,12 +32,13 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources; counter-based traffic figures are used only while it matches."""
+    """Hash of the HIP sources the Cahn-Hilliard step is built from (all but the surrogate's
+    evx_net.hip); counter-based traffic figures are used only while it matches."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2507_21748_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hpp", ".hip")):
+        if name.endswith((".hpp", ".hip")) and name != "evx_net.hip":
             h.update(name.encode())
             h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
@@ -69,6 +70,34 @@ PROFILE_COMMANDS = [
            "-- python3 {root}/bench.py --workload {w} --steps 4 --warmup 1 --no-cpu-baseline "
            "--no-extra"),
 ]
+
+
+# Kernel-trace runs of single extras, summarized by --summarize-trace into
+# profiles/kernels_<name>.md (same conventions as PROFILE_COMMANDS).
+TRACE_COMMANDS = {
+    "surrogate512": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv "
+                    "-d {d}/kt -o kt -- python3 {root}/bench.py --extra-only surrogate512",
+    "inverse128": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv "
+                  "-d {d}/kt -o kt -- python3 {root}/bench.py --extra-only inverse128",
+}
+
+
+def summarize_trace(d: str, name: str):
+    """profiles/kernels_<name>.md from the --stats CSV of the TRACE_COMMANDS run under d."""
+    import csv
+    import glob
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(d, "kt", "*kernel_stats.csv"))[0])))
+    cmd = TRACE_COMMANDS[name].format(d="$OUT", root="$REPO")
+    lines = [f"# rocprofv3 kernel trace: {name}", "",
+             "Command (REPO = repository root, OUT = an output directory; run from /tmp with "
+             f"TMPDIR=/tmp), then `python bench.py --summarize-trace $OUT --workload {name}`:", "",
+             f"    {cmd}", "", "| kernel | calls | avg us | total ms | % time |", "|---|---|---|---|---|"]
+    for r in stats[:20]:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) * 1e-3:.1f} | "
+                     f"{float(r['TotalDurationNs']) * 1e-6:.3f} | {float(r['Percentage']):.1f} |")
+    os.makedirs(PROFILES, exist_ok=True)
+    open(os.path.join(PROFILES, f"kernels_{name}.md"), "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def _pass_of_kernel(name: str):
@@ -327,9 +356,16 @@ def main():
                     help="size of the calibration copy run before the workload (0 = skip)")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarize the rocprofv3 runs of PROFILE_COMMANDS found under DIR")
+    ap.add_argument("--extra-only", choices=sorted(TRACE_COMMANDS),
+                    help="run only this extra workload and print its JSON (for kernel traces)")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="summarize the TRACE_COMMANDS run of --workload found under DIR")
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.workload)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the spectral stepper here runs on a single device "
@@ -342,6 +378,14 @@ def main():
     from paper_2507_21748_amd.inputs import WORKLOADS
     evx.load()
     torch.cuda.set_device(0)
+    if args.extra_only == "surrogate512":
+        print(json.dumps({"surrogate512_application":
+                          surrogate_workload(torch, WORKLOADS["surrogate512"])}))
+        return
+    if args.extra_only == "inverse128":
+        print(json.dumps({"inverse128_gradient":
+                          adjoint_workload(evx, torch, WORKLOADS["inverse128"])}))
+        return
     w = WORKLOADS[args.workload]
     probe = copy_probe(torch, args.copy_probe_gib) if args.copy_probe_gib > 0 else None
     res = run_workload(evx, torch, w, args.steps, args.warmup)

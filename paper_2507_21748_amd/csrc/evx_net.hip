@@ -11,7 +11,10 @@
 //                 (16 voxels, 16 output channels, one offset d, all 32 input channels).  A block
 //                 stages a 6x10x18-voxel halo tile (69 KB) and the layer's weights (55 KB) in LDS
 //                 and computes a 4x8x16 output tile with 8 waves.
-//   conv_small    1 -> 32 and 32 -> 1 layers on the VALU (27*32 MACs per voxel).
+//   conv_in_mfma  1 -> 32 layer (and the last layer's backward data) as a GEMM over the 27
+//                 offsets: D[o][v] = sum_d W[d][o] x[v + d]; GELU by a BF16 table.
+//   conv_out_mfma 32 -> 1 layer: P[u][d] = sum_i W[d][i] a[u][i] on MFMA, then
+//                 out[v] = c[v] + sum_d P[v + d][d] + b.
 //   wgrad32_mfma  dW[d,o,i] = sum_v gz[v,o] x[v+d,i] and db of the 32 -> 32 layers as MFMA GEMMs
 //   wgrad1_mfma   over voxels; wgrad1_mfma the same for the 1 -> 32 and 32 -> 1 layers; per-block
 //                 partial sums with a fixed-order reduction (bit-reproducible).
@@ -105,7 +108,38 @@ __device__ __forceinline__ float gelu_prime(float z) {
   return p + z * 0.39894228040143268f * g;
 }
 
+// GELU of a BF16 pre-activation, rounded to BF16, by table.  For |z| in [2^-8, 8) (11 binades x
+// 128 mantissas x 2 signs = 2816 values) the table holds bf16(gelu(z)) computed once by gelu()
+// above, so those results are identical to evaluating it.  Below 2^-8, Phi(z) = 1/2 + z/sqrt(2 pi)
+// to a relative 1e-8; from 8 up, gelu(z) rounds to z; from -8 down the full evaluation runs.
+constexpr int GT_EMIN = 127 - 8, GT_NEXP = 11, GT_HALF = GT_NEXP * 128, GT_N = 2 * GT_HALF;
+static_assert(GT_N % 8 == 0, "table staged in 16-byte chunks");
+__device__ __forceinline__ bf16_t gelu_table_arg(int idx) {
+  const int sign = idx / GT_HALF, rem = idx % GT_HALF;
+  return bf16_t((sign << 15) | ((GT_EMIN + rem / 128) << 7) | (rem % 128));
+}
+__device__ __forceinline__ bf16_t gelu_bf16(bf16_t zb, const bf16_t* tab) {
+  const int ex = (zb >> 7) & 0xFF;
+  const int idx = (zb >> 15) * GT_HALF + (ex - GT_EMIN) * 128 + (zb & 127);
+  const bool in_tab = ex >= GT_EMIN && ex < GT_EMIN + GT_NEXP;
+  const bf16_t tv = tab[in_tab ? idx : 0];
+  const float z = bf2f(zb);
+  bf16_t r = in_tab ? tv : f2bf(z * __builtin_fmaf(0.39894228040143268f, z, 0.5f));
+  if (ex >= GT_EMIN + GT_NEXP) {  // |z| >= 8 (and inf / NaN)
+    if (zb >> 15) r = f2bf(gelu(z));
+    else r = zb;
+  }
+  return r;
+}
+
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// true modulo: tiles past a grid edge can reach more than one period away on small grids
+__device__ __forceinline__ int pmod(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
 
 // epilogues
 enum : int {
@@ -118,13 +152,13 @@ enum : int {
 struct ConvArgs {
   const void* in;        // bf16 [V][Cin] or float [V] (Cin == 1, FP32 input)
   const bf16_t* w;       // bf16 [27][Cout][Cin]
-  const float* wf;       // the same weights as FP32 values (BF16-rounded), for the VALU layers
   const float* bias;     // [Cout] (fp32 master), null for EPI_DGELU
   bf16_t* z_out;         // EPI_GELU_Z
   bf16_t* a_out;         // EPI_GELU_Z, EPI_GELU, EPI_DGELU
   const bf16_t* zprev;   // EPI_DGELU: pre-activation of the layer below [V][Cout]
   const float* c;        // EPI_RESID: network input (fp32)
   float* out;            // EPI_RESID
+  const bf16_t* gtab;    // GELU table (GT_N entries), for conv_in_mfma's GELU epilogues
   int nx, ny, nz;
 };
 
@@ -281,6 +315,7 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
           const bf16_t zlo = f2bf(val[2 * k2] + a.bias[o]);
           const bf16_t zhi = f2bf(val[2 * k2 + 1] + a.bias[o + 1]);
           zw[k2] = unsigned(zlo) | (unsigned(zhi) << 16);
+          // evaluated, not looked up: here the table's LDS reads cost more than they save
           aw[k2] = unsigned(f2bf(gelu(bf2f(zlo)))) | (unsigned(f2bf(gelu(bf2f(zhi)))) << 16);
         }
         if constexpr (EPI == EPI_GELU_Z)
@@ -291,20 +326,162 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
   }
 }
 
-// ----------------------------------------------------------------------------- VALU conv
-// 1 -> 32 and 32 -> 1 layers on the VALU.  A block owns the same 4x8x16 output tile as the MFMA
-// kernel, stages its 6x10x18 halo (and the weights, as FP32) in LDS, and each thread computes one
-// voxel's Cout outputs; BF16 outputs leave as 16-byte stores (64 contiguous bytes per thread).
-// IN_F32: the input is FP32 [V] (Cin = 1).
+// The one-channel layers own the same 4x8x16 output tile as the 32 -> 32 kernel, one block each.
 constexpr int SMALL_THREADS = TX * TY * TZ;  // 512
 
-template <int CI, int CO, bool IN_F32, int EPI>
-__global__ __launch_bounds__(SMALL_THREADS) void conv_small(ConvArgs a) {
-  constexpr int IN_BYTES = IN_F32 ? 4 : 2 * CI;              // per voxel
-  __shared__ __attribute__((aligned(16))) unsigned char s_in[HALO_VOX * IN_BYTES];
-  __shared__ float s_b[CO];
-  // block-uniform weight reads: served by the scalar cache, no LDS traffic per FMA
-  const float* __restrict__ W = a.wf;
+// ----------------------------------------------------------------------------- MFMA 1 -> 32
+// The 1 -> 32 layer, and the backward data of the 32 -> 1 layer (with flipped weights a 1 -> 32
+// convolution of FP32 dY), as one GEMM per 16 voxels with the 27 offsets as the reduction index
+// (padded to 32): D[o][v] = sum_d W[d][o] x[v + d] on v_mfma_f32_16x16x32_bf16, with the weights
+// as A (held in registers) and B the halo values gathered for 16 voxels of a row.  A lane's D
+// fragment holds 4 consecutive channels of one voxel, so results leave as 8-byte stores without
+// staging.  FP32 input enters as three BF16 terms (hi + mid + lo, exact barring underflow), so
+// every product is exact and only the FP32 accumulation rounds.
+template <bool IN_F32, int EPI>
+__global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
+  typedef typename std::conditional<IN_F32, float, bf16_t>::type elem_t;
+  constexpr int NT = IN_F32 ? 3 : 1;
+  __shared__ elem_t s_h[HALO_VOX];
+  __shared__ __attribute__((aligned(16))) bf16_t s_gt[GT_N];
+  const int tid = threadIdx.x;
+  if (EPI != EPI_DGELU)
+    for (int i = tid; i < GT_N / 8; i += SMALL_THREADS)
+      reinterpret_cast<u32x4*>(s_gt)[i] = reinterpret_cast<const u32x4*>(a.gtab)[i];
+  const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
+  int t = blockIdx.x;
+  const int x0 = (t % ntx) * TX;
+  t /= ntx;
+  const int y0 = (t % nty) * TY;
+  const int z0 = (t / nty) * TZ;
+  {
+    constexpr int IT = (HALO_VOX + SMALL_THREADS - 1) / SMALL_THREADS;
+    const elem_t* gin = static_cast<const elem_t*>(a.in);
+    elem_t r[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * SMALL_THREADS;
+      if (i < HALO_VOX) {
+        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+        const long long gx = pmod(x0 + hx - 1, a.nx), gy = pmod(y0 + hy - 1, a.ny),
+                        gz = pmod(z0 + hz - 1, a.nz);
+        r[k] = gin[(gz * a.ny + gy) * a.nx + gx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * SMALL_THREADS;
+      if (i < HALO_VOX) s_h[i] = r[k];
+    }
+  }
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int zl = wave >> 1, yb = (wave & 1) * 4;
+  // A[o][d] = W[d][o] for o = 16 h + li and this lane's reduction slots d = 8 lg + j
+  bf16x8 aw[2];
+  float bias[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    u32x4 q;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int d = 8 * lg + 2 * k;
+      const unsigned lo = d < 27 ? a.w[d * CH + 16 * h + li] : 0u;
+      const unsigned hi = d + 1 < 27 ? a.w[(d + 1) * CH + 16 * h + li] : 0u;
+      q[k] = lo | (hi << 16);
+    }
+    aw[h] = as_bf16x8(q);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[h][r] = EPI != EPI_DGELU ? a.bias[16 * h + 4 * lg + r] : 0.f;
+  }
+  int rel[8];
+  bool ok[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int d = 8 * lg + j;
+    ok[j] = d < 27;
+    rel[j] = ok[j] ? ((d / 9 - 1) * HY + (d / 3) % 3 - 1) * HX + d % 3 - 1 : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int yl = yb + m;
+    const int base = ((zl + 1) * HY + yl + 1) * HX + li + 1;
+    u32x4 part[NT];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      unsigned lo[NT], hi[NT];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int j = 2 * k + e;
+        float v = 0.f;
+        if (ok[j]) {
+          if constexpr (IN_F32) v = s_h[base + rel[j]];
+          else v = bf2f(s_h[base + rel[j]]);
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const bf16_t hb = f2bf(v);
+          v -= bf2f(hb);
+          (e ? hi : lo)[n] = hb;
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < NT; ++n) part[n][k] = lo[n] | (hi[n] << 16);
+    }
+    f32x4 acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      acc[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[h], as_bf16x8(part[n]), acc[h], 0, 0, 0);
+    }
+    const int x = x0 + li, y = y0 + yl, z = z0 + zl;
+    if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+    const long long v = ((long long)z * a.ny + y) * a.nx + x;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int o0 = 16 * h + 4 * lg;
+      unsigned aw2[2], zw2[2];
+      if constexpr (EPI == EPI_DGELU) {
+        const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
+        const unsigned zz[2] = {zp.x, zp.y};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const bf16_t lo = f2bf(acc[h][2 * k] * gelu_prime(__uint_as_float(zz[k] << 16)));
+          const bf16_t hi =
+              f2bf(acc[h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
+          aw2[k] = unsigned(lo) | (unsigned(hi) << 16);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const bf16_t zlo = f2bf(acc[h][2 * k] + bias[h][2 * k]);
+          const bf16_t zhi = f2bf(acc[h][2 * k + 1] + bias[h][2 * k + 1]);
+          zw2[k] = unsigned(zlo) | (unsigned(zhi) << 16);
+          aw2[k] = unsigned(gelu_bf16(zlo, s_gt)) | (unsigned(gelu_bf16(zhi, s_gt)) << 16);
+        }
+        if constexpr (EPI == EPI_GELU_Z)
+          *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw2[0], zw2[1]);
+      }
+      *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw2[0], aw2[1]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- MFMA 32 -> 1
+// The 32 -> 1 layer (with the residual) with its 27 offsets moved into the GEMM's output: for each
+// halo voxel u, P[u][d] = sum_i W[d][i] a[u][i] on v_mfma_f32_16x16x32_bf16 (A = weights, rows d;
+// B = 16 halo voxels' channels, read straight from memory: 64 contiguous bytes per voxel), then
+// out[v] = c[v] + (sum_d P[v + d][d] + b).  The offsets are taken one z-layer (9 of them) at a
+// time, so P over the 4 halo planes that layer reads (720 voxels, 26 KB) is all the LDS a block
+// needs; each thread sums its voxel's 27 terms in a fixed order.
+constexpr int PO_VOX = TZ * HY * HX;  // 720
+constexpr int PO_GROUPS = PO_VOX / 16;  // 45 MFMA column groups per z-layer
+constexpr int PO_PER_WAVE = (PO_GROUPS + SMALL_THREADS / 64 - 1) / (SMALL_THREADS / 64);  // 6
+static_assert(PO_VOX % 16 == 0, "whole MFMA column groups");
+
+__global__ __launch_bounds__(SMALL_THREADS) void conv_out_mfma(ConvArgs a) {
+  __shared__ float s_p[PO_VOX * 9];
   const int tid = threadIdx.x;
   const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
   int t = blockIdx.x;
@@ -312,159 +489,64 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_small(ConvArgs a) {
   t /= ntx;
   const int y0 = (t % nty) * TY;
   const int z0 = (t / nty) * TZ;
-  // stage the halo: every load of a thread is issued before its LDS writes
-  if constexpr (IN_BYTES % 16 == 0) {
-    constexpr int CPV = IN_BYTES / 16;  // 16-byte chunks per voxel
-    constexpr int IT = (HALO_VOX * CPV + SMALL_THREADS - 1) / SMALL_THREADS;
-    const u32x4* gin = static_cast<const u32x4*>(a.in);
-    u32x4* sv = reinterpret_cast<u32x4*>(s_in);
-    u32x4 r[IT];
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const u32x4* gin = static_cast<const u32x4*>(a.in);
+  // A[d_local][i] = W[9 p + d_local][i] for z-layer p, rows 9..15 zero
+  bf16x8 aw[3];
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int i = tid + k * SMALL_THREADS;
-      if (i < HALO_VOX * CPV) {
-        const int vox = i / CPV, part = i % CPV;
-        const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
-        const long long gx = ((x0 + hx - 1) % a.nx + a.nx) % a.nx,
-                        gy = ((y0 + hy - 1) % a.ny + a.ny) % a.ny,
-                        gz = ((z0 + hz - 1) % a.nz + a.nz) % a.nz;
-        r[k] = gin[((gz * a.ny + gy) * a.nx + gx) * CPV + part];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int i = tid + k * SMALL_THREADS;
-      if (i < HALO_VOX * CPV) sv[i] = r[k];
-    }
-  } else {
-    // one element per voxel (2-byte BF16 or 4-byte FP32)
-    typedef typename std::conditional<IN_F32, unsigned, bf16_t>::type elem_t;
-    constexpr int IT = (HALO_VOX + SMALL_THREADS - 1) / SMALL_THREADS;
-    const elem_t* gin = static_cast<const elem_t*>(a.in);
-    elem_t* se = reinterpret_cast<elem_t*>(s_in);
-    elem_t r[IT];
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int i = tid + k * SMALL_THREADS;
-      if (i < HALO_VOX) {
-        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        const long long gx = ((x0 + hx - 1) % a.nx + a.nx) % a.nx,
-                        gy = ((y0 + hy - 1) % a.ny + a.ny) % a.ny,
-                        gz = ((z0 + hz - 1) % a.nz + a.nz) % a.nz;
-        r[k] = gin[(gz * a.ny + gy) * a.nx + gx];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int i = tid + k * SMALL_THREADS;
-      if (i < HALO_VOX) se[i] = r[k];
-    }
+  for (int p = 0; p < 3; ++p) {
+    u32x4 q = u32x4{0u, 0u, 0u, 0u};
+    if (li < 9) q = *reinterpret_cast<const u32x4*>(a.w + (9 * p + li) * CH + 8 * lg);
+    aw[p] = as_bf16x8(q);
   }
-  if (EPI != EPI_DGELU)
-    for (int i = tid; i < CO; i += SMALL_THREADS) s_b[i] = a.bias[i];
-  __syncthreads();
-
+  // global offsets (16-byte chunks) of this lane's halo voxels: group g = wave + 8 k, voxel li
+  long long src[PO_PER_WAVE];
+#pragma unroll
+  for (int k = 0; k < PO_PER_WAVE; ++k) {
+    const int g = wave + k * (SMALL_THREADS / 64);
+    const int u = (g < PO_GROUPS ? g : 0) * 16 + li;  // voxel within 4 consecutive halo planes
+    const int hx = u % HX, hy = (u / HX) % HY;
+    const long long gx = pmod(x0 + hx - 1, a.nx), gy = pmod(y0 + hy - 1, a.ny);
+    src[k] = (gy * a.nx + gx) * 4 + lg;
+  }
+  const float bias = a.bias[0];
   const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-  float acc[CO];
+  const long long plane4 = (long long)a.ny * a.nx * 4;
+  float acc = 0.f;
 #pragma unroll
-  for (int o = 0; o < CO; ++o) acc[o] = 0.f;
-  if constexpr (!IN_F32 && CI % 8 == 0) {
-    // BF16 pairs straight from LDS into packed dot products (two MACs per instruction, FP32
-    // accumulation); block-uniform BF16 weight pairs come through the scalar cache
-    const unsigned* __restrict__ W2 = reinterpret_cast<const unsigned*>(a.w);
-    for (int d = 0; d < 27; ++d) {
-      const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
-      const int h = ((lz + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
-      const u32x4* p = reinterpret_cast<const u32x4*>(s_in + size_t(h) * IN_BYTES);
-      unsigned xw[CI / 2];
+  for (int p = 0; p < 3; ++p) {  // dz = p - 1: halo planes p .. p + 3
+    u32x4 bq[PO_PER_WAVE];
 #pragma unroll
-      for (int q = 0; q < CI / 8; ++q) {
-        const u32x4 w4 = p[q];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) xw[4 * q + k] = w4[k];
-      }
-#pragma unroll
-      for (int o = 0; o < CO; ++o) {
-        float s = acc[o];
-#pragma unroll
-        for (int i = 0; i < CI / 2; ++i)
-          s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, xw[i]),
-                                              __builtin_bit_cast(bf16x2_t, W2[(d * CO + o) * (CI / 2) + i]),
-                                              s, false);
-        acc[o] = s;
-      }
-    }
-  } else
-  for (int d = 0; d < 27; ++d) {
-    const int dz = d / 9 - 1, dy = (d / 3) % 3 - 1, dx = d % 3 - 1;
-    const int h = ((lz + 1 + dz) * HY + (ly + 1 + dy)) * HX + (lx + 1 + dx);
-    float xin[CI];
-    if constexpr (IN_F32) {
-      xin[0] = reinterpret_cast<const float*>(s_in)[h];
-    } else if constexpr (CI == 1) {
-      xin[0] = bf2f(reinterpret_cast<const bf16_t*>(s_in)[h]);
-    } else {
-      const u32x4* p = reinterpret_cast<const u32x4*>(s_in + size_t(h) * IN_BYTES);
-#pragma unroll
-      for (int q = 0; q < CI / 8; ++q) {
-        const u32x4 w4 = p[q];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          xin[8 * q + 2 * k] = __uint_as_float(w4[k] << 16);
-          xin[8 * q + 2 * k + 1] = __uint_as_float(w4[k] & 0xFFFF0000u);
-        }
-      }
+    for (int k = 0; k < PO_PER_WAVE; ++k) {
+      const int g = wave + k * (SMALL_THREADS / 64);
+      const int u = g * 16 + li;
+      const int pz = u / (HX * HY);
+      bq[k] = u32x4{0u, 0u, 0u, 0u};
+      if (g < PO_GROUPS) bq[k] = gin[pmod(z0 + p + pz - 1, a.nz) * plane4 + src[k]];
     }
 #pragma unroll
-    for (int o = 0; o < CO; ++o) {
-      // multiply-adds may fuse here (the library is otherwise built without contraction)
-#pragma clang fp contract(fast)
-      float s = 0.f;
+    for (int k = 0; k < PO_PER_WAVE; ++k) {
+      const int g = wave + k * (SMALL_THREADS / 64);
+      if (g >= PO_GROUPS) continue;  // wave-uniform
+      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          aw[p], as_bf16x8(bq[k]), f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const int u = g * 16 + li;
 #pragma unroll
-      for (int i = 0; i < CI; ++i) s += W[(d * CO + o) * CI + i] * xin[i];
-      acc[o] += s;
+      for (int r = 0; r < 4; ++r)  // D[4 lg + r][li] = P[u][d_local]
+        if (4 * lg + r < 9) s_p[u * 9 + 4 * lg + r] = d[r];
     }
+    __syncthreads();
+#pragma unroll
+    for (int dyi = 0; dyi < 3; ++dyi)
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi)
+        acc += s_p[((lz * HY + ly + dyi) * HX + lx + dxi) * 9 + 3 * dyi + dxi];
+    __syncthreads();
   }
+  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
   if (x >= a.nx || y >= a.ny || z >= a.nz) return;
   const long long v = ((long long)z * a.ny + y) * a.nx + x;
-  if constexpr (EPI == EPI_RESID) {
-    a.out[v] = a.c[v] + (acc[0] + s_b[0]);
-  } else {
-    // CO == 32: pack pairs of bf16 into words, 4 x 16-byte stores per output array
-    unsigned zw[CO / 2], aw[CO / 2];
-    if constexpr (EPI == EPI_DGELU) {
-      const u32x4* zp = reinterpret_cast<const u32x4*>(a.zprev + v * CO);
-#pragma unroll
-      for (int q = 0; q < CO / 8; ++q) {
-        const u32x4 w4 = zp[q];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int o = 8 * q + 2 * k;
-          const bf16_t lo = f2bf(acc[o] * gelu_prime(__uint_as_float(w4[k] << 16)));
-          const bf16_t hi = f2bf(acc[o + 1] * gelu_prime(__uint_as_float(w4[k] & 0xFFFF0000u)));
-          aw[o / 2] = unsigned(lo) | (unsigned(hi) << 16);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int o = 0; o < CO; o += 2) {
-        const bf16_t z0b = f2bf(acc[o] + s_b[o]), z1b = f2bf(acc[o + 1] + s_b[o + 1]);
-        zw[o / 2] = unsigned(z0b) | (unsigned(z1b) << 16);
-        aw[o / 2] = unsigned(f2bf(gelu(bf2f(z0b)))) | (unsigned(f2bf(gelu(bf2f(z1b)))) << 16);
-      }
-    }
-    u32x4* ap = reinterpret_cast<u32x4*>(a.a_out + v * CO);
-#pragma unroll
-    for (int q = 0; q < CO / 8; ++q)
-      ap[q] = u32x4{aw[4 * q], aw[4 * q + 1], aw[4 * q + 2], aw[4 * q + 3]};
-    if constexpr (EPI == EPI_GELU_Z) {
-      u32x4* zp = reinterpret_cast<u32x4*>(a.z_out + v * CO);
-#pragma unroll
-      for (int q = 0; q < CO / 8; ++q)
-        zp[q] = u32x4{zw[4 * q], zw[4 * q + 1], zw[4 * q + 2], zw[4 * q + 3]};
-    }
-  }
+  a.out[v] = a.c[v] + (acc + bias);
 }
 
 // ----------------------------------------------------------------------------- weight gradient
@@ -477,16 +559,11 @@ constexpr int WT_X = 8, WT_Y = 16, WT_KS = WT_Y / 4;
 constexpr int WG_MAXBLK = 512;   // partial sets of the 32 -> 32 kernel
 constexpr int WG1_MAXBLK = 512;  // partial sets of the one-channel kernel
 
-__device__ __forceinline__ int pmod(int v, int n) {
-  const int r = v % n;
-  return r < 0 ? r + n : r;
-}
 // channel j of two voxels' 8-channel chunks as one dword (voxel a in the low half)
 __device__ __forceinline__ unsigned pack_pair(const u32x4& qa, const u32x4& qb, int j) {
   const unsigned a = qa[j >> 1], b = qb[j >> 1];
   return (j & 1) ? ((a >> 16) | (b & 0xFFFF0000u)) : ((a & 0xFFFFu) | (b << 16));
 }
-__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 // BF16 ones at the k-slots of lane group lg whose voxel is inside the grid
 __device__ __forceinline__ bf16x8 ones_mask(int x0, int nx, bool row_ok) {
   u32x4 m;
@@ -818,6 +895,12 @@ __global__ __launch_bounds__(RED_K * RED_G) void wgrad_reduce(const float* parti
 }
 
 // ----------------------------------------------------------------------------- misc element-wise
+__global__ void fill_gelu_table(bf16_t* tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < GT_N) tab[i] = f2bf(gelu(bf2f(gelu_table_arg(i))));
+}
+
+
 __global__ void cast_bf16(const float* c, bf16_t* out, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = f2bf(c[i]);
@@ -825,19 +908,16 @@ __global__ void cast_bf16(const float* c, bf16_t* out, long long n) {
 
 // master fp32 params -> bf16 weights in [d][o][i] and the flipped/transposed copy
 // wt[26 - d][i][o] used by the backward-data convolutions (grid.y = layer).
-__global__ void refresh_weights(const float* params, bf16_t* w, bf16_t* wt, float* wf,
-                                float* wtf) {
+__global__ void refresh_weights(const float* params, bf16_t* w, bf16_t* wt) {
   const int l = blockIdx.y;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= layer_w(l)) return;
   const bf16_t h = f2bf(params[layer_off(l) + k]);
   w[w_off(l) + k] = h;
-  wf[w_off(l) + k] = bf2f(h);
   const int ci = cin_of(l), co = cout_of(l);
   const int d = int(k / (ci * co)), o = int((k / ci) % co), i = int(k % ci);
   const long long kt = w_off(l) + ((long long)(26 - d) * ci + i) * co + o;
   wt[kt] = h;
-  wtf[kt] = bf2f(h);
 }
 
 struct LossArgs {
@@ -964,9 +1044,8 @@ struct evx_net {
   int device = 0;
   bf16_t* w = nullptr;   // [sum layer_w] bf16
   bf16_t* wt = nullptr;  // flipped/transposed copies
-  float* wf = nullptr;   // BF16-rounded weights as FP32 (VALU layers)
-  float* wtf = nullptr;
   float* params = nullptr;  // device copy of the master weights last set (biases are read here)
+  bf16_t* gtab = nullptr;   // GELU table
   bool have_params = false;
 };
 
@@ -992,16 +1071,15 @@ hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(conv32_mfma<EPI_DGELU>, dim3(grid), dim3(MFMA_THREADS), 0, s, a, ntiles);
   } else if (kind == K_IN1) {
     if (epi == EPI_GELU_Z)
-      hipLaunchKernelGGL((conv_small<1, CH, false, EPI_GELU_Z>), dim3(small_grid),
+      hipLaunchKernelGGL((conv_in_mfma<false, EPI_GELU_Z>), dim3(small_grid),
                          dim3(SMALL_THREADS), 0, s, a);
     else
-      hipLaunchKernelGGL((conv_small<1, CH, false, EPI_GELU>), dim3(small_grid),
+      hipLaunchKernelGGL((conv_in_mfma<false, EPI_GELU>), dim3(small_grid),
                          dim3(SMALL_THREADS), 0, s, a);
   } else if (kind == K_OUT1) {
-    hipLaunchKernelGGL((conv_small<CH, 1, false, EPI_RESID>), dim3(small_grid),
-                       dim3(SMALL_THREADS), 0, s, a);
+    hipLaunchKernelGGL(conv_out_mfma, dim3(small_grid), dim3(SMALL_THREADS), 0, s, a);
   } else {  // backward data of the last layer: FP32 dY -> bf16 dZ
-    hipLaunchKernelGGL((conv_small<1, CH, true, EPI_DGELU>), dim3(small_grid),
+    hipLaunchKernelGGL((conv_in_mfma<true, EPI_DGELU>), dim3(small_grid),
                        dim3(SMALL_THREADS), 0, s, a);
   }
   return hipGetLastError();
@@ -1090,8 +1168,8 @@ ConvArgs conv_args(const evx_net* n, int layer, bool transposed, const void* in,
   ConvArgs a{};
   a.in = in;
   a.w = (transposed ? n->wt : n->w) + w_off(layer);
-  a.wf = (transposed ? n->wtf : n->wf) + w_off(layer);
   a.bias = n->params + layer_off(layer) + layer_w(layer);
+  a.gtab = n->gtab;
   a.nx = nx;
   a.ny = ny;
   a.nz = nz;
@@ -1123,17 +1201,24 @@ evx_status evx_surrogate_create(evx_net** out) {
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, n->device);
   if (e == hipSuccess && cus > 0) g_num_cus = cus;
   const size_t wb = a256(size_t(w_off(NLAYER)) * sizeof(bf16_t));
-  const size_t wfb = a256(size_t(w_off(NLAYER)) * sizeof(float));
-  if (e == hipSuccess) e = hipMalloc(&n->w, 2 * wb + 2 * wfb + a256(NPARAM * sizeof(float)));
+  const size_t pb = a256(NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&n->w, 2 * wb + pb + a256(GT_N * sizeof(bf16_t)));
   if (e != hipSuccess) {
     delete n;
     return nfail(EVX_ERR_HIP, "evx_surrogate_create: %s", hipGetErrorString(e));
   }
   char* base = reinterpret_cast<char*>(n->w);
   n->wt = reinterpret_cast<bf16_t*>(base + wb);
-  n->wf = reinterpret_cast<float*>(base + 2 * wb);
-  n->wtf = reinterpret_cast<float*>(base + 2 * wb + wfb);
-  n->params = reinterpret_cast<float*>(base + 2 * wb + 2 * wfb);
+  n->params = reinterpret_cast<float*>(base + 2 * wb);
+  n->gtab = reinterpret_cast<bf16_t*>(base + 2 * wb + pb);
+  hipLaunchKernelGGL(fill_gelu_table, dim3((GT_N + 255) / 256), dim3(256), 0, nullptr, n->gtab);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(n->w);
+    delete n;
+    return nfail(EVX_ERR_HIP, "evx_surrogate_create: %s", hipGetErrorString(e));
+  }
   *out = n;
   return EVX_OK;
 }
@@ -1153,7 +1238,7 @@ evx_status evx_surrogate_set_params(evx_net* n, const float* params, void* strea
   if (e != hipSuccess) return nfail(EVX_ERR_HIP, "set_params copy: %s", hipGetErrorString(e));
   const long long nw = layer_w(1);  // the largest layer bounds the per-layer index range
   hipLaunchKernelGGL(refresh_weights, dim3(unsigned((nw + 255) / 256), NLAYER), dim3(256), 0, s,
-                     n->params, n->w, n->wt, n->wf, n->wtf);
+                     n->params, n->w, n->wt);
   e = hipGetLastError();
   if (e != hipSuccess) return nfail(EVX_ERR_HIP, "set_params: %s", hipGetErrorString(e));
   n->have_params = true;

@@ -106,6 +106,28 @@ def test_train_step_layers_match_oracle(evx_gpu, n):
         assert np.linalg.norm(got_b - gb) <= 1e-4 * np.linalg.norm(gb) + 1e-12, li
 
 
+def test_gelu_over_wide_preactivations(evx_gpu):
+    """First-layer weights scaled up so that its BF16 pre-activations reach past +-8 and down to
+    below 2^-8 in magnitude: the stored activations equal bf16(GELU(z)) of the FP64 oracle on every
+    range the GPU evaluates differently (table, small-argument series, large-argument paths)."""
+    from paper_2507_21748_amd.surrogate import Net
+    theta = _params(9).astype(np.float64)
+    (w_shape, b_shape) = S.layer_shapes()[0]
+    nw = int(np.prod(w_shape)) + b_shape[0]
+    theta[:nw] *= 4.0  # z in about [-11.4, 11.9]: no FP32 denormal results
+    net = Net(theta.astype(np.float32))
+    n = 24
+    c = torch.from_numpy(quench_field((n, n, n), 0.0, 0.8, seed=26)).cuda()[None].contiguous()
+    net.train_step(c, c, 4, lr=1e-30)
+    torch.cuda.synchronize()
+    b = net.train_buffers(n)
+    z = _bf(b["z1"])
+    a = _bf(b["a1"])
+    assert (z >= 8).any() and (z <= -8).any() and ((np.abs(z) < 2.0 ** -8) & (z != 0)).any()
+    exact = S.gelu(z)
+    _rounded_close(a, exact, np.abs(exact))
+
+
 def test_infer_equals_training_forward(evx_gpu):
     from paper_2507_21748_amd.surrogate import Net
     n = 24
