@@ -1,6 +1,7 @@
 // Pass schedules of the adjoint step and of the diagnostics (shared by the HIP launcher and the
-// host emulator).  A launcher L additionally provides spec(SpecArgs), realsum(RealSumArgs),
-// final(FinalArgs) and combine(CombineArgs).
+// host emulator).  A launcher L additionally provides col_batch / row_batch (one pass over a
+// PassBatch of buffer pairs), spec(SpecArgs), realsum(RealSumArgs), final(FinalArgs) and
+// combine(CombineArgs).
 //
 // Adjoint of one step c^{n+1} = A c^n - B f'(c^n), A = T^{-1} diag(G P) T,
 // B = T^{-1} diag(dt M K2 G) T (both symmetric):
@@ -75,14 +76,24 @@ template <class L>
 void sched_adjoint(L& l, const Geom& g, const TablePtrs& t, const float* c, float* lam,
                    const AdjointBufs& b, const AdjointCoef& co, double* dk, double* dM,
                    int remap) {
-  sched_forward(l, g, t, c, b.A, false, remap);
-  sched_forward(l, g, t, c, b.B, true, remap);
-  sched_forward(l, g, t, lam, b.Lm, false, remap);
+  // forward transforms of c, f'(c) and lam (A, B, Lm), each pass batched over the buffers
+  const PassBatch rows_fwd{{c, lam, nullptr}, {b.A, b.Lm, nullptr}, 2};
+  l.row_batch(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, c, b.A, nullptr), rows_fwd);
+  l.row(g.row_len, g.bc, ROW_FWD_FP, x_args(g, t, nullptr, c, b.B, nullptr));
+  const PassBatch spec3{{b.A, b.B, b.Lm}, {b.A, b.B, b.Lm}, 3};
+  l.col_batch(g.ny, g.bc, COL_FWD, y_args(g, t, b.A, b.A, remap), spec3);
+  l.col_batch(g.nz, g.bc, COL_FWD, z_args(g, t, b.A, b.A, nullptr, StepCoef{0, 0, 0}, remap),
+              spec3);
   l.spec(spec_args(g, t, b, co, 0));
   const double norm = (g.bc == BC_PERIODIC) ? 1.0 / double(g.V) : 1.0;
   l.final(FinalArgs{b.partial, AUX_BLOCKS, dk, dM, norm, norm, 1, 1});
-  sched_inverse(l, g, t, b.Lm, lam, remap);
-  sched_inverse(l, g, t, b.B, b.v, remap);
+  // inverse transforms: Lm -> lam, B -> v
+  const PassBatch spec2{{b.Lm, b.B, nullptr}, {b.Lm, b.B, nullptr}, 2};
+  l.col_batch(g.nz, g.bc, COL_INV, z_args(g, t, b.Lm, b.Lm, nullptr, StepCoef{0, 0, 0}, remap),
+              spec2);
+  l.col_batch(g.ny, g.bc, COL_INV, y_args(g, t, b.Lm, b.Lm, remap), spec2);
+  const PassBatch rows_inv{{b.Lm, b.B, nullptr}, {lam, b.v, nullptr}, 2};
+  l.row_batch(g.row_len, g.bc, ROW_INV, x_args(g, t, b.Lm, nullptr, nullptr, lam), rows_inv);
   l.combine(CombineArgs{lam, c, b.v, g.V});
 }
 

@@ -1,6 +1,7 @@
 // __global__ wrappers of the pass bodies for one transform length.  This file is compiled once
 // per supported length (EVX_INST_N) so the instantiations build in parallel; each object exports
-// evx_launch_col_<N> and evx_launch_row_<N>.
+// evx_launch_col_<N> and evx_launch_row_<N> (and their batched forms evx_launch_colb_<N>,
+// evx_launch_rowb_<N>).
 #include "evx_launch.hpp"
 
 #ifndef EVX_INST_N
@@ -15,6 +16,14 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_kernel(ColArgs a) {
   colpass_body<N, BC, MODE>(a, threadIdx.x, blockIdx.x, gridDim.x, lds);
 }
 
+// the same passes over a batch of buffer pairs (grid.y = pair)
+template <int N, int BC, int MODE>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void col_kernel_batch(ColArgs a, PassBatch p) {
+  __shared__ float2 lds[ColCfg<N>::LDS];
+  bind_batch(a, p, blockIdx.y);
+  colpass_body<N, BC, MODE>(a, threadIdx.x, blockIdx.x, gridDim.x, lds);
+}
+
 template <int NH, int BC>
 constexpr int row_threads() {
   return RowCfg<NH, BC>::THREADS;
@@ -23,6 +32,13 @@ constexpr int row_threads() {
 template <int NH, int BC, int MODE>
 __global__ __launch_bounds__((row_threads<NH, BC>())) void row_kernel(RowArgs a) {
   __shared__ float2 lds[RowCfg<NH, BC>::LDS];
+  rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, lds);
+}
+
+template <int NH, int BC, int MODE>
+__global__ __launch_bounds__((row_threads<NH, BC>())) void row_kernel_batch(RowArgs a, PassBatch p) {
+  __shared__ float2 lds[RowCfg<NH, BC>::LDS];
+  bind_batch(a, MODE == ROW_INV, p, blockIdx.y);
   rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, lds);
 }
 
@@ -51,6 +67,35 @@ static hipError_t row_go(const RowArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Batched launches check every pair's buffers like the single ones (the geometry is shared).
+template <int N, int BC, int MODE>
+static hipError_t col_go_batch(const ColArgs& a, const PassBatch& p, hipStream_t s) {
+  using C = ColCfg<N>;
+  const long long nblk = (a.nseq + C::B - 1) / C::B;
+  if (nblk <= 0) return hipSuccess;
+  if (p.n < 1 || p.n > 3) return hipErrorInvalidValue;
+  const long long lane_bytes = col_lane_bytes<N>(a);
+  if (nblk > 0x7fffffffLL || a.nseq > 0x7fffffffLL || lane_bytes >= (long long)kDeadLane)
+    return hipErrorInvalidConfiguration;
+  ColArgs b = a;
+  b.lane_bytes = unsigned(lane_bytes);
+  hipLaunchKernelGGL((col_kernel_batch<N, BC, MODE>), dim3(unsigned(nblk), unsigned(p.n)),
+                     dim3(C::THREADS), 0, s, b, p);
+  return hipGetLastError();
+}
+
+template <int NH, int BC, int MODE>
+static hipError_t row_go_batch(const RowArgs& a, const PassBatch& p, hipStream_t s) {
+  using C = RowCfg<NH, BC>;
+  const long long nblk = (a.nrows + C::ROWS - 1) / C::ROWS;
+  if (nblk <= 0) return hipSuccess;
+  if (p.n < 1 || p.n > 3) return hipErrorInvalidValue;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((row_kernel_batch<NH, BC, MODE>), dim3(unsigned(nblk), unsigned(p.n)),
+                     dim3(C::THREADS), 0, s, a, p);
+  return hipGetLastError();
+}
+
 template <int N, int BC>
 static hipError_t col_mode(int mode, const ColArgs& a, hipStream_t s) {
   switch (mode) {
@@ -74,6 +119,25 @@ static hipError_t row_mode(int mode, const RowArgs& a, hipStream_t s) {
   }
 }
 
+template <int N, int BC>
+static hipError_t col_mode_batch(int mode, const ColArgs& a, const PassBatch& p, hipStream_t s) {
+  switch (mode) {
+    case COL_FWD: return col_go_batch<N, BC, COL_FWD>(a, p, s);
+    case COL_INV: return col_go_batch<N, BC, COL_INV>(a, p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NH, int BC>
+static hipError_t row_mode_batch(int mode, const RowArgs& a, const PassBatch& p, hipStream_t s) {
+  switch (mode) {
+    case ROW_FWD: return row_go_batch<NH, BC, ROW_FWD>(a, p, s);
+    case ROW_INV: return row_go_batch<NH, BC, ROW_INV>(a, p, s);
+    case ROW_FWD_FP: return row_go_batch<NH, BC, ROW_FWD_FP>(a, p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 #define EVX_PASTE2(a, b) a##b
 #define EVX_PASTE(a, b) EVX_PASTE2(a, b)
 
@@ -87,6 +151,18 @@ hipError_t EVX_PASTE(evx_launch_row_, EVX_INST_N)(int bc, int mode, const RowArg
                                                   hipStream_t s) {
   return bc == BC_PERIODIC ? row_mode<EVX_INST_N, BC_PERIODIC>(mode, a, s)
                            : row_mode<EVX_INST_N, BC_ZERO_FLUX>(mode, a, s);
+}
+
+hipError_t EVX_PASTE(evx_launch_colb_, EVX_INST_N)(int bc, int mode, const ColArgs& a,
+                                                   const PassBatch& p, hipStream_t s) {
+  return bc == BC_PERIODIC ? col_mode_batch<EVX_INST_N, BC_PERIODIC>(mode, a, p, s)
+                           : col_mode_batch<EVX_INST_N, BC_ZERO_FLUX>(mode, a, p, s);
+}
+
+hipError_t EVX_PASTE(evx_launch_rowb_, EVX_INST_N)(int bc, int mode, const RowArgs& a,
+                                                   const PassBatch& p, hipStream_t s) {
+  return bc == BC_PERIODIC ? row_mode_batch<EVX_INST_N, BC_PERIODIC>(mode, a, p, s)
+                           : row_mode_batch<EVX_INST_N, BC_ZERO_FLUX>(mode, a, p, s);
 }
 
 }  // namespace evx

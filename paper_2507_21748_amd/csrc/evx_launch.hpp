@@ -10,7 +10,11 @@ namespace evx {
 
 #define EVX_DECL(N)                                                                     \
   hipError_t evx_launch_col_##N(int bc, int mode, const ColArgs& a, hipStream_t s);      \
-  hipError_t evx_launch_row_##N(int bc, int mode, const RowArgs& a, hipStream_t s);
+  hipError_t evx_launch_row_##N(int bc, int mode, const RowArgs& a, hipStream_t s);      \
+  hipError_t evx_launch_colb_##N(int bc, int mode, const ColArgs& a, const PassBatch& p, \
+                                 hipStream_t s);                                         \
+  hipError_t evx_launch_rowb_##N(int bc, int mode, const RowArgs& a, const PassBatch& p, \
+                                 hipStream_t s);
 EVX_FOR_EACH_N(EVX_DECL)
 #undef EVX_DECL
 
@@ -30,6 +34,26 @@ struct HipLauncher {
     switch (n) {
 #define EVX_CASE(N) \
   case N: err = evx_launch_col_##N(bc, mode, a, stream); return;
+      EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+      default: bad_len = true;
+    }
+  }
+  void col_batch(int n, int bc, int mode, const ColArgs& a, const PassBatch& p) {
+    if (err != hipSuccess || bad_len) return;
+    switch (n) {
+#define EVX_CASE(N) \
+  case N: err = evx_launch_colb_##N(bc, mode, a, p, stream); return;
+      EVX_FOR_EACH_N(EVX_CASE)
+#undef EVX_CASE
+      default: bad_len = true;
+    }
+  }
+  void row_batch(int n, int bc, int mode, const RowArgs& a, const PassBatch& p) {
+    if (err != hipSuccess || bad_len) return;
+    switch (n) {
+#define EVX_CASE(N) \
+  case N: err = evx_launch_rowb_##N(bc, mode, a, p, stream); return;
       EVX_FOR_EACH_N(EVX_CASE)
 #undef EVX_CASE
       default: bad_len = true;

@@ -72,6 +72,29 @@ struct RowArgs {
   float scale;         // 1/V (periodic) or 1/(8V) (zero flux), applied after the inverse
 };
 
+// One launch of the same transform pass over up to three independent (in, out) buffer pairs: the
+// grid's y index selects the pair (the small-grid adjoint runs its transforms this way, which
+// halves its launches).
+struct PassBatch {
+  const void* in[3];
+  void* out[3];
+  int n;
+};
+EVX_HD void bind_batch(ColArgs& a, const PassBatch& b, int k) {
+  a.in = static_cast<const float2*>(b.in[k]);
+  a.out = static_cast<float2*>(b.out[k]);
+}
+// forward modes read real rows and write complex ones; the inverse does the opposite
+EVX_HD void bind_batch(RowArgs& a, bool inverse, const PassBatch& b, int k) {
+  if (inverse) {
+    a.in_c = static_cast<const float2*>(b.in[k]);
+    a.out_r = static_cast<float*>(b.out[k]);
+  } else {
+    a.in_r = static_cast<const float*>(b.in[k]);
+    a.out_c = static_cast<float2*>(b.out[k]);
+  }
+}
+
 // Block order: consecutive logical blocks (neighbouring columns, sharing 128-byte lines) are
 // placed on the same XCD.  Hardware dispatches block i to XCD i % 8.
 EVX_DEV int remap_block(int bid, int nblk, int on) {

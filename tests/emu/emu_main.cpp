@@ -102,6 +102,21 @@ struct EmuLauncher {
       default: std::fprintf(stderr, "unsupported column length %d\n", n); std::exit(3);
     }
   }
+  // a batched pass runs its pairs one after another (they are independent)
+  void col_batch(int n, int bc, int mode, const ColArgs& a, const PassBatch& p) {
+    for (int k = 0; k < p.n; ++k) {
+      ColArgs b = a;
+      bind_batch(b, p, k);
+      col(n, bc, mode, b);
+    }
+  }
+  void row_batch(int n, int bc, int mode, const RowArgs& a, const PassBatch& p) {
+    for (int k = 0; k < p.n; ++k) {
+      RowArgs b = a;
+      bind_batch(b, mode == ROW_INV, p, k);
+      row(n, bc, mode, b);
+    }
+  }
   void spec(const SpecArgs& a) {
     run_grid(AUX_BLOCKS, AUX_THREADS, 2 * AUX_THREADS, [&](int tid, int bid, int nb, float2* lds) {
       spec_body(a, tid, bid, nb, reinterpret_cast<double*>(lds));
