@@ -171,8 +171,6 @@ constexpr int HALO_CHUNKS = HALO_VOX * 4;        // 16-byte chunks (64 B per vox
 constexpr int W_CHUNKS = 27 * CH * CH * 2 / 16;  // 3456
 
 constexpr int HALO_IT = (HALO_CHUNKS + MFMA_THREADS - 1) / MFMA_THREADS;  // 9
-constexpr int ACC_STRIDE = CH + 1;  // floats per voxel row of the epilogue staging (bank spread)
-static_assert(TX * TY * TZ * ACC_STRIDE * 4 <= HALO_VOX * CH * 2, "epilogue staging fits");
 
 // Persistent: each block stages the weights once and walks tiles blockIdx.x, +gridDim.x, ...;
 // the next tile's halo is loaded into registers while the current one is computed.
@@ -227,7 +225,11 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
   const int zl = wave >> 1;          // output z within the tile
   const int yb = (wave & 1) * 4;     // first of the wave's 4 output rows
   const int li = lane & 15, lg = lane >> 4;
-  float* s_acc = reinterpret_cast<float*>(s_in);
+  float bias[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[h][r] = EPI != EPI_DGELU ? a.bias[16 * h + 4 * lg + r] : 0.f;
 
   for (; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % ntx) * TX;
@@ -271,57 +273,46 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
             if (dyi < 0 || dyi > 2) continue;
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-              acc[m][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dyi][h], acc[m][h], 0, 0, 0);
+              acc[m][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[dyi][h], av, acc[m][h], 0, 0, 0);
           }
         }
       }
     }
-    // stage the FP32 accumulators as [voxel][channel] (D[i][n]: voxel x offset 4 lg + r,
-    // channel 16 h + li), then leave with 16-byte stores
-    __syncthreads();
+    // D[o][v] of lane (li, lg), element r: channel 16 h + 4 lg + r of voxel x0 + li in output
+    // row m, so each lane leaves 4 consecutive channels of one voxel as an 8-byte store
+    const int y = y0 + yb, z = z0 + zl, x = x0 + li;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m) {
+      if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
+      const long long v = ((long long)z * a.ny + y + m) * a.nx + x;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int vl = (zl * TY + yb + m) * TX + 4 * lg + r;
+      for (int h = 0; h < 2; ++h) {
+        const int o0 = 16 * h + 4 * lg;
+        unsigned aw[2], zw[2];
+        if constexpr (EPI == EPI_DGELU) {
+          const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
+          const unsigned zz[2] = {zp.x, zp.y};
 #pragma unroll
-        for (int h = 0; h < 2; ++h) s_acc[vl * ACC_STRIDE + 16 * h + li] = acc[m][h][r];
-      }
-    __syncthreads();
+          for (int k = 0; k < 2; ++k) {
+            const bf16_t lo = f2bf(acc[m][h][2 * k] * gelu_prime(__uint_as_float(zz[k] << 16)));
+            const bf16_t hi =
+                f2bf(acc[m][h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
+            aw[k] = unsigned(lo) | (unsigned(hi) << 16);
+          }
+        } else {
 #pragma unroll
-    for (int k = 0; k < (TX * TY * TZ * 4) / MFMA_THREADS; ++k) {
-      const int item = tid + k * MFMA_THREADS;
-      const int vl = item >> 2, g = item & 3;
-      const int x = x0 + vl % TX, y = y0 + (vl / TX) % TY, z = z0 + vl / (TX * TY);
-      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-      const long long v = ((long long)z * a.ny + y) * a.nx + x;
-      float val[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) val[j] = s_acc[vl * ACC_STRIDE + 8 * g + j];
-      unsigned aw[4], zw[4];
-      if constexpr (EPI == EPI_DGELU) {
-        const u32x4 zp = reinterpret_cast<const u32x4*>(a.zprev + v * CH)[g];
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) {
-          const bf16_t lo = f2bf(val[2 * k2] * gelu_prime(__uint_as_float(zp[k2] << 16)));
-          const bf16_t hi =
-              f2bf(val[2 * k2 + 1] * gelu_prime(__uint_as_float(zp[k2] & 0xFFFF0000u)));
-          aw[k2] = unsigned(lo) | (unsigned(hi) << 16);
+          for (int k = 0; k < 2; ++k) {
+            const bf16_t zlo = f2bf(acc[m][h][2 * k] + bias[h][2 * k]);
+            const bf16_t zhi = f2bf(acc[m][h][2 * k + 1] + bias[h][2 * k + 1]);
+            zw[k] = unsigned(zlo) | (unsigned(zhi) << 16);
+            // evaluated, not looked up: here the table's LDS reads cost more than they save
+            aw[k] = unsigned(f2bf(gelu(bf2f(zlo)))) | (unsigned(f2bf(gelu(bf2f(zhi)))) << 16);
+          }
+          if constexpr (EPI == EPI_GELU_Z)
+            *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw[0], zw[1]);
         }
-      } else {
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) {
-          const int o = 8 * g + 2 * k2;
-          const bf16_t zlo = f2bf(val[2 * k2] + a.bias[o]);
-          const bf16_t zhi = f2bf(val[2 * k2 + 1] + a.bias[o + 1]);
-          zw[k2] = unsigned(zlo) | (unsigned(zhi) << 16);
-          // evaluated, not looked up: here the table's LDS reads cost more than they save
-          aw[k2] = unsigned(f2bf(gelu(bf2f(zlo)))) | (unsigned(f2bf(gelu(bf2f(zhi)))) << 16);
-        }
-        if constexpr (EPI == EPI_GELU_Z)
-          reinterpret_cast<u32x4*>(a.z_out + v * CH)[g] = u32x4{zw[0], zw[1], zw[2], zw[3]};
+        *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw[0], aw[1]);
       }
-      reinterpret_cast<u32x4*>(a.a_out + v * CH)[g] = u32x4{aw[0], aw[1], aw[2], aw[3]};
     }
   }
 }
