@@ -158,7 +158,7 @@ struct ConvArgs {
   const bf16_t* zprev;   // EPI_DGELU: pre-activation of the layer below [V][Cout]
   const float* c;        // EPI_RESID: network input (fp32)
   float* out;            // EPI_RESID
-  const bf16_t* gtab;    // GELU table (GT_N entries), for conv_in_mfma's GELU epilogues
+  const bf16_t* gtab;    // GELU table (GT_N entries), for the GELU epilogues
   int nx, ny, nz;
 };
 
@@ -178,7 +178,11 @@ template <int EPI>
 __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntiles) {
   __shared__ __attribute__((aligned(16))) bf16_t s_in[HALO_VOX * CH];
   __shared__ __attribute__((aligned(16))) bf16_t s_w[27 * CH * CH];
+  __shared__ __attribute__((aligned(16))) bf16_t s_gt[GT_N];
   const int tid = threadIdx.x;
+  if (EPI != EPI_DGELU)
+    for (int i = tid; i < GT_N / 8; i += MFMA_THREADS)
+      reinterpret_cast<u32x4*>(s_gt)[i] = reinterpret_cast<const u32x4*>(a.gtab)[i];
   const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
   const u32x4* gin = static_cast<const u32x4*>(a.in);
   u32x4* sin4 = reinterpret_cast<u32x4*>(s_in);
@@ -305,8 +309,7 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
             const bf16_t zlo = f2bf(acc[m][h][2 * k] + bias[h][2 * k]);
             const bf16_t zhi = f2bf(acc[m][h][2 * k + 1] + bias[h][2 * k + 1]);
             zw[k] = unsigned(zlo) | (unsigned(zhi) << 16);
-            // evaluated, not looked up: here the table's LDS reads cost more than they save
-            aw[k] = unsigned(f2bf(gelu(bf2f(zlo)))) | (unsigned(f2bf(gelu(bf2f(zhi)))) << 16);
+            aw[k] = unsigned(gelu_bf16(zlo, s_gt)) | (unsigned(gelu_bf16(zhi, s_gt)) << 16);
           }
           if constexpr (EPI == EPI_GELU_Z)
             *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw[0], zw[1]);
