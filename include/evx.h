@@ -51,14 +51,28 @@ typedef enum evx_status {
 typedef enum evx_bc { EVX_BC_PERIODIC = 0, EVX_BC_ZERO_FLUX = 1 } evx_bc;
 typedef enum evx_scheme { EVX_SCHEME_SPECTRAL = 0, EVX_SCHEME_STENCIL7 = 1 } evx_scheme;
 
+/* Time integrator of evx_ch_advance / evx_ch_step.  Both split the k-space right-hand side as
+ * dC/dt = S C + N, S = -(M kappa K2^2 + A K2), N = -M K2 F + A K2 C (F = T[f'(c)]):
+ *   EVX_INTEGRATOR_SEMI_IMPLICIT: C' = (C + dt N) / (1 - dt S)  (Appendix, semi-implicit step);
+ *   EVX_INTEGRATOR_ETD1: first-order exponential time differencing, one of the exponential
+ *     integrators the paper lists among the supported steppers:
+ *     C' = exp(dt S) C + dt phi1(dt S) N, phi1(z) = (exp(z) - 1) / z. */
+typedef enum evx_integrator {
+  EVX_INTEGRATOR_SEMI_IMPLICIT = 0,
+  EVX_INTEGRATOR_ETD1 = 1
+} evx_integrator;
+
 /* Per-call physics: time step, mobility, gradient-energy coefficient, stabilisation.  They are
  * per call (not plan fields) so gradient loops over kappa and M never re-plan.  A multiplies
- * dt K2 alone (not M): P = 1 + A dt K2. */
+ * dt K2 alone (not M): P = 1 + A dt K2.  integrator is an evx_integrator (0, the semi-implicit
+ * step, when the struct is zero-initialised past A); the adjoint supports the semi-implicit step
+ * only (EVX_ERR_UNSUPPORTED otherwise). */
 typedef struct evx_ch_params {
   double dt;
   double M;
   double kappa;
   double A;
+  int integrator;
 } evx_ch_params;
 
 /* Workspace users (bit mask for evx_plan_workspace_bytes). */

@@ -104,6 +104,7 @@ static hipError_t col_mode(int mode, const ColArgs& a, hipStream_t s) {
     case COL_Z_INIT: return col_go<N, BC, COL_Z_INIT>(a, s);
     case COL_Z_UPDATE: return col_go<N, BC, COL_Z_UPDATE>(a, s);
     case COL_Z_INV_STATE: return col_go<N, BC, COL_Z_INV_STATE>(a, s);
+    case COL_Z_ETD: return col_go<N, BC, COL_Z_ETD>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

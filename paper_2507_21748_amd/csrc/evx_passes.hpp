@@ -29,7 +29,8 @@ enum : int {
   COL_INV = 1,         // in -> inverse transform -> out
   COL_Z_INIT = 2,      // in -> forward -> state; -> inverse -> out
   COL_Z_UPDATE = 3,    // in -> forward -> k-space update of state -> inverse -> out
-  COL_Z_INV_STATE = 4  // state -> inverse -> out
+  COL_Z_INV_STATE = 4, // state -> inverse -> out
+  COL_Z_ETD = 5        // as COL_Z_UPDATE with the exponential (ETD1) update
 };
 
 // row (x) pass modes
@@ -275,9 +276,10 @@ template <int N, int BC, int MODE>
 EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* lds) {
   using C = ColCfg<N>;
   constexpr int E = C::E, TPS = C::TPS, B = C::B;
-  constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE;
+  constexpr bool has_fwd =
+      MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE || MODE == COL_Z_ETD;
   constexpr bool has_inv = MODE != COL_FWD;
-  constexpr bool upd = MODE == COL_Z_UPDATE;
+  constexpr bool upd = MODE == COL_Z_UPDATE || MODE == COL_Z_ETD;
   constexpr bool zf = BC == BC_ZERO_FLUX;
   const int b = tid % B;
   const int t = tid / B;
@@ -355,11 +357,22 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
       const float2 Cs = cs[e];
       const float2 F = x[e];
       const float K2a = kca + kr, K2b = kcb + kr;
-      const float Pa = 1.0f + a.a_dt * K2a, Pb = 1.0f + a.a_dt * K2b;
-      const float Ga = evx_rcp(1.0f + a.dt_m_kappa * K2a * K2a + a.a_dt * K2a);
-      const float Gb = evx_rcp(1.0f + a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
-      x[e] = make_float2(Ga * (Pa * Cs.x - a.dt_m * K2a * F.x),
-                         Gb * (Pb * Cs.y - a.dt_m * K2b * F.y));
+      if constexpr (MODE == COL_Z_ETD) {
+        // C' = C + phi1(dt S) dt R, dt S = -(dt M kappa K2^2 + A dt K2),
+        // dt R = -(dt M K2 F + dt M kappa K2^2 C); phi1(0) = 1 keeps the DC bin exact
+        const float sa = -(a.dt_m_kappa * K2a * K2a + a.a_dt * K2a);
+        const float sb = -(a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
+        const float pa = evx_phi1(sa), pb = evx_phi1(sb);
+        const float ra = -(a.dt_m * K2a * F.x + a.dt_m_kappa * K2a * K2a * Cs.x);
+        const float rb = -(a.dt_m * K2b * F.y + a.dt_m_kappa * K2b * K2b * Cs.y);
+        x[e] = make_float2(Cs.x + pa * ra, Cs.y + pb * rb);
+      } else {
+        const float Pa = 1.0f + a.a_dt * K2a, Pb = 1.0f + a.a_dt * K2b;
+        const float Ga = evx_rcp(1.0f + a.dt_m_kappa * K2a * K2a + a.a_dt * K2a);
+        const float Gb = evx_rcp(1.0f + a.dt_m_kappa * K2b * K2b + a.a_dt * K2b);
+        x[e] = make_float2(Ga * (Pa * Cs.x - a.dt_m * K2a * F.x),
+                           Gb * (Pb * Cs.y - a.dt_m * K2b * F.y));
+      }
       evx_buf_store2(ct.sres(a.state, e), ct.so, x[e]);
     });
   }

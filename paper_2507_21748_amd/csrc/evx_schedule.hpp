@@ -223,12 +223,12 @@ void sched_begin(L& l, const Geom& g, const TablePtrs& t, const float* c, float2
 // nsteps steps; W must hold F_z^{-1} S on entry and holds it again on exit.
 template <class L>
 void sched_advance(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, StepCoef c,
-                   int nsteps, int remap) {
+                   int nsteps, int remap, int zmode = COL_Z_UPDATE) {
   for (int n = 0; n < nsteps; ++n) {
     l.col(g.ny, g.bc, COL_INV, y_args(g, t, W, W, remap));
     l.row(g.row_len, g.bc, ROW_FUSED, x_args(g, t, W, nullptr, W, nullptr));
     l.col(g.ny, g.bc, COL_FWD, y_args(g, t, W, W, remap));
-    l.col(g.nz, g.bc, COL_Z_UPDATE, z_args(g, t, W, W, S, c, remap));
+    l.col(g.nz, g.bc, zmode, z_args(g, t, W, W, S, c, remap));
   }
 }
 

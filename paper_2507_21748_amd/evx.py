@@ -11,7 +11,8 @@ from dataclasses import dataclass
 
 import torch
 
-__all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME"]
+__all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME", "SEMI_IMPLICIT",
+           "ETD1"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -30,7 +31,10 @@ class EvxError(RuntimeError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("M", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("A", ctypes.c_double)]
+                ("A", ctypes.c_double), ("integrator", ctypes.c_int)]
+
+
+SEMI_IMPLICIT, ETD1 = 0, 1  # evx_integrator
 
 
 @dataclass(frozen=True)
@@ -39,9 +43,10 @@ class CHParams:
     M: float = 1.0
     kappa: float = 1.0
     A: float = 2.0
+    integrator: int = SEMI_IMPLICIT
 
     def c(self) -> _Params:
-        return _Params(self.dt, self.M, self.kappa, self.A)
+        return _Params(self.dt, self.M, self.kappa, self.A, self.integrator)
 
 
 def lib_path() -> str:

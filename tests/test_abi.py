@@ -72,3 +72,28 @@ def test_null_arguments(lib):
     assert lib.evx_plan_destroy(None) == 1
     assert lib.evx_ch_step(None, None, 1, None, None) == 1
     assert lib.evx_ch_advance(None, 1, None, None) == 1
+
+
+def test_params_struct_layout_matches_header(tmp_path):
+    """The binding's evx_ch_params mirrors the C struct: size and every field offset, as the host
+    compiler lays it out from include/evx.h."""
+    import shutil
+    import subprocess
+    from paper_2507_21748_amd.evx import _Params
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "evx.h"\nint main(void) {\n'
+                   '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(evx_ch_params),\n'
+                   '         offsetof(evx_ch_params, dt), offsetof(evx_ch_params, M),\n'
+                   '         offsetof(evx_ch_params, kappa), offsetof(evx_ch_params, A),\n'
+                   '         offsetof(evx_ch_params, integrator));\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [ctypes.sizeof(_Params)] + [getattr(_Params, f).offset
+                                       for f in ("dt", "M", "kappa", "A", "integrator")]
+    assert got == want
