@@ -33,6 +33,13 @@ dC/dt = S C + N(C), S = -(M kappa K2^2 + A K2), N = -M K2 F + A K2 C, and steps
 i.e. in the increment form c^{n+1} = c^n + T^{-1}{ dt phi1(dt S) T{rhs(c^n)} }: the multiplier
 dt / (1 - dt S) is replaced by dt phi1(dt S).
 
+The Allen-Cahn model (the paper's first-order-transformation kinetics: linear relaxation of the
+same free energy towards its minimum) is dc/dt = -M (f'(c) - kappa lap c), M the kinetic
+coefficient.  Its split is S = -(M kappa K2 + A), N = -M F + A C (stabilisation A C rather than
+A K2 C), so the semi-implicit step is the linear solve
+        ((1 + A dt) I - dt M kappa L) c^{n+1} = (1 + A dt) c^n - dt M f'(c^n)
+and the ETD1 step is C' = C + dt phi1(dt S) R with R = -M F - M kappa K2 C.
+
 Both forms are implemented here independently (k-space form with spectral multipliers; increment
 form with a real-space 7-point stencil for the stencil scheme) and the tests assert that they agree.
 """
@@ -47,6 +54,7 @@ __all__ = [
     "CHParams", "axis_k2", "k2_grid", "T", "Tinv", "fprime", "fsecond", "fwell",
     "ch_step", "ch_step_increment", "ch_run", "laplacian", "energy", "mass", "growth_factor",
     "ch_step_etd1", "ch_run_etd1", "growth_factor_etd1", "phi1",
+    "ac_step", "ac_step_etd1", "ac_run", "ac_growth_factor",
 ]
 
 WORKERS = 1  # scipy.fft threads; the CPU-baseline leg raises it to the host core count
@@ -170,6 +178,50 @@ def growth_factor_etd1(K2, cbar: float, p: CHParams):
     lam = -p.M * K2 * (fsecond(cbar) + p.kappa * K2)
     S = -(p.M * p.kappa * K2 * K2 + p.A * K2)
     return 1.0 + p.dt * phi1(p.dt * S) * lam
+
+
+def ac_step(c, p: CHParams, bc: str, scheme: str):
+    """One semi-implicit Allen-Cahn step: C' = G (P C - dt M F), P = 1 + A dt,
+    G = 1 / (1 + A dt + dt M kappa K2)."""
+    K2 = k2_grid(c.shape, p.dx, bc, scheme)
+    C = T(c, bc)
+    F = T(fprime(c), bc)
+    P = 1.0 + p.A * p.dt
+    G = 1.0 / (1.0 + p.A * p.dt + p.dt * p.M * p.kappa * K2)
+    return Tinv(G * (P * C - p.dt * p.M * F), bc)
+
+
+def ac_step_etd1(c, p: CHParams, bc: str, scheme: str):
+    """One exponential (ETD1) Allen-Cahn step: C' = C + dt phi1(dt S) R,
+    S = -(M kappa K2 + A), R = -M F - M kappa K2 C."""
+    K2 = k2_grid(c.shape, p.dx, bc, scheme)
+    C = T(c, bc)
+    F = T(fprime(c), bc)
+    S = -(p.M * p.kappa * K2 + p.A)
+    R = -p.M * F - p.M * p.kappa * K2 * C
+    return Tinv(C + p.dt * phi1(p.dt * S) * R, bc)
+
+
+def ac_run(c0, nsteps: int, p: CHParams, bc: str, scheme: str, etd1: bool = False):
+    """nsteps Allen-Cahn steps from c0 (float64 copy)."""
+    step = ac_step_etd1 if etd1 else ac_step
+    c = np.asarray(c0, dtype=np.float64).copy()
+    for _ in range(nsteps):
+        c = step(c, p, bc, scheme)
+    return c
+
+
+def ac_growth_factor(K2, cbar: float, p: CHParams, etd1: bool = False):
+    """Per-step amplification of a small mode on a constant background cbar (itself moving only
+    at second order when f'(cbar) = 0): the linearised right-hand side is lam C,
+    lam = -M (f''(cbar) + kappa K2); semi-implicit g = (1 + A dt - dt M f''(cbar)) /
+    (1 + A dt + dt M kappa K2); ETD1 g = 1 + dt phi1(dt S) lam."""
+    K2 = np.asarray(K2, dtype=np.float64)
+    if etd1:
+        lam = -p.M * (fsecond(cbar) + p.kappa * K2)
+        return 1.0 + p.dt * phi1(-p.dt * (p.M * p.kappa * K2 + p.A)) * lam
+    return (1.0 + p.A * p.dt - p.dt * p.M * fsecond(cbar)) / (
+        1.0 + p.A * p.dt + p.dt * p.M * p.kappa * K2)
 
 
 def laplacian(u, dx: float, bc: str, scheme: str):
