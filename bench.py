@@ -7,8 +7,9 @@ seed 3, dt 0.5, spectral wavenumbers).  The line also carries:
   roofline     - the dominant kernel's algorithmic bytes per launch over its average launch
                  duration, timed with HIP events on the launch stream inside the timed region;
   cpu_baseline - the FP64 oracle (SciPy FFTs) timed on this host on a bounded sample;
-  extra        - smaller and zero-flux grids, the exponential (ETD1) stepper on the same workload,
-                 the inverse-problem gradient and the learned coarse stepper.
+  extra        - smaller and zero-flux grids, the exponential (ETD1) stepper and the Allen-Cahn
+                 model on the same workload, the inverse-problem gradient and the learned coarse
+                 stepper.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
        python bench.py --summarize-profile DIR [--workload NAME]
@@ -211,10 +212,10 @@ def pass_bytes(shape, bc):
     return [2 * spec, 2 * spec, 2 * spec, 4 * spec]
 
 
-def run_workload(evx, torch, w, steps, warmup, timing=True, integrator=0):
+def run_workload(evx, torch, w, steps, warmup, timing=True, integrator=0, model=0):
     from paper_2507_21748_amd.inputs import quench_field
     plan = evx.Plan(w.shape, w.bc, w.scheme, dx=w.dx)
-    prm = evx.CHParams(dt=w.dt, M=w.M, kappa=w.kappa, A=w.A, integrator=integrator)
+    prm = evx.CHParams(dt=w.dt, M=w.M, kappa=w.kappa, A=w.A, integrator=integrator, model=model)
     c = torch.from_numpy(quench_field(w.shape, w.mean, w.amp, w.seed)).cuda()
     plan.begin(c)
     plan.advance(warmup, prm)
@@ -440,6 +441,10 @@ def main():
         r = run_workload(evx, torch, w, 50, 5, timing=False, integrator=evx.ETD1)
         extra[f"{w.name}_etd1"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
                                    "ms_per_step": r["ms_per_step"]}
+        # the Allen-Cahn model on the same grid and passes (semi-implicit update)
+        r = run_workload(evx, torch, w, 50, 5, timing=False, model=evx.ALLEN_CAHN)
+        extra[f"{w.name}_allen_cahn"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
+                                         "ms_per_step": r["ms_per_step"]}
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
         extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
         line["extra"] = extra

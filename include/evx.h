@@ -62,17 +62,27 @@ typedef enum evx_integrator {
   EVX_INTEGRATOR_ETD1 = 1
 } evx_integrator;
 
+/* Model stepped by evx_ch_advance / evx_ch_step (same plan, transforms and free energy):
+ *   EVX_MODEL_CAHN_HILLIARD: dc/dt = M lap(f'(c) - kappa lap c) (conserved; the split above);
+ *   EVX_MODEL_ALLEN_CAHN: dc/dt = -M (f'(c) - kappa lap c), the linear relaxation of the same
+ *     free energy (the paper's Allen-Cahn equation for a non-conserved order parameter, M the
+ *     kinetic coefficient).  Its split is S = -(M kappa K2 + A), N = -M F + A C: the
+ *     stabilisation multiplies dt alone, so the semi-implicit step is
+ *     C' = (P C - dt M F) / (1 + A dt + dt M kappa K2), P = 1 + A dt. */
+typedef enum evx_model { EVX_MODEL_CAHN_HILLIARD = 0, EVX_MODEL_ALLEN_CAHN = 1 } evx_model;
+
 /* Per-call physics: time step, mobility, gradient-energy coefficient, stabilisation.  They are
- * per call (not plan fields) so gradient loops over kappa and M never re-plan.  A multiplies
- * dt K2 alone (not M): P = 1 + A dt K2.  integrator is an evx_integrator (0, the semi-implicit
- * step, when the struct is zero-initialised past A); the adjoint supports the semi-implicit step
- * only (EVX_ERR_UNSUPPORTED otherwise). */
+ * per call (not plan fields) so gradient loops over kappa and M never re-plan.  For Cahn-Hilliard
+ * A multiplies dt K2 alone (not M): P = 1 + A dt K2.  integrator is an evx_integrator and model an
+ * evx_model (both 0 -- semi-implicit Cahn-Hilliard -- when the struct is zero-initialised past
+ * A); the adjoint supports that combination only (EVX_ERR_UNSUPPORTED otherwise). */
 typedef struct evx_ch_params {
   double dt;
   double M;
   double kappa;
   double A;
   int integrator;
+  int model;
 } evx_ch_params;
 
 /* Workspace users (bit mask for evx_plan_workspace_bytes). */

@@ -83,7 +83,16 @@ evx_status check_params(const evx_ch_params* q) {
     return fail(EVX_ERR_ARG, "params need dt > 0, M >= 0, kappa >= 0, A >= 0");
   if (q->integrator != EVX_INTEGRATOR_SEMI_IMPLICIT && q->integrator != EVX_INTEGRATOR_ETD1)
     return fail(EVX_ERR_ARG, "unknown integrator %d", q->integrator);
+  if (q->model != EVX_MODEL_CAHN_HILLIARD && q->model != EVX_MODEL_ALLEN_CAHN)
+    return fail(EVX_ERR_ARG, "unknown model %d", q->model);
   return EVX_OK;
+}
+
+// z-pass mode of a (model, integrator) pair
+int zmode_of(const evx_ch_params* q) {
+  const bool etd = q->integrator == EVX_INTEGRATOR_ETD1;
+  if (q->model == EVX_MODEL_ALLEN_CAHN) return etd ? COL_Z_AC_ETD : COL_Z_AC;
+  return etd ? COL_Z_ETD : COL_Z_UPDATE;
 }
 
 StepCoef coef_of(const evx_ch_params* q) {
@@ -119,7 +128,8 @@ struct TimedLauncher : HipLauncher {
   void col(int n, int bc, int mode, const ColArgs& a) {
     kind = (mode == COL_INV)                             ? 0
            : (mode == COL_FWD)                           ? 2
-           : (mode == COL_Z_UPDATE || mode == COL_Z_ETD) ? 3
+           : (mode == COL_Z_UPDATE || mode == COL_Z_ETD || mode == COL_Z_AC ||
+              mode == COL_Z_AC_ETD)                      ? 3
                                                          : -1;
     mark_begin();
     HipLauncher::col(n, bc, mode, a);
@@ -329,8 +339,7 @@ evx_status evx_ch_advance(evx_plan* p, int nsteps, const evx_ch_params* q, void*
     if ((st = evx_ch_restore(p, s)) != EVX_OK) return st;
   }
   TimedLauncher l = launcher(p, s);
-  sched_advance(l, p->g, p->t, p->S, p->W, coef_of(q), nsteps, p->remap,
-                q->integrator == EVX_INTEGRATOR_ETD1 ? COL_Z_ETD : COL_Z_UPDATE);
+  sched_advance(l, p->g, p->t, p->S, p->W, coef_of(q), nsteps, p->remap, zmode_of(q));
   return finish(l, "advance");
 }
 
@@ -364,8 +373,8 @@ evx_status evx_ch_adjoint_step(evx_plan* p, const float* c_n, float* lam,
   if (st != EVX_OK) return st;
   if ((st = check_params(q)) != EVX_OK) return st;
   if (!c_n || !lam || !dkappa || !dM) return fail(EVX_ERR_ARG, "NULL argument");
-  if (q->integrator != EVX_INTEGRATOR_SEMI_IMPLICIT)
-    return fail(EVX_ERR_UNSUPPORTED, "the adjoint step is the semi-implicit step's");
+  if (q->integrator != EVX_INTEGRATOR_SEMI_IMPLICIT || q->model != EVX_MODEL_CAHN_HILLIARD)
+    return fail(EVX_ERR_UNSUPPORTED, "the adjoint step is the semi-implicit Cahn-Hilliard step's");
   if (!p->has_adj)
     return fail(EVX_ERR_NOMEM, "workspace too small for the adjoint (EVX_OP_ADJOINT)");
   AdjointCoef co{coef_of(q), float(q->dt), float(q->dt * q->kappa)};

@@ -105,6 +105,8 @@ static hipError_t col_mode(int mode, const ColArgs& a, hipStream_t s) {
     case COL_Z_UPDATE: return col_go<N, BC, COL_Z_UPDATE>(a, s);
     case COL_Z_INV_STATE: return col_go<N, BC, COL_Z_INV_STATE>(a, s);
     case COL_Z_ETD: return col_go<N, BC, COL_Z_ETD>(a, s);
+    case COL_Z_AC: return col_go<N, BC, COL_Z_AC>(a, s);
+    case COL_Z_AC_ETD: return col_go<N, BC, COL_Z_AC_ETD>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -30,7 +30,9 @@ enum : int {
   COL_Z_INIT = 2,      // in -> forward -> state; -> inverse -> out
   COL_Z_UPDATE = 3,    // in -> forward -> k-space update of state -> inverse -> out
   COL_Z_INV_STATE = 4, // state -> inverse -> out
-  COL_Z_ETD = 5        // as COL_Z_UPDATE with the exponential (ETD1) update
+  COL_Z_ETD = 5,       // as COL_Z_UPDATE with the exponential (ETD1) update
+  COL_Z_AC = 6,        // as COL_Z_UPDATE for the Allen-Cahn model (semi-implicit)
+  COL_Z_AC_ETD = 7     // Allen-Cahn, exponential (ETD1) update
 };
 
 // row (x) pass modes
@@ -276,10 +278,10 @@ template <int N, int BC, int MODE>
 EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* lds) {
   using C = ColCfg<N>;
   constexpr int E = C::E, TPS = C::TPS, B = C::B;
-  constexpr bool has_fwd =
-      MODE == COL_FWD || MODE == COL_Z_INIT || MODE == COL_Z_UPDATE || MODE == COL_Z_ETD;
+  constexpr bool upd =
+      MODE == COL_Z_UPDATE || MODE == COL_Z_ETD || MODE == COL_Z_AC || MODE == COL_Z_AC_ETD;
+  constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || upd;
   constexpr bool has_inv = MODE != COL_FWD;
-  constexpr bool upd = MODE == COL_Z_UPDATE || MODE == COL_Z_ETD;
   constexpr bool zf = BC == BC_ZERO_FLUX;
   const int b = tid % B;
   const int t = tid / B;
@@ -366,6 +368,18 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
         const float ra = -(a.dt_m * K2a * F.x + a.dt_m_kappa * K2a * K2a * Cs.x);
         const float rb = -(a.dt_m * K2b * F.y + a.dt_m_kappa * K2b * K2b * Cs.y);
         x[e] = make_float2(Cs.x + pa * ra, Cs.y + pb * rb);
+      } else if constexpr (MODE == COL_Z_AC) {
+        // Allen-Cahn: C' = G (P C - dt M F), P = 1 + A dt, G = 1 / (1 + A dt + dt M kappa K2)
+        const float P = 1.0f + a.a_dt;
+        const float Ga = evx_rcp(P + a.dt_m_kappa * K2a), Gb = evx_rcp(P + a.dt_m_kappa * K2b);
+        x[e] = make_float2(Ga * (P * Cs.x - a.dt_m * F.x), Gb * (P * Cs.y - a.dt_m * F.y));
+      } else if constexpr (MODE == COL_Z_AC_ETD) {
+        // Allen-Cahn ETD1: C' = C + phi1(dt S) dt R, dt S = -(dt M kappa K2 + A dt),
+        // dt R = -(dt M F + dt M kappa K2 C)
+        const float sa = -(a.dt_m_kappa * K2a + a.a_dt), sb = -(a.dt_m_kappa * K2b + a.a_dt);
+        const float ra = -(a.dt_m * F.x + a.dt_m_kappa * K2a * Cs.x);
+        const float rb = -(a.dt_m * F.y + a.dt_m_kappa * K2b * Cs.y);
+        x[e] = make_float2(Cs.x + evx_phi1(sa) * ra, Cs.y + evx_phi1(sb) * rb);
       } else {
         const float Pa = 1.0f + a.a_dt * K2a, Pb = 1.0f + a.a_dt * K2b;
         const float Ga = evx_rcp(1.0f + a.dt_m_kappa * K2a * K2a + a.a_dt * K2a);

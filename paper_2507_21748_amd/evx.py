@@ -12,7 +12,7 @@ from dataclasses import dataclass
 import torch
 
 __all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME", "SEMI_IMPLICIT",
-           "ETD1"]
+           "ETD1", "CAHN_HILLIARD", "ALLEN_CAHN"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -31,10 +31,11 @@ class EvxError(RuntimeError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("M", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("A", ctypes.c_double), ("integrator", ctypes.c_int)]
+                ("A", ctypes.c_double), ("integrator", ctypes.c_int), ("model", ctypes.c_int)]
 
 
 SEMI_IMPLICIT, ETD1 = 0, 1  # evx_integrator
+CAHN_HILLIARD, ALLEN_CAHN = 0, 1  # evx_model
 
 
 @dataclass(frozen=True)
@@ -44,9 +45,10 @@ class CHParams:
     kappa: float = 1.0
     A: float = 2.0
     integrator: int = SEMI_IMPLICIT
+    model: int = CAHN_HILLIARD
 
     def c(self) -> _Params:
-        return _Params(self.dt, self.M, self.kappa, self.A, self.integrator)
+        return _Params(self.dt, self.M, self.kappa, self.A, self.integrator, self.model)
 
 
 def lib_path() -> str:

@@ -5,7 +5,8 @@
 // barrier shows up as a data race on the LDS buffer).  LDS is filled with NaN before every
 // workgroup, so a read of a slot nobody wrote poisons the result.
 //
-// usage: evx_emu nx ny nz bc scheme dx dt M kappa A nsteps remap in.f32 out.f32 [integrator]
+// usage: evx_emu nx ny nz bc scheme dx dt M kappa A nsteps remap in.f32 out.f32 [integrator [model]]
+//   integrator 0 semi-implicit / 1 ETD1; model 0 Cahn-Hilliard / 1 Allen-Cahn.
 //   bc 0 periodic / 1 zero flux; scheme 0 spectral / 1 stencil7.  nsteps < 0 runs |nsteps| steps
 //   in two halves with an end + restore between them (the resume path).
 //        evx_emu adj nx ny nz bc scheme dx dt M kappa A c.f32 lam.f32 out_lam.f32 out_grad.f64
@@ -79,6 +80,8 @@ struct EmuLauncher {
       case COL_Z_INIT: col_t<N, BC, COL_Z_INIT>(a); break;
       case COL_Z_UPDATE: col_t<N, BC, COL_Z_UPDATE>(a); break;
       case COL_Z_ETD: col_t<N, BC, COL_Z_ETD>(a); break;
+      case COL_Z_AC: col_t<N, BC, COL_Z_AC>(a); break;
+      case COL_Z_AC_ETD: col_t<N, BC, COL_Z_AC_ETD>(a); break;
       default: col_t<N, BC, COL_Z_INV_STATE>(a); break;
     }
   }
@@ -216,13 +219,16 @@ static int run_aux(int argc, char** argv) {
 int main(int argc, char** argv) {
   if (argc > 1 && (std::strcmp(argv[1], "adj") == 0 || std::strcmp(argv[1], "diag") == 0))
     return run_aux(argc, argv);
-  if (argc != 15 && argc != 16) {
+  if (argc < 15 || argc > 17) {
     std::fprintf(stderr,
-                 "usage: %s nx ny nz bc scheme dx dt M kappa A nsteps remap in out [integrator]\n",
+                 "usage: %s nx ny nz bc scheme dx dt M kappa A nsteps remap in out [integrator "
+                 "[model]]\n",
                  argv[0]);
     return 2;
   }
-  const int zmode = (argc == 16 && std::atoi(argv[15]) == 1) ? COL_Z_ETD : COL_Z_UPDATE;
+  const bool etd = argc >= 16 && std::atoi(argv[15]) == 1;
+  const bool ac = argc >= 17 && std::atoi(argv[16]) == 1;
+  const int zmode = ac ? (etd ? COL_Z_AC_ETD : COL_Z_AC) : (etd ? COL_Z_ETD : COL_Z_UPDATE);
   const int nx = std::atoi(argv[1]), ny = std::atoi(argv[2]), nz = std::atoi(argv[3]);
   const int bc = std::atoi(argv[4]), scheme = std::atoi(argv[5]);
   const double dx = std::atof(argv[6]), dt = std::atof(argv[7]), M = std::atof(argv[8]);

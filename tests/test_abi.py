@@ -85,15 +85,16 @@ def test_params_struct_layout_matches_header(tmp_path):
         pytest.skip("no host C compiler")
     src = tmp_path / "layout.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "evx.h"\nint main(void) {\n'
-                   '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(evx_ch_params),\n'
+                   '  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(evx_ch_params),\n'
                    '         offsetof(evx_ch_params, dt), offsetof(evx_ch_params, M),\n'
                    '         offsetof(evx_ch_params, kappa), offsetof(evx_ch_params, A),\n'
-                   '         offsetof(evx_ch_params, integrator));\n  return 0;\n}\n')
+                   '         offsetof(evx_ch_params, integrator),\n'
+                   '         offsetof(evx_ch_params, model));\n  return 0;\n}\n')
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True, capture_output=True)
     got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
                                           text=True).stdout.split()]
     want = [ctypes.sizeof(_Params)] + [getattr(_Params, f).offset
-                                       for f in ("dt", "M", "kappa", "A", "integrator")]
+                                       for f in ("dt", "M", "kappa", "A", "integrator", "model")]
     assert got == want

@@ -60,7 +60,7 @@ def tsan():
     return _build("tsan")
 
 
-def _run(exe, shape, bc, scheme, nsteps, p, c0, remap=1, integrator=0):
+def _run(exe, shape, bc, scheme, nsteps, p, c0, remap=1, integrator=0, model=0):
     nz, ny, nx = shape
     with tempfile.TemporaryDirectory() as d:
         c0.astype(np.float32).tofile(os.path.join(d, "in"))
@@ -68,7 +68,8 @@ def _run(exe, shape, bc, scheme, nsteps, p, c0, remap=1, integrator=0):
         r = subprocess.run([exe, str(nx), str(ny), str(nz), str(int(bc == "zero_flux")),
                             str(int(scheme == "stencil7")), repr(p.dx), repr(p.dt), repr(p.M),
                             repr(p.kappa), repr(p.A), str(nsteps), str(remap),
-                            os.path.join(d, "in"), os.path.join(d, "out"), str(integrator)],
+                            os.path.join(d, "in"), os.path.join(d, "out"), str(integrator),
+                            str(model)],
                            capture_output=True, text=True, env=env, timeout=600)
         assert r.returncode == 0, r.stderr[-4000:]
         assert "WARNING: ThreadSanitizer" not in r.stderr, r.stderr[-4000:]
@@ -97,6 +98,17 @@ def test_emulated_etd1_matches_oracle(asan, shape, bc, scheme, n):
     c0 = quench_field(shape, 0.1, 0.3, seed=14)
     got = _run(asan, shape, bc, scheme, n, p, c0, integrator=1)
     ref = ch.ch_run_etd1(c0, abs(n), p, bc, scheme)
+    assert _rel(got, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("shape,bc,scheme,n", [CASES[0], CASES[1]])
+@pytest.mark.parametrize("etd1", [False, True])
+def test_emulated_allen_cahn_matches_oracle(asan, shape, bc, scheme, n, etd1):
+    """The Allen-Cahn z-pass updates against the oracle's Allen-Cahn steps."""
+    p = CHParams(dt=0.5, M=0.9, kappa=1.1, A=2.0)
+    c0 = quench_field(shape, 0.1, 0.3, seed=15)
+    got = _run(asan, shape, bc, scheme, n, p, c0, integrator=int(etd1), model=1)
+    ref = ch.ac_run(c0, abs(n), p, bc, scheme, etd1=etd1)
     assert _rel(got, ref) <= 1e-6
 
 
