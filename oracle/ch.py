@@ -21,9 +21,10 @@ What it computes (paper, Appendix "Semi-implicit timestepping" and "Phase transf
         (I + dt M kappa L^2 - A dt L) c^{n+1} = (I - A dt L) c^n + dt M L f'(c^n)
     with the discrete Laplacian L that T diagonalises.
 
-T is the 3D DFT (periodic) or the separable DCT-II (zero flux on a cell-centred grid, where the
-update has homogeneous Neumann data; the appendix notes the update inherits homogeneous boundary
-data, which is what makes a fast transform applicable).  K2 is the eigenvalue of -L: k^2 for the
+T is the 3D DFT (periodic), the separable DCT-II (zero flux on a cell-centred grid, where the
+update has homogeneous Neumann data) or the separable DST-II (Dirichlet: c and its even
+derivatives vanish at the outer cell faces).  The appendix notes that the update inherits
+homogeneous boundary data, which is what makes a fast transform applicable.  K2 is the eigenvalue of -L: k^2 for the
 spectral Laplacian or (4/dx^2) sin^2(k dx/2) for the 7-point stencil, summed over the three axes.
 
 The exponential stepper (first-order exponential time differencing, ETD1; the paper names
@@ -88,7 +89,8 @@ def axis_k2(n: int, dx: float, bc: str, scheme: str) -> np.ndarray:
     """Eigenvalues of -d^2/dx^2 along one axis of n cells (float64).
 
     periodic:  k = 2 pi m' / (n dx), m' = m for m <= n/2 else m - n;
-    zero flux: k = pi m / (n dx), m = 0..n-1 (cosine modes of the cell-centred grid).
+    zero flux: k = pi m / (n dx), m = 0..n-1 (cosine modes of the cell-centred grid);
+    dirichlet: k = pi m / (n dx), m = 1..n (sine modes: zero at the outer cell faces).
     spectral:  k^2;   stencil7: (4 / dx^2) sin^2(k dx / 2), the symbol of the 3-point
     second difference (7 points in 3D).
     """
@@ -98,6 +100,8 @@ def axis_k2(n: int, dx: float, bc: str, scheme: str) -> np.ndarray:
         k = 2.0 * np.pi * mp / (n * dx)
     elif bc == "zero_flux":
         k = np.pi * m / (n * dx)
+    elif bc == "dirichlet":
+        k = np.pi * (m + 1.0) / (n * dx)
     else:
         raise ValueError(f"unknown bc {bc!r}")
     if scheme == "spectral":
@@ -116,9 +120,12 @@ def k2_grid(shape, dx: float, bc: str, scheme: str) -> np.ndarray:
 
 
 def T(c, bc: str):
-    """Forward transform: full complex 3D DFT (periodic) or 3D DCT-II (zero flux), unnormalised."""
+    """Forward transform, unnormalised: full complex 3D DFT (periodic), 3D DCT-II (zero flux) or
+    3D DST-II (Dirichlet)."""
     if bc == "periodic":
         return sfft.fftn(c, workers=WORKERS)
+    if bc == "dirichlet":
+        return sfft.dstn(c, type=2, workers=WORKERS)
     return sfft.dctn(c, type=2, workers=WORKERS)
 
 
@@ -128,6 +135,8 @@ def Tinv(C, bc: str, keep_complex: bool = False):
     if bc == "periodic":
         out = sfft.ifftn(C, workers=WORKERS)
         return out if keep_complex else out.real
+    if bc == "dirichlet":
+        return sfft.idstn(C, type=2, workers=WORKERS)
     return sfft.idctn(C, type=2, workers=WORKERS)
 
 
