@@ -445,6 +445,13 @@ def main():
         r = run_workload(evx, torch, w, 50, 5, timing=False, model=evx.ALLEN_CAHN)
         extra[f"{w.name}_allen_cahn"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
                                          "ms_per_step": r["ms_per_step"]}
+        # Dirichlet boundary (DST-II) on the 256^3 stencil quench
+        import dataclasses
+        wd = dataclasses.replace(WORKLOADS["ch256_zeroflux"], name="ch256_dirichlet",
+                                 bc="dirichlet")
+        r = run_workload(evx, torch, wd, 200, 10, timing=False)
+        extra["ch256_dirichlet"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
+                                    "ms_per_step": r["ms_per_step"]}
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
         extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
         line["extra"] = extra

@@ -48,7 +48,16 @@ typedef enum evx_status {
   EVX_ERR_STATE = 6        /* call out of order (e.g. advance before begin) */
 } evx_status;
 
-typedef enum evx_bc { EVX_BC_PERIODIC = 0, EVX_BC_ZERO_FLUX = 1 } evx_bc;
+/* Boundary conditions on the cell-centred grid.  EVX_BC_DIRICHLET: c (and its even derivatives)
+ * vanish at the outer cell faces, i.e. the DST-II basis -- the homogeneous data the update
+ * inherits, which the paper notes is what makes a fast transform applicable.  It runs the
+ * zero-flux kernels on (-1)^(i+j+l) c (DST-II(x)[k] = DCT-II((-1)^n x)[N-1-k]) with the
+ * wavenumbers in reversed order; f' is odd, so the sign cancels inside the step. */
+typedef enum evx_bc {
+  EVX_BC_PERIODIC = 0,
+  EVX_BC_ZERO_FLUX = 1,
+  EVX_BC_DIRICHLET = 2
+} evx_bc;
 typedef enum evx_scheme { EVX_SCHEME_SPECTRAL = 0, EVX_SCHEME_STENCIL7 = 1 } evx_scheme;
 
 /* Time integrator of evx_ch_advance / evx_ch_step.  Both split the k-space right-hand side as

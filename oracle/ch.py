@@ -235,8 +235,9 @@ def ac_growth_factor(K2, cbar: float, p: CHParams, etd1: bool = False):
 
 def laplacian(u, dx: float, bc: str, scheme: str):
     """Discrete Laplacian L u.  stencil7: real-space 3-point second difference per axis with
-    periodic wrap or, for zero flux on the cell-centred grid, a mirrored ghost cell (u_{-1} = u_0,
-    u_n = u_{n-1}).  spectral: multiplier -K2 through T."""
+    periodic wrap or, on the cell-centred grid, a mirrored ghost cell (zero flux: u_{-1} = u_0,
+    u_n = u_{n-1}; Dirichlet: u_{-1} = -u_0, u_n = -u_{n-1}, zero at the faces).  spectral:
+    multiplier -K2 through T."""
     if scheme == "spectral":
         return Tinv(-k2_grid(u.shape, dx, bc, scheme) * T(u, bc), bc)
     out = np.zeros_like(u)
@@ -252,6 +253,13 @@ def laplacian(u, dx: float, bc: str, scheme: str):
             sl_dn = [slice(None)] * 3
             sl_up[ax] = slice(2, None)
             sl_dn[ax] = slice(0, -2)
+            if bc == "dirichlet":  # antisymmetric ghosts
+                lo = [slice(None)] * 3
+                hi = [slice(None)] * 3
+                lo[ax] = slice(0, 1)
+                hi[ax] = slice(-1, None)
+                ue[tuple(lo)] *= -1.0
+                ue[tuple(hi)] *= -1.0
             up = ue[tuple(sl_up)]
             dn = ue[tuple(sl_dn)]
         out = out + (up - 2.0 * u + dn)

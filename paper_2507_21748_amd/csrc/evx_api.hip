@@ -184,7 +184,8 @@ void evx_internal_set_error(const char* msg) { g_last_error = msg; }
 evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, evx_scheme scheme,
                            double dx) {
   if (!out) return fail(EVX_ERR_ARG, "out is NULL");
-  if (bc != EVX_BC_PERIODIC && bc != EVX_BC_ZERO_FLUX) return fail(EVX_ERR_ARG, "bad bc %d", bc);
+  if (bc != EVX_BC_PERIODIC && bc != EVX_BC_ZERO_FLUX && bc != EVX_BC_DIRICHLET)
+    return fail(EVX_ERR_ARG, "bad bc %d", bc);
   if (scheme != EVX_SCHEME_SPECTRAL && scheme != EVX_SCHEME_STENCIL7)
     return fail(EVX_ERR_ARG, "bad scheme %d", scheme);
   if (!(dx > 0)) return fail(EVX_ERR_ARG, "dx must be > 0");

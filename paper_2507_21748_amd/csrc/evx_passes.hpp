@@ -18,7 +18,7 @@
 
 namespace evx {
 
-enum : int { BC_PERIODIC = 0, BC_ZERO_FLUX = 1 };
+enum : int { BC_PERIODIC = 0, BC_ZERO_FLUX = 1, BC_DIRICHLET = 2 };
 
 // Row pitch (complex values) of a periodic half spectrum whose rows hold nh + 1 values.
 EVX_HD constexpr int spectral_pitch(int nh) { return ((nh + 1 + 7) / 8) * 8; }
@@ -73,7 +73,16 @@ struct RowArgs {
   const float2* tw;    // row FFT twiddles
   const float2* post;  // periodic: exp(-2 pi i k / nx), k <= nx/2; zero flux: exp(-i pi k/(2 nx))
   float scale;         // 1/V (periodic) or 1/(8V) (zero flux), applied after the inverse
+  int flip;            // Dirichlet grid: real rows in and out carry (-1)^(i + j + l)
+  int ny;              // rows r = j + ny l (for the sign)
 };
+
+// (-1)^(i + j + l) of point i of row r = j + ny l
+EVX_HD float dirichlet_sign(long long r, int i, int ny) {
+  const long long l = r / ny;
+  const int j = int(r - l * ny);
+  return ((i + j + int(l & 1)) & 1) ? -1.0f : 1.0f;
+}
 
 // One launch of the same transform pass over up to three independent (in, out) buffer pairs: the
 // grid's y index selects the pair (the small-grid adjoint runs its transforms this way, which
@@ -610,6 +619,11 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         const int n = t + TPS * decltype(e)::value;
         const int s = makhoul_src<NX>(n);
         x[e] = make_float2(st[(2 * b) * ZS + s], st[(2 * b + 1) * ZS + s]);
+        if (a.flip) {
+          const long long ra = r0 + 2 * b;
+          x[e] = make_float2(x[e].x * dirichlet_sign(ra, s, a.ny),
+                             x[e].y * dirichlet_sign(ra + 1, s, a.ny));
+        }
       });
       if constexpr (MODE == ROW_FWD_FP)
         static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
@@ -632,8 +646,14 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         static_for<E>([&](auto e) {
           const int n = t + TPS * decltype(e)::value;
           const int s = makhoul_src<NX>(n);
-          st[(2 * b) * ZS + s] = x[e].x;
-          st[(2 * b + 1) * ZS + s] = x[e].y;
+          float va = x[e].x, vb = x[e].y;
+          if (a.flip) {
+            const long long ra = r0 + 2 * b;
+            va *= dirichlet_sign(ra, s, a.ny);
+            vb *= dirichlet_sign(ra + 1, s, a.ny);
+          }
+          st[(2 * b) * ZS + s] = va;
+          st[(2 * b + 1) * ZS + s] = vb;
         });
         evx_sync();
         if constexpr (C::ZPAD) {

@@ -45,7 +45,8 @@ inline int col_block_seqs(int n) {
 
 struct Geom {
   int nx = 0, ny = 0, nz = 0;
-  int bc = BC_PERIODIC;
+  int bc = BC_PERIODIC;  // transform family: Dirichlet grids run the zero-flux kernels
+  bool dirichlet = false;  // DST-II grid: real rows carry the sign (-1)^(i+j+l), K2 reversed
   int scheme = 0;        // 0 spectral, 1 stencil7
   double dx = 1.0;       // grid spacing baked into the K2 tables
   long long V = 0;       // voxels
@@ -62,7 +63,9 @@ inline Geom make_geom(int nx, int ny, int nz, int bc, int scheme, double dx) {
   g.nx = nx;
   g.ny = ny;
   g.nz = nz;
-  g.bc = bc;
+  g.dirichlet = bc == BC_DIRICHLET;
+  g.bc = g.dirichlet ? BC_ZERO_FLUX : bc;
+  bc = g.bc;
   g.scheme = scheme;
   g.dx = dx;
   g.V = (long long)nx * ny * nz;
@@ -117,9 +120,12 @@ inline double axis_k2(int m, int n, int bc, int scheme, double dx) {
   return 4.0 / (dx * dx) * s * s;
 }
 
-inline std::vector<float> k2_table(int count, int n, int bc, int scheme, double dx) {
+// Dirichlet: bin j of the zero-flux transform of the sign-alternated field holds sine mode n - j
+inline std::vector<float> k2_table(int count, int n, int bc, int scheme, double dx,
+                                   bool dirichlet = false) {
   std::vector<float> t(count);
-  for (int m = 0; m < count; ++m) t[m] = float(axis_k2(m, n, bc, scheme, dx));
+  for (int m = 0; m < count; ++m)
+    t[m] = float(axis_k2(dirichlet ? n - m : m, n, bc, scheme, dx));
   return t;
 }
 
@@ -139,10 +145,10 @@ inline HostTables make_tables(const Geom& g) {
     h.post_x = makhoul_twiddles(g.nx);
     h.mk_y = makhoul_twiddles(g.ny);
     h.mk_z = makhoul_twiddles(g.nz);
-    h.k2_x = k2_table(g.nx, g.nx, g.bc, g.scheme, g.dx);
+    h.k2_x = k2_table(g.nx, g.nx, g.bc, g.scheme, g.dx, g.dirichlet);
   }
-  h.k2_y = k2_table(g.ny, g.ny, g.bc, g.scheme, g.dx);
-  h.k2_z = k2_table(g.nz, g.nz, g.bc, g.scheme, g.dx);
+  h.k2_y = k2_table(g.ny, g.ny, g.bc, g.scheme, g.dx, g.dirichlet);
+  h.k2_z = k2_table(g.nz, g.nz, g.bc, g.scheme, g.dx, g.dirichlet);
   return h;
 }
 
@@ -206,6 +212,8 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   a.tw = t.tw_x;
   a.post = t.post_x;
   a.scale = (g.bc == BC_PERIODIC) ? float(1.0 / double(g.V)) : float(1.0 / (8.0 * double(g.V)));
+  a.flip = g.dirichlet ? 1 : 0;
+  a.ny = g.ny;
   return a;
 }
 

@@ -17,7 +17,7 @@ __all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME", "
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-BC = {"periodic": 0, "zero_flux": 1}
+BC = {"periodic": 0, "zero_flux": 1, "dirichlet": 2}
 SCHEME = {"spectral": 0, "stencil7": 1}
 
 OP_STEP, OP_DIAG, OP_ADJOINT = 1, 2, 4

@@ -65,7 +65,8 @@ def _run(exe, shape, bc, scheme, nsteps, p, c0, remap=1, integrator=0, model=0):
     with tempfile.TemporaryDirectory() as d:
         c0.astype(np.float32).tofile(os.path.join(d, "in"))
         env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=0")
-        r = subprocess.run([exe, str(nx), str(ny), str(nz), str(int(bc == "zero_flux")),
+        r = subprocess.run([exe, str(nx), str(ny), str(nz),
+                            str({"periodic": 0, "zero_flux": 1, "dirichlet": 2}[bc]),
                             str(int(scheme == "stencil7")), repr(p.dx), repr(p.dt), repr(p.M),
                             repr(p.kappa), repr(p.A), str(nsteps), str(remap),
                             os.path.join(d, "in"), os.path.join(d, "out"), str(integrator),
@@ -109,6 +110,19 @@ def test_emulated_allen_cahn_matches_oracle(asan, shape, bc, scheme, n, etd1):
     c0 = quench_field(shape, 0.1, 0.3, seed=15)
     got = _run(asan, shape, bc, scheme, n, p, c0, integrator=int(etd1), model=1)
     ref = ch.ac_run(c0, abs(n), p, bc, scheme, etd1=etd1)
+    assert _rel(got, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("shape,scheme,n", [((16, 12, 16), "spectral", 2),
+                                             ((20, 16, 24), "stencil7", -3),
+                                             ((8, 48, 96), "spectral", 1)])
+def test_emulated_dirichlet_matches_oracle(asan, shape, scheme, n):
+    """Dirichlet grids (zero-flux kernels on the sign-alternated field, reversed K2) against the
+    oracle's DST-II steps, including the resume path."""
+    p = CHParams(dt=0.5, M=0.9, kappa=1.1, A=2.0)
+    c0 = quench_field(shape, 0.1, 0.3, seed=16)
+    got = _run(asan, shape, "dirichlet", scheme, n, p, c0)
+    ref = ch.ch_run(c0, abs(n), p, "dirichlet", scheme)
     assert _rel(got, ref) <= 1e-6
 
 

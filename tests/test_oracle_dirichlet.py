@@ -104,3 +104,21 @@ def test_transform_round_trip_and_sine_basis():
     C = ch.T(_sine_mode((6, 8, 10), (2, 1, 3)), "dirichlet")
     k = np.unravel_index(np.argmax(np.abs(C)), C.shape)
     assert k == (1, 0, 2)  # bin index m - 1
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_increment_form_equals_kspace_form(scheme):
+    """The paper's increment form with the real-space Laplacian (antisymmetric ghost cells for the
+    stencil) equals the k-space step on Dirichlet grids."""
+    p = CHParams(dt=0.3, M=0.9, kappa=1.1, A=1.5)
+    c = quench_field((6, 8, 10), 0.1, 0.5, seed=10).astype(np.float64)
+    a = ch.ch_step(c, p, "dirichlet", scheme)
+    b = ch.ch_step_increment(c, p, "dirichlet", scheme)
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_stencil_laplacian_against_dense():
+    c = quench_field((4, 6, 5), 0.2, 0.5, seed=12).astype(np.float64)
+    L = _dense_laplacian(c.shape, 0.8, "stencil7")
+    want = (L @ c.reshape(-1)).reshape(c.shape)
+    assert np.max(np.abs(ch.laplacian(c, 0.8, "dirichlet", "stencil7") - want)) < 1e-12
