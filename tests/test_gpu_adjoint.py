@@ -23,7 +23,8 @@ def rel(a, b):
 
 
 CASES = [((16, 12, 16), "periodic", "spectral"), ((8, 24, 16), "zero_flux", "stencil7"),
-         ((32, 40, 48), "zero_flux", "spectral"), ((24, 32, 20), "periodic", "stencil7")]
+         ((32, 40, 48), "zero_flux", "spectral"), ((24, 32, 20), "periodic", "stencil7"),
+         ((16, 12, 16), "dirichlet", "spectral"), ((8, 24, 16), "dirichlet", "stencil7")]
 
 
 @pytest.mark.parametrize("shape,bc,scheme", CASES)
@@ -71,7 +72,8 @@ def _rollout_grads(evx_gpu, c0, target, shape, bc, scheme, p, nsteps, every):
     return loss.item(), c.grad.cpu().numpy(), kappa.grad.item(), M.grad.item()
 
 
-@pytest.mark.parametrize("bc,scheme", [("periodic", "spectral"), ("zero_flux", "stencil7")])
+@pytest.mark.parametrize("bc,scheme", [("periodic", "spectral"), ("zero_flux", "stencil7"),
+                                       ("dirichlet", "spectral")])
 def test_rollout_gradients_vs_oracle_and_fd(evx_gpu, bc, scheme):
     """16^3, 40 steps of dt 0.5, checkpoint every 8: gradients w.r.t. c0, kappa, M against the
     oracle's adjoint and FP64 central differences of the oracle's loss (<= 1e-4 relative)."""

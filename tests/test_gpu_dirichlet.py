@@ -98,3 +98,26 @@ def test_diagnostics(evx_gpu, scheme):
     c64 = c0.astype(np.float64)
     assert abs(mass / ch.mass(c64, p.dx) - 1.0) <= 1e-5
     assert abs(energy / ch.energy(c64, p, "dirichlet", scheme) - 1.0) <= 1e-5
+
+
+@pytest.mark.parametrize("which", ["etd1", "allen_cahn", "allen_cahn_etd1"])
+def test_with_other_integrators_and_models(evx_gpu, which):
+    """Dirichlet grids with the exponential integrator and the Allen-Cahn model: one step against
+    the oracle's DST-II versions of those steps."""
+    shape, scheme = (24, 20, 32), "stencil7"
+    p = OParams(dt=0.5, M=0.9, kappa=1.1, A=2.0)
+    c0 = quench_field(shape, 0.1, 0.3, seed=65)
+    etd1 = which.endswith("etd1")
+    ac = which.startswith("allen")
+    plan = evx_gpu.Plan(shape, "dirichlet", scheme)
+    c = torch.from_numpy(c0).cuda()
+    plan.step(c, 1, evx_gpu.CHParams(dt=p.dt, M=p.M, kappa=p.kappa, A=p.A,
+                                     integrator=evx_gpu.ETD1 if etd1 else evx_gpu.SEMI_IMPLICIT,
+                                     model=evx_gpu.ALLEN_CAHN if ac else evx_gpu.CAHN_HILLIARD))
+    torch.cuda.synchronize()
+    c64 = c0.astype(np.float64)
+    if ac:
+        ref = ch.ac_run(c64, 1, p, "dirichlet", scheme, etd1=etd1)
+    else:
+        ref = ch.ch_step_etd1(c64, p, "dirichlet", scheme)
+    assert rel_l2(c.cpu().numpy(), ref) <= 1e-5
