@@ -134,6 +134,15 @@ evx_status evx_ch_begin(evx_plan* plan, const float* c, void* hip_stream);
 
 /* nsteps (>= 0) semi-implicit steps on the spectral state.  Requires a prior begin (or restore);
  * runs the restore pass first if an end consumed the work buffer. */
+/* As evx_ch_advance, also writing the real field c^n at the start of each of the nsteps steps to
+ * traj + n V (caller-owned device memory, nsteps x V floats, C order per field).  It is the
+ * recomputation a checkpointed adjoint sweep needs (the gradient of a rollout with respect to
+ * c0, kappa and M, extension 3 of the paper's outlook): one fused x pass per step both stores the
+ * row it passes through and continues the step, so a recorded step costs the four passes of a
+ * plain one.  The recorded fields are bitwise equal to what evx_ch_end returns at the same step.
+ * Errors as evx_ch_advance; EVX_ERR_ARG if traj is NULL while nsteps > 0. */
+evx_status evx_ch_advance_record(evx_plan* plan, int nsteps, const evx_ch_params* params,
+                                 float* traj, void* hip_stream);
 evx_status evx_ch_advance(evx_plan* plan, int nsteps, const evx_ch_params* params,
                           void* hip_stream);
 

@@ -44,13 +44,10 @@ class CHRollout(torch.autograd.Function):
             k = min(every, nsteps - seg * every)
             plan.state().copy_(ctx.ckpts[seg])
             plan.restore()
-            states = []
-            for i in range(k):
-                ci = torch.empty_like(lam)
-                plan.end(ci)
-                states.append(ci)
-                if i < k - 1:
-                    plan.advance(1, prm)
+            # c^n of the segment: k - 1 recorded steps, then the last state
+            states = torch.empty((k,) + tuple(lam.shape), dtype=torch.float32, device=lam.device)
+            plan.advance_record(k - 1, prm, states)
+            plan.end(states[k - 1])
             for i in range(k - 1, -1, -1):
                 plan.adjoint_step(states[i], lam, prm, dk, dM)
             del states

@@ -344,6 +344,23 @@ evx_status evx_ch_advance(evx_plan* p, int nsteps, const evx_ch_params* q, void*
   return finish(l, "advance");
 }
 
+evx_status evx_ch_advance_record(evx_plan* p, int nsteps, const evx_ch_params* q, float* traj,
+                                 void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if ((st = check_params(q)) != EVX_OK) return st;
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  if (nsteps > 0 && !traj) return fail(EVX_ERR_ARG, "traj is NULL");
+  if (!p->begun) return fail(EVX_ERR_STATE, "advance before begin/restore");
+  if (!p->w_valid) {
+    if ((st = evx_ch_restore(p, s)) != EVX_OK) return st;
+  }
+  TimedLauncher l = launcher(p, s);
+  sched_advance_record(l, p->g, p->t, p->S, p->W, coef_of(q), nsteps, p->remap, zmode_of(q),
+                       traj);
+  return finish(l, "advance_record");
+}
+
 evx_status evx_ch_end(evx_plan* p, float* c, void* s) {
   evx_status st = check_plan(p);
   if (st != EVX_OK) return st;

@@ -40,7 +40,8 @@ enum : int {
   ROW_FUSED = 0,  // complex row -> inverse x -> f' -> forward x -> complex row
   ROW_FWD = 1,    // real row -> forward x -> complex row
   ROW_INV = 2,    // complex row -> inverse x -> real row
-  ROW_FWD_FP = 3  // real row -> f'(c) -> forward x -> complex row (adjoint: T[f'(c)])
+  ROW_FWD_FP = 3, // real row -> f'(c) -> forward x -> complex row (adjoint: T[f'(c)])
+  ROW_FUSED_REC = 4  // ROW_FUSED that also stores the real row it passes through (out_r)
 };
 
 struct ColArgs {
@@ -566,12 +567,13 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       evx_sync();
       fft_regs<NH, +1, B>(x, lds, b, t, twl);
       static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
-      if constexpr (MODE == ROW_INV) {
+      if constexpr (MODE == ROW_INV || MODE == ROW_FUSED_REC) {
         static_for<E>([&](auto e) { lds[b * NH + t + TPS * decltype(e)::value] = x[e]; });
         evx_sync();
         copy_out<B * NH, T>(reinterpret_cast<float2*>(a.out_r) + r0 * NH, (a.nrows - r0) * NH,
                             lds, tid);
-        return;
+        if constexpr (MODE == ROW_INV) return;
+        evx_sync();  // the forward transform reuses the staging area
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
     }
@@ -642,7 +644,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       evx_sync();
       fft_regs<NX, +1, B>(x, lds, b, t, twl);
       static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
-      if constexpr (MODE == ROW_INV) {
+      if constexpr (MODE == ROW_INV || MODE == ROW_FUSED_REC) {
         static_for<E>([&](auto e) {
           const int n = t + TPS * decltype(e)::value;
           const int s = makhoul_src<NX>(n);
@@ -664,7 +666,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
           copy_out<B * NX, T>(reinterpret_cast<float2*>(a.out_r) + r0 * (NX / 2),
                               (a.nrows - r0) * (NX / 2), lds, tid);
         }
-        return;
+        if constexpr (MODE == ROW_INV) return;
+        evx_sync();  // the forward transform reuses the staging area
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
     }

@@ -240,6 +240,19 @@ void sched_advance(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W
   }
 }
 
+// As sched_advance, also recording the real field c^n at the start of each step into
+// traj + n V (the fused x pass stores the row it passes through).
+template <class L>
+void sched_advance_record(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W,
+                          StepCoef c, int nsteps, int remap, int zmode, float* traj) {
+  for (int n = 0; n < nsteps; ++n) {
+    l.col(g.ny, g.bc, COL_INV, y_args(g, t, W, W, remap));
+    l.row(g.row_len, g.bc, ROW_FUSED_REC, x_args(g, t, W, nullptr, W, traj + (long long)n * g.V));
+    l.col(g.ny, g.bc, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.nz, g.bc, zmode, z_args(g, t, W, W, S, c, remap));
+  }
+}
+
 // Real field from W = F_z^{-1} S (consumes W).
 template <class L>
 void sched_end(L& l, const Geom& g, const TablePtrs& t, float* c, float2* W, int remap) {

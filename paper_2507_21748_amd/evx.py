@@ -65,6 +65,8 @@ _PROTOS = {
                        ctypes.POINTER(ctypes.c_size_t)],
     "evx_ch_begin": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_advance": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params), ctypes.c_void_p],
+    "evx_ch_advance_record": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
+                              ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_end": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_restore": [ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
@@ -176,6 +178,19 @@ class Plan:
         p = params.c()
         _check(_LIB.evx_ch_advance(self._h, int(nsteps), ctypes.byref(p), _stream_handle(stream)),
                "evx_ch_advance")
+
+    def advance_record(self, nsteps: int, params: CHParams, traj: torch.Tensor, stream=None):
+        """Advance nsteps, writing c^n at the start of each step to traj[n] (float32 device tensor
+        of shape (>= nsteps, nz, ny, nx))."""
+        p = params.c()
+        ptr = None
+        if nsteps > 0:
+            if traj.numel() < nsteps * self.voxels:
+                raise ValueError(f"traj holds {traj.numel()} values, needs {nsteps * self.voxels}")
+            ptr = _dev_ptr(traj)
+        _check(_LIB.evx_ch_advance_record(self._h, int(nsteps), ctypes.byref(p), ptr,
+                                          _stream_handle(stream)), "evx_ch_advance_record")
+        return traj
 
     def end(self, c: torch.Tensor, stream=None):
         _check(_LIB.evx_ch_end(self._h, _dev_ptr(c, numel=self.voxels), _stream_handle(stream)),

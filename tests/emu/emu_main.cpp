@@ -91,6 +91,7 @@ struct EmuLauncher {
       case ROW_FUSED: row_t<NH, BC, ROW_FUSED>(a); break;
       case ROW_FWD: row_t<NH, BC, ROW_FWD>(a); break;
       case ROW_FWD_FP: row_t<NH, BC, ROW_FWD_FP>(a); break;
+      case ROW_FUSED_REC: row_t<NH, BC, ROW_FUSED_REC>(a); break;
       default: row_t<NH, BC, ROW_INV>(a); break;
     }
   }

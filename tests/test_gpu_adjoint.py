@@ -141,3 +141,38 @@ def test_inverse_problem_128(evx_gpu):
     gs = g.reshape(-1)[gld["index"]]
     assert np.linalg.norm(gs - gld["grad_c0_sample"]) / np.linalg.norm(gld["grad_c0_sample"]) <= 1e-4
     assert abs(np.linalg.norm(g) / float(gld["grad_c0_norm"]) - 1) <= 1e-4
+
+
+@pytest.mark.parametrize("bc,scheme", [("periodic", "spectral"), ("zero_flux", "stencil7"),
+                                       ("dirichlet", "spectral")])
+def test_advance_record_is_bitwise(evx_gpu, bc, scheme):
+    """evx_ch_advance_record writes the same c^n as end() after each single step, and leaves the
+    same state as plain advancing (bitwise)."""
+    shape, n = (16, 24, 32), 6
+    prm = evx_gpu.CHParams(dt=0.5)
+    c0 = torch.from_numpy(quench_field(shape, 0.1, 0.3, seed=7)).cuda()
+    a = evx_gpu.Plan(shape, bc, scheme)
+    a.begin(c0)
+    ref = []
+    for _ in range(n):
+        ci = torch.empty_like(c0)
+        a.end(ci)
+        ref.append(ci)
+        a.advance(1, prm)
+    b = evx_gpu.Plan(shape, bc, scheme)
+    b.begin(c0)
+    traj = torch.empty((n,) + shape, dtype=torch.float32, device="cuda")
+    b.advance_record(n, prm, traj)
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert torch.equal(traj[i], ref[i]), i
+    # the state itself (its whole-tile padding holds whatever the workspace held) through what
+    # it determines: the field now and one step later
+    for _ in range(2):
+        ea, eb = torch.empty_like(c0), torch.empty_like(c0)
+        a.end(ea)
+        b.end(eb)
+        torch.cuda.synchronize()
+        assert torch.equal(ea, eb)
+        a.advance(1, prm)
+        b.advance(1, prm)
