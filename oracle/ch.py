@@ -55,7 +55,7 @@ __all__ = [
     "CHParams", "axis_k2", "k2_grid", "T", "Tinv", "fprime", "fsecond", "fwell",
     "ch_step", "ch_step_increment", "ch_run", "laplacian", "energy", "mass", "growth_factor",
     "ch_step_etd1", "ch_run_etd1", "growth_factor_etd1", "phi1",
-    "ac_step", "ac_step_etd1", "ac_run", "ac_growth_factor",
+    "ac_step", "ac_step_etd1", "ac_run", "ac_growth_factor", "axis_bcs",
 ]
 
 WORKERS = 1  # scipy.fft threads; the CPU-baseline leg raises it to the host core count
@@ -111,17 +111,35 @@ def axis_k2(n: int, dx: float, bc: str, scheme: str) -> np.ndarray:
     raise ValueError(f"unknown scheme {scheme!r}")
 
 
-def k2_grid(shape, dx: float, bc: str, scheme: str) -> np.ndarray:
+def axis_bcs(bc):
+    """Per-axis boundary conditions (z, y, x): a name for all three axes, or a 3-tuple mixing
+    'zero_flux' and 'dirichlet' (the transforms are then applied axis by axis)."""
+    if isinstance(bc, str):
+        return (bc, bc, bc)
+    bcs = tuple(bc)
+    if len(bcs) != 3 or any(b not in ("zero_flux", "dirichlet") for b in bcs):
+        raise ValueError(f"per-axis bc must mix 'zero_flux' and 'dirichlet': {bc!r}")
+    return bcs
+
+
+def k2_grid(shape, dx: float, bc, scheme: str) -> np.ndarray:
     """K2(kz, ky, kx) = sum of the per-axis eigenvalues, shape (nz, ny, nx)."""
     nz, ny, nx = shape
-    return (axis_k2(nz, dx, bc, scheme)[:, None, None]
-            + axis_k2(ny, dx, bc, scheme)[None, :, None]
-            + axis_k2(nx, dx, bc, scheme)[None, None, :])
+    bz, by, bx = axis_bcs(bc)
+    return (axis_k2(nz, dx, bz, scheme)[:, None, None]
+            + axis_k2(ny, dx, by, scheme)[None, :, None]
+            + axis_k2(nx, dx, bx, scheme)[None, None, :])
 
 
 def T(c, bc: str):
     """Forward transform, unnormalised: full complex 3D DFT (periodic), 3D DCT-II (zero flux) or
     3D DST-II (Dirichlet)."""
+    if not isinstance(bc, str):  # per-axis DCT-II / DST-II
+        out = np.asarray(c, dtype=np.float64)
+        for ax, b in enumerate(axis_bcs(bc)):
+            f = sfft.dst if b == "dirichlet" else sfft.dct
+            out = f(out, type=2, axis=ax, workers=WORKERS)
+        return out
     if bc == "periodic":
         return sfft.fftn(c, workers=WORKERS)
     if bc == "dirichlet":
@@ -135,6 +153,12 @@ def Tinv(C, bc: str, keep_complex: bool = False):
     if bc == "periodic":
         out = sfft.ifftn(C, workers=WORKERS)
         return out if keep_complex else out.real
+    if not isinstance(bc, str):
+        out = np.asarray(C, dtype=np.float64)
+        for ax, b in enumerate(axis_bcs(bc)):
+            f = sfft.idst if b == "dirichlet" else sfft.idct
+            out = f(out, type=2, axis=ax, workers=WORKERS)
+        return out
     if bc == "dirichlet":
         return sfft.idstn(C, type=2, workers=WORKERS)
     return sfft.idctn(C, type=2, workers=WORKERS)
@@ -241,8 +265,8 @@ def laplacian(u, dx: float, bc: str, scheme: str):
     if scheme == "spectral":
         return Tinv(-k2_grid(u.shape, dx, bc, scheme) * T(u, bc), bc)
     out = np.zeros_like(u)
-    for ax in range(3):
-        if bc == "periodic":
+    for ax, bca in enumerate(axis_bcs(bc)):
+        if bca == "periodic":
             up = np.roll(u, -1, axis=ax)
             dn = np.roll(u, 1, axis=ax)
         else:
@@ -253,7 +277,7 @@ def laplacian(u, dx: float, bc: str, scheme: str):
             sl_dn = [slice(None)] * 3
             sl_up[ax] = slice(2, None)
             sl_dn[ax] = slice(0, -2)
-            if bc == "dirichlet":  # antisymmetric ghosts
+            if bca == "dirichlet":  # antisymmetric ghosts
                 lo = [slice(None)] * 3
                 hi = [slice(None)] * 3
                 lo[ax] = slice(0, 1)

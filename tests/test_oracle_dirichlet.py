@@ -122,3 +122,43 @@ def test_stencil_laplacian_against_dense():
     L = _dense_laplacian(c.shape, 0.8, "stencil7")
     want = (L @ c.reshape(-1)).reshape(c.shape)
     assert np.max(np.abs(ch.laplacian(c, 0.8, "dirichlet", "stencil7") - want)) < 1e-12
+
+
+MIXES = [("dirichlet", "zero_flux", "zero_flux"), ("zero_flux", "dirichlet", "dirichlet"),
+         ("zero_flux", "zero_flux", "dirichlet")]
+
+
+@pytest.mark.parametrize("bcs", MIXES)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_mixed_axes_extension_identity(bcs, scheme):
+    """Per-axis boundaries (z, y, x): the step equals the periodic step on the 2n extension that is
+    even along zero-flux axes and odd along Dirichlet axes, restricted."""
+    p = CHParams(dt=0.5)
+    c = quench_field((6, 10, 8), 0.0, 0.5, seed=13).astype(np.float64)
+    e = c
+    for ax, b in enumerate(bcs):
+        sgn = -1.0 if b == "dirichlet" else 1.0
+        e = np.concatenate([e, sgn * np.flip(e, axis=ax)], axis=ax)
+    per = ch.ch_step(e, p, "periodic", scheme)[:6, :10, :8]
+    got = ch.ch_step(c, p, bcs, scheme)
+    assert np.max(np.abs(per - got)) < 1e-13
+
+
+@pytest.mark.parametrize("bcs", MIXES)
+def test_mixed_axes_dense_solve(bcs):
+    from tests.test_oracle_ch import _d2_1d
+    p = CHParams(dx=0.7, dt=0.3, M=0.8, kappa=1.3, A=2.0)
+    c = quench_field((4, 6, 4), 0.1, 0.6, seed=14).astype(np.float64)
+    mats = [_d2_dirichlet(n, p.dx, "stencil7") if b == "dirichlet"
+            else _d2_1d(n, p.dx, "zero_flux", "stencil7") for n, b in zip(c.shape, bcs)]
+    Lz, Ly, Lx = mats
+    Iz, Iy, Ix = (np.eye(n) for n in c.shape)
+    L = (np.kron(Lz, np.kron(Iy, Ix)) + np.kron(Iz, np.kron(Ly, Ix))
+         + np.kron(Iz, np.kron(Iy, Lx)))
+    I = np.eye(L.shape[0])
+    v = c.reshape(-1)
+    lhs = I + p.dt * p.M * p.kappa * (L @ L) - p.A * p.dt * L
+    rhs = (I - p.A * p.dt * L) @ v + p.dt * p.M * (L @ (v ** 3 - v))
+    ref = np.linalg.solve(lhs, rhs).reshape(c.shape)
+    assert np.max(np.abs(ch.ch_step(c, p, bcs, "stencil7") - ref)) < 1e-12
+    assert np.max(np.abs(ch.ch_step_increment(c, p, bcs, "stencil7") - ref)) < 1e-12
