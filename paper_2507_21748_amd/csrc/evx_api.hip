@@ -183,9 +183,19 @@ void evx_internal_set_error(const char* msg) { g_last_error = msg; }
 
 evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, evx_scheme scheme,
                            double dx) {
+  return evx_plan_create_axes(out, nx, ny, nz, bc, bc, bc, scheme, dx);
+}
+
+evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc bc_x, evx_bc bc_y,
+                                evx_bc bc_z, evx_scheme scheme, double dx) {
   if (!out) return fail(EVX_ERR_ARG, "out is NULL");
-  if (bc != EVX_BC_PERIODIC && bc != EVX_BC_ZERO_FLUX && bc != EVX_BC_DIRICHLET)
-    return fail(EVX_ERR_ARG, "bad bc %d", bc);
+  for (evx_bc b : {bc_x, bc_y, bc_z})
+    if (b != EVX_BC_PERIODIC && b != EVX_BC_ZERO_FLUX && b != EVX_BC_DIRICHLET)
+      return fail(EVX_ERR_ARG, "bad bc %d", b);
+  const int nper = (bc_x == EVX_BC_PERIODIC) + (bc_y == EVX_BC_PERIODIC) + (bc_z == EVX_BC_PERIODIC);
+  if (nper != 0 && nper != 3)
+    return fail(EVX_ERR_UNSUPPORTED, "periodic axes mixed with zero-flux / Dirichlet ones");
+  const evx_bc bc = bc_x;
   if (scheme != EVX_SCHEME_SPECTRAL && scheme != EVX_SCHEME_STENCIL7)
     return fail(EVX_ERR_ARG, "bad scheme %d", scheme);
   if (!(dx > 0)) return fail(EVX_ERR_ARG, "dx must be > 0");
@@ -198,7 +208,7 @@ evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, ev
     return fail(EVX_ERR_SIZE, "nx=%d not supported", nx);
   }
   evx_plan* p = new evx_plan();
-  p->g = make_geom(nx, ny, nz, int(bc), int(scheme), dx);
+  p->g = make_geom3(nx, ny, nz, int(bc_x), int(bc_y), int(bc_z), int(scheme), dx);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;

@@ -74,15 +74,16 @@ struct RowArgs {
   const float2* tw;    // row FFT twiddles
   const float2* post;  // periodic: exp(-2 pi i k / nx), k <= nx/2; zero flux: exp(-i pi k/(2 nx))
   float scale;         // 1/V (periodic) or 1/(8V) (zero flux), applied after the inverse
-  int flip;            // Dirichlet grid: real rows in and out carry (-1)^(i + j + l)
+  int flip;            // Dirichlet axes (bit 0 x, 1 y, 2 z): real rows carry (-1)^(their index)
   int ny;              // rows r = j + ny l (for the sign)
 };
 
-// (-1)^(i + j + l) of point i of row r = j + ny l
-EVX_HD float dirichlet_sign(long long r, int i, int ny) {
+// (-1)^(i [x Dirichlet] + j [y Dirichlet] + l [z Dirichlet]) of point i of row r = j + ny l
+EVX_HD float dirichlet_sign(long long r, int i, int ny, int mask) {
   const long long l = r / ny;
   const int j = int(r - l * ny);
-  return ((i + j + int(l & 1)) & 1) ? -1.0f : 1.0f;
+  const int par = ((mask & 1) ? i : 0) + ((mask & 2) ? j : 0) + ((mask & 4) ? int(l & 1) : 0);
+  return (par & 1) ? -1.0f : 1.0f;
 }
 
 // One launch of the same transform pass over up to three independent (in, out) buffer pairs: the
@@ -623,8 +624,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         x[e] = make_float2(st[(2 * b) * ZS + s], st[(2 * b + 1) * ZS + s]);
         if (a.flip) {
           const long long ra = r0 + 2 * b;
-          x[e] = make_float2(x[e].x * dirichlet_sign(ra, s, a.ny),
-                             x[e].y * dirichlet_sign(ra + 1, s, a.ny));
+          x[e] = make_float2(x[e].x * dirichlet_sign(ra, s, a.ny, a.flip),
+                             x[e].y * dirichlet_sign(ra + 1, s, a.ny, a.flip));
         }
       });
       if constexpr (MODE == ROW_FWD_FP)
@@ -651,8 +652,8 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
           float va = x[e].x, vb = x[e].y;
           if (a.flip) {
             const long long ra = r0 + 2 * b;
-            va *= dirichlet_sign(ra, s, a.ny);
-            vb *= dirichlet_sign(ra + 1, s, a.ny);
+            va *= dirichlet_sign(ra, s, a.ny, a.flip);
+            vb *= dirichlet_sign(ra + 1, s, a.ny, a.flip);
           }
           st[(2 * b) * ZS + s] = va;
           st[(2 * b + 1) * ZS + s] = vb;

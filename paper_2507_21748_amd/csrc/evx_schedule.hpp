@@ -45,8 +45,8 @@ inline int col_block_seqs(int n) {
 
 struct Geom {
   int nx = 0, ny = 0, nz = 0;
-  int bc = BC_PERIODIC;  // transform family: Dirichlet grids run the zero-flux kernels
-  bool dirichlet = false;  // DST-II grid: real rows carry the sign (-1)^(i+j+l), K2 reversed
+  int bc = BC_PERIODIC;  // transform family: Dirichlet axes run the zero-flux kernels
+  int flip = 0;          // Dirichlet (DST-II) axes, bit 0 x, 1 y, 2 z: sign and reversed K2
   int scheme = 0;        // 0 spectral, 1 stencil7
   double dx = 1.0;       // grid spacing baked into the K2 tables
   long long V = 0;       // voxels
@@ -58,14 +58,16 @@ struct Geom {
   long long nrows = 0;   // ny * nz
 };
 
-inline Geom make_geom(int nx, int ny, int nz, int bc, int scheme, double dx) {
+// Per-axis boundaries: all periodic, or any mix of zero flux and Dirichlet.
+inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int scheme, double dx) {
   Geom g;
   g.nx = nx;
   g.ny = ny;
   g.nz = nz;
-  g.dirichlet = bc == BC_DIRICHLET;
-  g.bc = g.dirichlet ? BC_ZERO_FLUX : bc;
-  bc = g.bc;
+  g.flip = (bcx == BC_DIRICHLET ? 1 : 0) | (bcy == BC_DIRICHLET ? 2 : 0) |
+           (bcz == BC_DIRICHLET ? 4 : 0);
+  const int bc = bcx == BC_PERIODIC ? BC_PERIODIC : BC_ZERO_FLUX;
+  g.bc = bc;
   g.scheme = scheme;
   g.dx = dx;
   g.V = (long long)nx * ny * nz;
@@ -120,6 +122,10 @@ inline double axis_k2(int m, int n, int bc, int scheme, double dx) {
   return 4.0 / (dx * dx) * s * s;
 }
 
+inline Geom make_geom(int nx, int ny, int nz, int bc, int scheme, double dx) {
+  return make_geom3(nx, ny, nz, bc, bc, bc, scheme, dx);
+}
+
 // Dirichlet: bin j of the zero-flux transform of the sign-alternated field holds sine mode n - j
 inline std::vector<float> k2_table(int count, int n, int bc, int scheme, double dx,
                                    bool dirichlet = false) {
@@ -145,10 +151,10 @@ inline HostTables make_tables(const Geom& g) {
     h.post_x = makhoul_twiddles(g.nx);
     h.mk_y = makhoul_twiddles(g.ny);
     h.mk_z = makhoul_twiddles(g.nz);
-    h.k2_x = k2_table(g.nx, g.nx, g.bc, g.scheme, g.dx, g.dirichlet);
+    h.k2_x = k2_table(g.nx, g.nx, g.bc, g.scheme, g.dx, (g.flip & 1) != 0);
   }
-  h.k2_y = k2_table(g.ny, g.ny, g.bc, g.scheme, g.dx, g.dirichlet);
-  h.k2_z = k2_table(g.nz, g.nz, g.bc, g.scheme, g.dx, g.dirichlet);
+  h.k2_y = k2_table(g.ny, g.ny, g.bc, g.scheme, g.dx, (g.flip & 2) != 0);
+  h.k2_z = k2_table(g.nz, g.nz, g.bc, g.scheme, g.dx, (g.flip & 4) != 0);
   return h;
 }
 
@@ -212,7 +218,7 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   a.tw = t.tw_x;
   a.post = t.post_x;
   a.scale = (g.bc == BC_PERIODIC) ? float(1.0 / double(g.V)) : float(1.0 / (8.0 * double(g.V)));
-  a.flip = g.dirichlet ? 1 : 0;
+  a.flip = g.flip;
   a.ny = g.ny;
   return a;
 }

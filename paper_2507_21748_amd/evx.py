@@ -56,6 +56,9 @@ def lib_path() -> str:
 
 
 _PROTOS = {
+    "evx_plan_create_axes": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_double],
     "evx_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                         ctypes.c_int, ctypes.c_int, ctypes.c_double],
     "evx_plan_destroy": [ctypes.c_void_p],
@@ -131,7 +134,8 @@ def _dev_ptr(t: torch.Tensor, dtype=torch.float32, numel=None):
 
 
 class Plan:
-    """A grid (nz, ny, nx) with boundary condition and wavenumber scheme, plus its workspace."""
+    """A grid (nz, ny, nx) with boundary condition and wavenumber scheme, plus its workspace.
+    bc is a name for all axes or a (bc_z, bc_y, bc_x) tuple mixing "zero_flux" and "dirichlet"."""
 
     def __init__(self, shape, bc: str = "periodic", scheme: str = "spectral", dx: float = 1.0,
                  ops: int = OP_STEP, device=None):
@@ -144,8 +148,13 @@ class Plan:
         self.device = dev
         h = ctypes.c_void_p()
         with torch.cuda.device(dev):
-            _check(lib.evx_plan_create(ctypes.byref(h), nx, ny, nz, BC[bc], SCHEME[scheme],
-                                       self.dx), "evx_plan_create")
+            if isinstance(bc, str):
+                _check(lib.evx_plan_create(ctypes.byref(h), nx, ny, nz, BC[bc], SCHEME[scheme],
+                                           self.dx), "evx_plan_create")
+            else:
+                bz, by, bx = (BC[b] for b in bc)
+                _check(lib.evx_plan_create_axes(ctypes.byref(h), nx, ny, nz, bx, by, bz,
+                                                SCHEME[scheme], self.dx), "evx_plan_create_axes")
         self._h = h
         nb = ctypes.c_size_t()
         _check(lib.evx_plan_workspace_bytes(h, ops, ctypes.byref(nb)), "evx_plan_workspace_bytes")

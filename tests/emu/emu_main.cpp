@@ -7,7 +7,8 @@
 //
 // usage: evx_emu nx ny nz bc scheme dx dt M kappa A nsteps remap in.f32 out.f32 [integrator [model]]
 //   integrator 0 semi-implicit / 1 ETD1; model 0 Cahn-Hilliard / 1 Allen-Cahn.
-//   bc 0 periodic / 1 zero flux; scheme 0 spectral / 1 stencil7.  nsteps < 0 runs |nsteps| steps
+//   bc 0 periodic / 1 zero flux / 2 Dirichlet, or 100 bc_x + 10 bc_y + bc_z mixing 1 and 2;
+//   scheme 0 spectral / 1 stencil7.  nsteps < 0 runs |nsteps| steps
 //   in two halves with an end + restore between them (the resume path).
 //        evx_emu adj nx ny nz bc scheme dx dt M kappa A c.f32 lam.f32 out_lam.f32 out_grad.f64
 //   one adjoint step (lam <- dL/dc^n, out_grad = [dL/dkappa, dL/dM] of the step).
@@ -28,6 +29,13 @@ thread_local std::barrier<>* block_barrier = nullptr;
 }
 
 using namespace evx;
+
+// bc 0 / 1 / 2 for all axes, or a 3-digit code 100 bc_x + 10 bc_y + bc_z of zero flux (1) and
+// Dirichlet (2) per axis
+static Geom geom_of(int nx, int ny, int nz, int bc, int scheme, double dx) {
+  if (bc >= 100) return make_geom3(nx, ny, nz, bc / 100, (bc / 10) % 10, bc % 10, scheme, dx);
+  return make_geom(nx, ny, nz, bc, scheme, dx);
+}
 
 template <class Body>
 static void run_grid(int nblk, int threads, int lds_slots, Body body) {
@@ -190,7 +198,7 @@ static int run_aux(int argc, char** argv) {
   const int nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
   const int bc = std::atoi(argv[5]), scheme = std::atoi(argv[6]);
   const double dx = std::atof(argv[7]);
-  const Geom g = make_geom(nx, ny, nz, bc, scheme, dx);
+  const Geom g = geom_of(nx, ny, nz, bc, scheme, dx);
   Tabs tb(g);
   std::vector<float2> A(g.spec), B(g.spec), Lm(g.spec);
   std::vector<float> v(g.V), c(g.V);
@@ -235,7 +243,7 @@ int main(int argc, char** argv) {
   const double dx = std::atof(argv[6]), dt = std::atof(argv[7]), M = std::atof(argv[8]);
   const double kappa = std::atof(argv[9]), A = std::atof(argv[10]);
   const int nsteps = std::atoi(argv[11]), remap = std::atoi(argv[12]);
-  const Geom g = make_geom(nx, ny, nz, bc, scheme, dx);
+  const Geom g = geom_of(nx, ny, nz, bc, scheme, dx);
   const HostTables h = make_tables(g);
   TablePtrs t{h.tw_x.data(), h.tw_y.data(), h.tw_z.data(), h.post_x.data(),
               h.mk_y.empty() ? nullptr : h.mk_y.data(), h.mk_z.empty() ? nullptr : h.mk_z.data(),

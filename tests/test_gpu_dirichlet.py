@@ -121,3 +121,41 @@ def test_with_other_integrators_and_models(evx_gpu, which):
     else:
         ref = ch.ch_step_etd1(c64, p, "dirichlet", scheme)
     assert rel_l2(c.cpu().numpy(), ref) <= 1e-5
+
+
+MIXES = [("dirichlet", "zero_flux", "zero_flux"), ("zero_flux", "dirichlet", "dirichlet"),
+         ("zero_flux", "zero_flux", "dirichlet")]
+
+
+@pytest.mark.parametrize("bcs", MIXES)
+@pytest.mark.parametrize("scheme", ["spectral", "stencil7"])
+def test_mixed_axes_parity(evx_gpu, bcs, scheme):
+    """Per-axis boundaries (z, y, x): one step within 1e-5 and 20 steps within 1e-4 of the
+    oracle."""
+    shape = (24, 20, 32)
+    p = OParams(dt=0.5, M=0.8, kappa=1.3, A=2.0)
+    c0 = quench_field(shape, 0.0, 0.3, seed=66)
+    got1 = gpu_run(evx_gpu, c0, bcs, scheme, 1, p)
+    assert rel_l2(got1, ch.ch_step(c0.astype(np.float64), p, bcs, scheme)) <= 1e-5
+    got20 = gpu_run(evx_gpu, c0, bcs, scheme, 20, p)
+    assert rel_l2(got20, ch.ch_run(c0, 20, p, bcs, scheme)) <= 1e-4
+
+
+def test_mixed_axes_extension_identity_on_gpu(evx_gpu):
+    """z Dirichlet, y zero flux, x Dirichlet at 64 x 96 x 128 for 5 steps = periodic
+    128 x 192 x 256 on the extension odd in z and x and even in y (both on the GPU)."""
+    p = OParams(dt=0.5)
+    bcs = ("dirichlet", "zero_flux", "dirichlet")
+    c0 = quench_field((64, 96, 128), 0.0, 0.3, seed=67)
+    e = c0
+    for ax, b in enumerate(bcs):
+        e = np.concatenate([e, (-1.0 if b == "dirichlet" else 1.0) * np.flip(e, axis=ax)], axis=ax)
+    per = gpu_run(evx_gpu, e.astype(np.float32), "periodic", "spectral", 5, p)[:64, :96, :128]
+    got = gpu_run(evx_gpu, c0, bcs, "spectral", 5, p)
+    assert rel_l2(got, per) <= 2e-5
+
+
+def test_periodic_mixed_with_other_axes_is_unsupported(evx_gpu):
+    with pytest.raises(evx_gpu.EvxError) as e:
+        evx_gpu.Plan((16, 16, 16), ("periodic", "zero_flux", "zero_flux"), "spectral")
+    assert e.value.status == 3
