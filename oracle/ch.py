@@ -112,13 +112,14 @@ def axis_k2(n: int, dx: float, bc: str, scheme: str) -> np.ndarray:
 
 
 def axis_bcs(bc):
-    """Per-axis boundary conditions (z, y, x): a name for all three axes, or a 3-tuple mixing
-    'zero_flux' and 'dirichlet' (the transforms are then applied axis by axis)."""
+    """Per-axis boundary conditions (z, y, x): a name for all three axes, or a 3-tuple of
+    'periodic', 'zero_flux' and 'dirichlet' (the transforms are then applied axis by axis; a DCT
+    or DST of complex data transforms its real and imaginary parts)."""
     if isinstance(bc, str):
         return (bc, bc, bc)
     bcs = tuple(bc)
-    if len(bcs) != 3 or any(b not in ("zero_flux", "dirichlet") for b in bcs):
-        raise ValueError(f"per-axis bc must mix 'zero_flux' and 'dirichlet': {bc!r}")
+    if len(bcs) != 3 or any(b not in ("periodic", "zero_flux", "dirichlet") for b in bcs):
+        raise ValueError(f"bad per-axis bc {bc!r}")
     return bcs
 
 
@@ -134,11 +135,14 @@ def k2_grid(shape, dx: float, bc, scheme: str) -> np.ndarray:
 def T(c, bc: str):
     """Forward transform, unnormalised: full complex 3D DFT (periodic), 3D DCT-II (zero flux) or
     3D DST-II (Dirichlet)."""
-    if not isinstance(bc, str):  # per-axis DCT-II / DST-II
-        out = np.asarray(c, dtype=np.float64)
+    if not isinstance(bc, str):  # per-axis DFT / DCT-II / DST-II
+        out = np.asarray(c)
         for ax, b in enumerate(axis_bcs(bc)):
-            f = sfft.dst if b == "dirichlet" else sfft.dct
-            out = f(out, type=2, axis=ax, workers=WORKERS)
+            if b == "periodic":
+                out = sfft.fft(out, axis=ax, workers=WORKERS)
+            else:
+                f = sfft.dst if b == "dirichlet" else sfft.dct
+                out = f(out, type=2, axis=ax, workers=WORKERS)
         return out
     if bc == "periodic":
         return sfft.fftn(c, workers=WORKERS)
@@ -154,11 +158,14 @@ def Tinv(C, bc: str, keep_complex: bool = False):
         out = sfft.ifftn(C, workers=WORKERS)
         return out if keep_complex else out.real
     if not isinstance(bc, str):
-        out = np.asarray(C, dtype=np.float64)
+        out = np.asarray(C)
         for ax, b in enumerate(axis_bcs(bc)):
-            f = sfft.idst if b == "dirichlet" else sfft.idct
-            out = f(out, type=2, axis=ax, workers=WORKERS)
-        return out
+            if b == "periodic":
+                out = sfft.ifft(out, axis=ax, workers=WORKERS)
+            else:
+                f = sfft.idst if b == "dirichlet" else sfft.idct
+                out = f(out, type=2, axis=ax, workers=WORKERS)
+        return out if (keep_complex or not np.iscomplexobj(out)) else out.real
     if bc == "dirichlet":
         return sfft.idstn(C, type=2, workers=WORKERS)
     return sfft.idctn(C, type=2, workers=WORKERS)
