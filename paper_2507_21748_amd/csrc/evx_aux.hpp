@@ -27,6 +27,7 @@ struct SpecArgs {
   float2* L;        // in: T[lam^{n+1}]; out: G P Lam        (the A operator's multiplier)
   long long n;      // float2 elements of a spectral buffer
   int nx, ny, nz, pitch, ncols, bc;  // pitch: float2 per row; ncols: of them holding data
+  int bcy, bcz;                      // y and z transform families (x periodic may mix them)
   const float *k2x, *k2y, *k2z;
   float a_dt, dt_m_kappa, dt_m, dt, dt_kappa;
   double* partial;  // 2 per block: sum for dL/dkappa, sum for dL/dM (before the 1/V factor)
@@ -76,8 +77,12 @@ EVX_DEV void spec_body(const SpecArgs& a, int tid, int bid, int nblk, double* re
     double w[2];
     if (a.bc == BC_PERIODIC) {
       K2[0] = K2[1] = a.k2x[xc] + kyz;
+      // half spectrum along x; a cosine axis weighs its bins n w_k relative to a periodic one
+      // (the 1/V normalisation is applied to the sums)
       const double wx = (xc == 0 || 2 * xc == a.nx) ? 1.0 : 2.0;
-      w[0] = w[1] = wx;
+      const double fy = a.bcy == BC_PERIODIC ? 1.0 : (y == 0 ? 0.25 : 0.5);
+      const double fz = a.bcz == BC_PERIODIC ? 1.0 : (z == 0 ? 0.25 : 0.5);
+      w[0] = w[1] = wx * fy * fz;
     } else {
       K2[0] = a.k2x[2 * xc] + kyz;
       K2[1] = a.k2x[2 * xc + 1] + kyz;

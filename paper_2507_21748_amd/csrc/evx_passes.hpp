@@ -62,6 +62,7 @@ struct ColArgs {
   float dt_m_kappa;        // dt M kappa
   float dt_m;              // dt M
   int remap;               // XCD-aware block order
+  int xcomplex;            // zero-flux z pass under a periodic x: a column is one complex x bin
   unsigned lane_bytes;     // bytes addressable from a point's block base (col_lane_bytes)
 };
 
@@ -326,8 +327,13 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
     const int o = ct.live ? ct.outer : 0, cc = ct.live ? ct.col : 0;
     const float ko = a.k2o[o];
     if constexpr (zf) {
-      kca = a.k2c[2 * cc] + ko;
-      kcb = a.k2c[2 * cc + 1] + ko;
+      if (a.xcomplex) {  // both components belong to x bin cc
+        kca = a.k2c[cc] + ko;
+        kcb = kca;
+      } else {           // two real x bins per column
+        kca = a.k2c[2 * cc] + ko;
+        kcb = a.k2c[2 * cc + 1] + ko;
+      }
     } else {
       kca = a.k2c[cc] + ko;
       kcb = kca;
@@ -548,6 +554,10 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       pos.store(pol, tid);
       evx_sync();
       static_for<E>([&](auto e) { x[e] = lds[b * NH + t + TPS * decltype(e)::value]; });
+      if (a.flip) {  // Dirichlet y / z: one sign per row
+        const float sg = dirichlet_sign(r0 + b, 0, a.ny, a.flip);
+        static_for<E>([&](auto e) { x[e] = cscale(x[e], sg); });
+      }
       if constexpr (MODE == ROW_FWD_FP)
         static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
       evx_sync();
@@ -569,7 +579,10 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       fft_regs<NH, +1, B>(x, lds, b, t, twl);
       static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
       if constexpr (MODE == ROW_INV || MODE == ROW_FUSED_REC) {
-        static_for<E>([&](auto e) { lds[b * NH + t + TPS * decltype(e)::value] = x[e]; });
+        const float sg = a.flip ? dirichlet_sign(r0 + b, 0, a.ny, a.flip) : 1.0f;
+        static_for<E>([&](auto e) {
+          lds[b * NH + t + TPS * decltype(e)::value] = a.flip ? cscale(x[e], sg) : x[e];
+        });
         evx_sync();
         copy_out<B * NH, T>(reinterpret_cast<float2*>(a.out_r) + r0 * NH, (a.nrows - r0) * NH,
                             lds, tid);

@@ -45,7 +45,8 @@ inline int col_block_seqs(int n) {
 
 struct Geom {
   int nx = 0, ny = 0, nz = 0;
-  int bc = BC_PERIODIC;  // transform family: Dirichlet axes run the zero-flux kernels
+  int bc = BC_PERIODIC;  // x transform family: Dirichlet axes run the zero-flux kernels
+  int bcy = BC_PERIODIC, bcz = BC_PERIODIC;  // y and z transform families
   int flip = 0;          // Dirichlet (DST-II) axes, bit 0 x, 1 y, 2 z: sign and reversed K2
   int scheme = 0;        // 0 spectral, 1 stencil7
   double dx = 1.0;       // grid spacing baked into the K2 tables
@@ -58,7 +59,8 @@ struct Geom {
   long long nrows = 0;   // ny * nz
 };
 
-// Per-axis boundaries: all periodic, or any mix of zero flux and Dirichlet.
+// Per-axis boundaries: x periodic with any y and z, or any mix of zero flux and Dirichlet (a
+// non-periodic x makes the spectral data real, which a periodic y or z transform cannot keep).
 inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int scheme, double dx) {
   Geom g;
   g.nx = nx;
@@ -68,6 +70,8 @@ inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int sc
            (bcz == BC_DIRICHLET ? 4 : 0);
   const int bc = bcx == BC_PERIODIC ? BC_PERIODIC : BC_ZERO_FLUX;
   g.bc = bc;
+  g.bcy = bcy == BC_PERIODIC ? BC_PERIODIC : BC_ZERO_FLUX;
+  g.bcz = bcz == BC_PERIODIC ? BC_PERIODIC : BC_ZERO_FLUX;
   g.scheme = scheme;
   g.dx = dx;
   g.V = (long long)nx * ny * nz;
@@ -149,12 +153,12 @@ inline HostTables make_tables(const Geom& g) {
     h.k2_x = k2_table(g.nx / 2 + 1, g.nx, g.bc, g.scheme, g.dx);
   } else {
     h.post_x = makhoul_twiddles(g.nx);
-    h.mk_y = makhoul_twiddles(g.ny);
-    h.mk_z = makhoul_twiddles(g.nz);
     h.k2_x = k2_table(g.nx, g.nx, g.bc, g.scheme, g.dx, (g.flip & 1) != 0);
   }
-  h.k2_y = k2_table(g.ny, g.ny, g.bc, g.scheme, g.dx, (g.flip & 2) != 0);
-  h.k2_z = k2_table(g.nz, g.nz, g.bc, g.scheme, g.dx, (g.flip & 4) != 0);
+  if (g.bcy != BC_PERIODIC) h.mk_y = makhoul_twiddles(g.ny);
+  if (g.bcz != BC_PERIODIC) h.mk_z = makhoul_twiddles(g.nz);
+  h.k2_y = k2_table(g.ny, g.ny, g.bcy, g.scheme, g.dx, (g.flip & 2) != 0);
+  h.k2_z = k2_table(g.nz, g.nz, g.bcz, g.scheme, g.dx, (g.flip & 4) != 0);
   return h;
 }
 
@@ -204,6 +208,7 @@ inline ColArgs z_args(const Geom& g, const TablePtrs& t, const float2* in, float
   a.dt_m_kappa = c.dt_m_kappa;
   a.dt_m = c.dt_m;
   a.remap = remap;
+  a.xcomplex = g.bc == BC_PERIODIC ? 1 : 0;
   return a;
 }
 
@@ -217,7 +222,9 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   a.nrows = g.nrows;
   a.tw = t.tw_x;
   a.post = t.post_x;
-  a.scale = (g.bc == BC_PERIODIC) ? float(1.0 / double(g.V)) : float(1.0 / (8.0 * double(g.V)));
+  // inverse normalisation: 1/n per periodic axis, 1/(2n) per cosine (DCT-III of DCT-II) axis
+  const int ncos = (g.bc != BC_PERIODIC) + (g.bcy != BC_PERIODIC) + (g.bcz != BC_PERIODIC);
+  a.scale = float(1.0 / (double(1 << ncos) * double(g.V)));
   a.flip = g.flip;
   a.ny = g.ny;
   return a;
@@ -230,8 +237,8 @@ template <class L>
 void sched_begin(L& l, const Geom& g, const TablePtrs& t, const float* c, float2* S, float2* W,
                  int remap) {
   l.row(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, c, W, nullptr));
-  l.col(g.ny, g.bc, COL_FWD, y_args(g, t, W, W, remap));
-  l.col(g.nz, g.bc, COL_Z_INIT, z_args(g, t, W, W, S, StepCoef{0, 0, 0}, remap));
+  l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+  l.col(g.nz, g.bcz, COL_Z_INIT, z_args(g, t, W, W, S, StepCoef{0, 0, 0}, remap));
 }
 
 // nsteps steps; W must hold F_z^{-1} S on entry and holds it again on exit.
@@ -239,10 +246,10 @@ template <class L>
 void sched_advance(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, StepCoef c,
                    int nsteps, int remap, int zmode = COL_Z_UPDATE) {
   for (int n = 0; n < nsteps; ++n) {
-    l.col(g.ny, g.bc, COL_INV, y_args(g, t, W, W, remap));
+    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
     l.row(g.row_len, g.bc, ROW_FUSED, x_args(g, t, W, nullptr, W, nullptr));
-    l.col(g.ny, g.bc, COL_FWD, y_args(g, t, W, W, remap));
-    l.col(g.nz, g.bc, zmode, z_args(g, t, W, W, S, c, remap));
+    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.nz, g.bcz, zmode, z_args(g, t, W, W, S, c, remap));
   }
 }
 
@@ -252,24 +259,24 @@ template <class L>
 void sched_advance_record(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W,
                           StepCoef c, int nsteps, int remap, int zmode, float* traj) {
   for (int n = 0; n < nsteps; ++n) {
-    l.col(g.ny, g.bc, COL_INV, y_args(g, t, W, W, remap));
+    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
     l.row(g.row_len, g.bc, ROW_FUSED_REC, x_args(g, t, W, nullptr, W, traj + (long long)n * g.V));
-    l.col(g.ny, g.bc, COL_FWD, y_args(g, t, W, W, remap));
-    l.col(g.nz, g.bc, zmode, z_args(g, t, W, W, S, c, remap));
+    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.nz, g.bcz, zmode, z_args(g, t, W, W, S, c, remap));
   }
 }
 
 // Real field from W = F_z^{-1} S (consumes W).
 template <class L>
 void sched_end(L& l, const Geom& g, const TablePtrs& t, float* c, float2* W, int remap) {
-  l.col(g.ny, g.bc, COL_INV, y_args(g, t, W, W, remap));
+  l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
   l.row(g.row_len, g.bc, ROW_INV, x_args(g, t, W, nullptr, nullptr, c));
 }
 
 // W <- F_z^{-1} S (restores the loop-entry buffer from the state).
 template <class L>
 void sched_restore(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, int remap) {
-  l.col(g.nz, g.bc, COL_Z_INV_STATE, z_args(g, t, nullptr, W, S, StepCoef{0, 0, 0}, remap));
+  l.col(g.nz, g.bcz, COL_Z_INV_STATE, z_args(g, t, nullptr, W, S, StepCoef{0, 0, 0}, remap));
 }
 
 }  // namespace evx

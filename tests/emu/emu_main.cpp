@@ -7,7 +7,7 @@
 //
 // usage: evx_emu nx ny nz bc scheme dx dt M kappa A nsteps remap in.f32 out.f32 [integrator [model]]
 //   integrator 0 semi-implicit / 1 ETD1; model 0 Cahn-Hilliard / 1 Allen-Cahn.
-//   bc 0 periodic / 1 zero flux / 2 Dirichlet, or 100 bc_x + 10 bc_y + bc_z mixing 1 and 2;
+//   bc 0 periodic / 1 zero flux / 2 Dirichlet, or 1000 + 100 bc_x + 10 bc_y + bc_z per axis;
 //   scheme 0 spectral / 1 stencil7.  nsteps < 0 runs |nsteps| steps
 //   in two halves with an end + restore between them (the resume path).
 //        evx_emu adj nx ny nz bc scheme dx dt M kappa A c.f32 lam.f32 out_lam.f32 out_grad.f64
@@ -30,10 +30,11 @@ thread_local std::barrier<>* block_barrier = nullptr;
 
 using namespace evx;
 
-// bc 0 / 1 / 2 for all axes, or a 3-digit code 100 bc_x + 10 bc_y + bc_z of zero flux (1) and
-// Dirichlet (2) per axis
+// bc 0 / 1 / 2 for all axes, or 1000 + 100 bc_x + 10 bc_y + bc_z with periodic (0), zero flux
+// (1) and Dirichlet (2) per axis
 static Geom geom_of(int nx, int ny, int nz, int bc, int scheme, double dx) {
-  if (bc >= 100) return make_geom3(nx, ny, nz, bc / 100, (bc / 10) % 10, bc % 10, scheme, dx);
+  if (bc >= 1000)
+    return make_geom3(nx, ny, nz, (bc / 100) % 10, (bc / 10) % 10, bc % 10, scheme, dx);
   return make_geom(nx, ny, nz, bc, scheme, dx);
 }
 

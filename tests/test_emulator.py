@@ -66,7 +66,8 @@ def _run(exe, shape, bc, scheme, nsteps, p, c0, remap=1, integrator=0, model=0):
         c0.astype(np.float32).tofile(os.path.join(d, "in"))
         env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=0")
         code = {"periodic": 0, "zero_flux": 1, "dirichlet": 2}
-        bcarg = code[bc] if isinstance(bc, str) else 100 * code[bc[2]] + 10 * code[bc[1]] + code[bc[0]]
+        bcarg = code[bc] if isinstance(bc, str) else \
+            1000 + 100 * code[bc[2]] + 10 * code[bc[1]] + code[bc[0]]
         r = subprocess.run([exe, str(nx), str(ny), str(nz), str(bcarg),
                             str(int(scheme == "stencil7")), repr(p.dx), repr(p.dt), repr(p.M),
                             repr(p.kappa), repr(p.A), str(nsteps), str(remap),
@@ -114,9 +115,11 @@ def test_emulated_allen_cahn_matches_oracle(asan, shape, bc, scheme, n, etd1):
     assert _rel(got, ref) <= 1e-6
 
 
-def test_emulated_mixed_axes_match_oracle(asan):
-    """Per-axis boundaries (z Dirichlet, y zero flux, x Dirichlet) against the oracle."""
-    shape, bcs = (12, 20, 16), ("dirichlet", "zero_flux", "dirichlet")
+@pytest.mark.parametrize("bcs", [("dirichlet", "zero_flux", "dirichlet"),
+                                 ("zero_flux", "dirichlet", "periodic")])
+def test_emulated_mixed_axes_match_oracle(asan, bcs):
+    """Per-axis boundaries (z, y, x) against the oracle, with and without a periodic x."""
+    shape = (12, 20, 16)
     p = CHParams(dt=0.5, M=0.9, kappa=1.1, A=2.0)
     c0 = quench_field(shape, 0.1, 0.3, seed=17)
     got = _run(asan, shape, bcs, "stencil7", 2, p, c0)
@@ -193,7 +196,11 @@ def test_planted_missing_barrier_is_caught(tmp_path):
 
 @pytest.mark.parametrize("shape,bc,scheme", [((16, 12, 16), "periodic", "spectral"),
                                              ((8, 24, 16), "zero_flux", "stencil7"),
-                                             ((12, 16, 20), "zero_flux", "spectral")])
+                                             ((12, 16, 20), "zero_flux", "spectral"),
+                                             ((12, 20, 16), ("zero_flux", "dirichlet",
+                                                             "periodic"), "stencil7"),
+                                             ((12, 20, 16), ("dirichlet", "zero_flux",
+                                                             "dirichlet"), "spectral")])
 def test_emulated_adjoint_step_and_diagnostics(asan, shape, bc, scheme):
     """One adjoint step (lam, dL/dkappa, dL/dM) and the mass/energy diagnostics of the emulated
     kernels against the oracle's adjoint and energy."""
@@ -204,8 +211,10 @@ def test_emulated_adjoint_step_and_diagnostics(asan, shape, bc, scheme):
     c1 = ch.ch_step(c.astype(np.float64), p, bc, scheme)
     _, g, dk, dM = adjoint.adjoint_gradients(c, c1 - lam.astype(np.float64) / 2, 1, p, bc, scheme)
     nz, ny, nx = shape
-    geo = [str(nx), str(ny), str(nz), str(int(bc == "zero_flux")), str(int(scheme == "stencil7")),
-           "1"]
+    code = {"periodic": 0, "zero_flux": 1, "dirichlet": 2}
+    bcarg = code[bc] if isinstance(bc, str) else \
+        1000 + 100 * code[bc[2]] + 10 * code[bc[1]] + code[bc[0]]
+    geo = [str(nx), str(ny), str(nz), str(bcarg), str(int(scheme == "stencil7")), "1"]
     with tempfile.TemporaryDirectory() as d:
         c.tofile(os.path.join(d, "c"))
         lam.tofile(os.path.join(d, "l"))

@@ -24,7 +24,8 @@ def rel(a, b):
 
 CASES = [((16, 12, 16), "periodic", "spectral"), ((8, 24, 16), "zero_flux", "stencil7"),
          ((32, 40, 48), "zero_flux", "spectral"), ((24, 32, 20), "periodic", "stencil7"),
-         ((16, 12, 16), "dirichlet", "spectral"), ((8, 24, 16), "dirichlet", "stencil7")]
+         ((16, 12, 16), "dirichlet", "spectral"), ((8, 24, 16), "dirichlet", "stencil7"),
+         ((12, 20, 16), ("zero_flux", "dirichlet", "periodic"), "stencil7")]
 
 
 @pytest.mark.parametrize("shape,bc,scheme", CASES)

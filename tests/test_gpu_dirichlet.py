@@ -124,7 +124,8 @@ def test_with_other_integrators_and_models(evx_gpu, which):
 
 
 MIXES = [("dirichlet", "zero_flux", "zero_flux"), ("zero_flux", "dirichlet", "dirichlet"),
-         ("zero_flux", "zero_flux", "dirichlet")]
+         ("zero_flux", "zero_flux", "dirichlet"), ("zero_flux", "dirichlet", "periodic"),
+         ("periodic", "zero_flux", "periodic"), ("dirichlet", "periodic", "periodic")]
 
 
 @pytest.mark.parametrize("bcs", MIXES)
