@@ -17,6 +17,10 @@
  * Neumann data, so a cosine transform diagonalises it).  K2 is the eigenvalue of -lap: k^2
  * (spectral) or sum over axes of (4/dx^2) sin^2(k dx / 2) (7-point stencil).
  *
+ * The same passes also run Dirichlet boundaries (DST-II) and per-axis boundary mixes (evx_bc,
+ * evx_plan_create_axes), an exponential (ETD1) integrator and the Allen-Cahn model (the
+ * integrator and model fields of evx_ch_params).
+ *
  * Conventions for every entry point:
  *   - Arrays are C order (nz, ny, nx), x fastest, FP32, in device memory of the device that was
  *     current when the plan was created; that device must be current for every call.
