@@ -1,0 +1,59 @@
+"""Pins of the Gray-Scott oracle: the uniform-field map (the reaction ODE stepped by hand), the
+fixed point (1, 0), closed-form decay of small modes around it for each species, and a dense
+brute-force solve of each species' linear system."""
+import numpy as np
+import pytest
+
+from oracle import ch, gray_scott as gs
+from paper_2507_21748_amd.inputs import quench_field
+from tests.test_oracle_ch import _dense_laplacian
+
+BCS = ["periodic", "zero_flux"]
+SCHEMES = ["spectral", "stencil7"]
+
+
+def test_uniform_field_map_and_fixed_point():
+    p = gs.GSParams(dt=0.7)
+    for u0, v0 in ((0.5, 0.25), (1.0, 0.0), (0.3, 0.6)):
+        u = np.full((4, 6, 8), u0)
+        v = np.full((4, 6, 8), v0)
+        un, vn = gs.gs_step(u, v, p, "periodic", "spectral")
+        uv2 = u0 * v0 * v0
+        assert np.max(np.abs(un - (u0 + p.dt * (-uv2 + p.F * (1 - u0))))) < 1e-14
+        assert np.max(np.abs(vn - (v0 + p.dt * (uv2 - (p.F + p.k) * v0)))) < 1e-14
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_small_modes_decay_in_closed_form(bc, scheme):
+    """Around (1, 0): R_u = -F du + O(dv^2), R_v = -(F + k) dv + O(du dv^2), so a small mode of
+    each species decays by (1 - dt F) / (1 + dt D_u K2) and (1 - dt (F + k)) / (1 + dt D_v K2)."""
+    from paper_2507_21748_amd.inputs import mode_field
+    p = gs.GSParams(dt=0.5)
+    shape, m, n, delta = (8, 12, 16), (1, 1, 2), 5, 1e-7
+    mode = mode_field(shape, 0.0, 1.0, m, bc).astype(np.float64)
+    u, v = 1.0 + delta * mode, delta * mode
+    for _ in range(n):
+        u, v = gs.gs_step(u, v, p, bc, scheme)
+    K2 = sum(ch.axis_k2(s, p.dx, bc, scheme)[mi] for s, mi in zip(shape, m))
+    gu = (1 - p.dt * p.F) / (1 + p.dt * p.Du * K2)
+    gv = (1 - p.dt * (p.F + p.k)) / (1 + p.dt * p.Dv * K2)
+    au = np.sum((u - 1.0) * mode) / np.sum(mode * mode)
+    av = np.sum(v * mode) / np.sum(mode * mode)
+    assert abs(au / (delta * gu ** n) - 1) < 1e-6
+    assert abs(av / (delta * gv ** n) - 1) < 1e-6
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_step_equals_dense_solve(bc, scheme):
+    p = gs.GSParams(dx=0.8, dt=0.6)
+    u = quench_field((4, 6, 4), 0.6, 0.3, seed=21).astype(np.float64)
+    v = quench_field((4, 6, 4), 0.3, 0.3, seed=22).astype(np.float64)
+    L = _dense_laplacian(u.shape, p.dx, bc, scheme)
+    I = np.eye(L.shape[0])
+    ru, rv = gs.reaction(u, v, p)
+    uref = np.linalg.solve(I - p.dt * p.Du * L, (u + p.dt * ru).reshape(-1)).reshape(u.shape)
+    vref = np.linalg.solve(I - p.dt * p.Dv * L, (v + p.dt * rv).reshape(-1)).reshape(u.shape)
+    un, vn = gs.gs_step(u, v, p, bc, scheme)
+    assert np.max(np.abs(un - uref)) < 1e-12 and np.max(np.abs(vn - vref)) < 1e-12
