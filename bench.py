@@ -8,8 +8,8 @@ seed 3, dt 0.5, spectral wavenumbers).  The line also carries:
                  duration, timed with HIP events on the launch stream inside the timed region;
   cpu_baseline - the FP64 oracle (SciPy FFTs) timed on this host on a bounded sample;
   extra        - smaller and zero-flux grids, the exponential (ETD1) stepper and the Allen-Cahn
-                 model on the same workload, the inverse-problem gradient and the learned coarse
-                 stepper.
+                 model on the same workload, Dirichlet boundaries, the Gray-Scott model, the
+                 inverse-problem gradient and the learned coarse stepper.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
        python bench.py --summarize-profile DIR [--workload NAME]
@@ -284,6 +284,26 @@ def adjoint_workload(evx, torch, w, steps: int = 200, every: int = 20):
     return out
 
 
+def gray_scott_workload(evx, torch, n: int = 256, steps: int = 100):
+    """The Gray-Scott two-species model on a 256^3 periodic spectral grid (u ~ 1, v seeded as a
+    0.25 +- 0.2 quench): ms per step (8 launches: reaction, 4 batched forward transforms, spectral
+    update, 2 batched inverse transforms)."""
+    from paper_2507_21748_amd.inputs import quench_field
+    shape = (n, n, n)
+    plan = evx.Plan(shape, "periodic", "spectral", ops=evx.OP_STEP | evx.OP_GRAY_SCOTT)
+    u = torch.from_numpy(quench_field(shape, 0.75, 0.2, seed=11)).cuda()
+    v = torch.from_numpy(quench_field(shape, 0.25, 0.2, seed=12)).cuda()
+    prm = evx.GSParams(dt=1.0)
+    plan.gs_step(u, v, 5, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.gs_step(u, v, steps, prm)
+    torch.cuda.synchronize()
+    secs = (time.perf_counter() - t0) / steps
+    return {"grid": [n, n, n], "ms_per_step": 1e3 * secs,
+            "finite": bool(torch.isfinite(u).all().item() and torch.isfinite(v).all().item())}
+
+
 def surrogate_workload(torch, w, reps: int = 5):
     """One coarse-stepper application (4 convolution layers, residual, mass projection) on the
     512^3 field: ms per application and the convolution flop rate (114,048 flop/voxel)."""
@@ -452,6 +472,7 @@ def main():
         r = run_workload(evx, torch, wd, 200, 10, timing=False)
         extra["ch256_dirichlet"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
                                     "ms_per_step": r["ms_per_step"]}
+        extra["gray_scott256"] = gray_scott_workload(evx, torch)
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
         extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
         line["extra"] = extra

@@ -19,7 +19,8 @@
  *
  * The same passes also run Dirichlet boundaries (DST-II) and per-axis boundary mixes (evx_bc,
  * evx_plan_create_axes), an exponential (ETD1) integrator and the Allen-Cahn model (the
- * integrator and model fields of evx_ch_params).
+ * integrator and model fields of evx_ch_params), and the Gray-Scott two-species model
+ * (evx_gs_step).
  *
  * Conventions for every entry point:
  *   - Arrays are C order (nz, ny, nx), x fastest, FP32, in device memory of the device that was
@@ -99,7 +100,7 @@ typedef struct evx_ch_params {
 } evx_ch_params;
 
 /* Workspace users (bit mask for evx_plan_workspace_bytes). */
-enum { EVX_OP_STEP = 1, EVX_OP_DIAG = 2, EVX_OP_ADJOINT = 4 };
+enum { EVX_OP_STEP = 1, EVX_OP_DIAG = 2, EVX_OP_ADJOINT = 4, EVX_OP_GRAY_SCOTT = 8 };
 
 typedef struct evx_plan evx_plan;
 
@@ -186,6 +187,26 @@ evx_status evx_ch_adjoint_step(evx_plan* plan, const float* c_n, float* lam,
  * out[1] = dx^3 [sum f(c) + (kappa/2) sum c (-L c)], L the plan's discrete Laplacian.
  * c: device, V floats (read).  out: two device doubles (written).  Only params->kappa is used.
  * Needs a workspace sized with EVX_OP_DIAG or EVX_OP_ADJOINT. */
+/* Gray-Scott two-species model (the paper's reaction-diffusion example, appendix
+ * "Reaction-diffusion systems"):
+ *   du/dt = Du lap u - u v^2 + F (1 - u),   dv/dt = Dv lap v + u v^2 - (F + k) v,
+ * stepped with the same symbol rule: diffusion implicit, reaction explicit,
+ *   U' = (U + dt T[R_u]) / (1 + dt Du K2),  V' = (V + dt T[R_v]) / (1 + dt Dv K2).
+ * u, v: caller-owned real fields (C order, V floats each), advanced nsteps in place on the plan's
+ * grid, boundaries and scheme.  Needs a workspace sized for EVX_OP_GRAY_SCOTT (EVX_ERR_NOMEM
+ * otherwise); it uses the stepper's work buffer, so a later evx_ch_advance restores it from the
+ * state first.  Per step: one reaction kernel, the four forward transforms batched per pass, one
+ * spectral update, the two inverse transforms batched per pass. */
+typedef struct evx_gs_params {
+  double dt;
+  double Du;
+  double Dv;
+  double F;
+  double k;
+} evx_gs_params;
+evx_status evx_gs_step(evx_plan* plan, float* u, float* v, int nsteps, const evx_gs_params* params,
+                       void* hip_stream);
+
 evx_status evx_ch_diagnostics(evx_plan* plan, const float* c, const evx_ch_params* params,
                               double* out, void* hip_stream);
 

@@ -38,6 +38,7 @@ struct AdjointBufs {
   float2 *A, *B, *Lm;  // spectral scratch
   float* v;            // real scratch
   double* partial;     // 2 * AUX_BLOCKS
+  float* v2;           // second real scratch (two-species model)
 };
 
 struct AdjointCoef {
@@ -120,6 +121,48 @@ void sched_distance(L& l, const Geom& g, const float* a, const float* b, const A
                     double* out) {
   l.realsum(RealSumArgs{a, g.V, bufs.partial, b});
   l.final(FinalArgs{bufs.partial, AUX_BLOCKS, out, out + 1, 1.0, 1.0, 0, 0});
+}
+
+// Gray-Scott: nsteps of both species in place in the real fields u, v.  Spectral scratch: A, B
+// (U, V), Lm and W (the reactions); real scratch: v, v2.
+struct GsCoef {
+  float dt, dt_du, dt_dv, F, k;
+};
+
+template <class L>
+void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* v,
+                      const AdjointBufs& b, float2* W, const GsCoef& co, int nsteps, int remap) {
+  float2 *U = b.A, *V = b.B, *RU = b.Lm, *RV = W;
+  for (int n = 0; n < nsteps; ++n) {
+    l.gs_react(GsReactArgs{u, v, b.v, b.v2, g.V, co.F, co.k});
+    const PassBatch rows{{u, v, b.v, b.v2}, {U, V, RU, RV}, 4};
+    l.row_batch(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, u, U, nullptr), rows);
+    const PassBatch all{{U, V, RU, RV}, {U, V, RU, RV}, 4};
+    l.col_batch(g.ny, g.bcy, COL_FWD, y_args(g, t, U, U, remap), all);
+    l.col_batch(g.nz, g.bcz, COL_FWD, z_args(g, t, U, U, nullptr, StepCoef{0, 0, 0}, remap), all);
+    GsUpdateArgs ua{};
+    ua.U = U;
+    ua.V = V;
+    ua.RU = RU;
+    ua.RV = RV;
+    ua.n = g.spec;
+    ua.ny = g.ny;
+    ua.pitch = g.pitch;
+    ua.ncols = g.ncols;
+    ua.bc = g.bc;
+    ua.k2x = t.k2_x;
+    ua.k2y = t.k2_y;
+    ua.k2z = t.k2_z;
+    ua.dt = co.dt;
+    ua.dt_du = co.dt_du;
+    ua.dt_dv = co.dt_dv;
+    l.gs_update(ua);
+    const PassBatch two{{U, V}, {U, V}, 2};
+    l.col_batch(g.nz, g.bcz, COL_INV, z_args(g, t, U, U, nullptr, StepCoef{0, 0, 0}, remap), two);
+    l.col_batch(g.ny, g.bcy, COL_INV, y_args(g, t, U, U, remap), two);
+    const PassBatch back{{U, V}, {u, v}, 2};
+    l.row_batch(g.row_len, g.bc, ROW_INV, x_args(g, t, U, nullptr, nullptr, u), back);
+  }
 }
 
 }  // namespace evx

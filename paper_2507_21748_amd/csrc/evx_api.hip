@@ -42,6 +42,7 @@ struct evx_plan {
   AdjointBufs aux{};      // diagnostics / adjoint scratch (inside the workspace)
   bool has_diag = false;
   bool has_adj = false;
+  bool has_gs = false;
   bool begun = false;     // S holds a state
   bool w_valid = false;   // W holds F_z^{-1} S
   int remap = 1;
@@ -65,6 +66,7 @@ size_t real_bytes(const Geom& g) { return align256(size_t(g.V) * sizeof(float));
 size_t ws_step(const Geom& g) { return state_bytes(g) + spec_bytes(g); }
 size_t ws_diag(const Geom& g) { return ws_step(g) + spec_bytes(g) + partial_bytes(); }
 size_t ws_adj(const Geom& g) { return ws_diag(g) + 2 * spec_bytes(g) + real_bytes(g); }
+size_t ws_gs(const Geom& g) { return ws_adj(g) + real_bytes(g); }
 
 evx_status check_plan(const evx_plan* p) {
   if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
@@ -269,10 +271,12 @@ evx_status evx_plan_destroy(evx_plan* p) {
 
 evx_status evx_plan_workspace_bytes(const evx_plan* p, int ops, size_t* bytes) {
   if (!p || !bytes) return fail(EVX_ERR_ARG, "NULL argument");
-  if (ops & ~(EVX_OP_STEP | EVX_OP_DIAG | EVX_OP_ADJOINT))
+  if (ops & ~(EVX_OP_STEP | EVX_OP_DIAG | EVX_OP_ADJOINT | EVX_OP_GRAY_SCOTT))
     return fail(EVX_ERR_ARG, "unknown workspace ops 0x%x", ops);
-  *bytes = (ops & EVX_OP_ADJOINT) ? ws_adj(p->g) : (ops & EVX_OP_DIAG) ? ws_diag(p->g)
-                                                                       : ws_step(p->g);
+  *bytes = (ops & EVX_OP_GRAY_SCOTT) ? ws_gs(p->g)
+           : (ops & EVX_OP_ADJOINT)  ? ws_adj(p->g)
+           : (ops & EVX_OP_DIAG)     ? ws_diag(p->g)
+                                     : ws_step(p->g);
   return EVX_OK;
 }
 
@@ -301,6 +305,8 @@ evx_status evx_plan_set_workspace(evx_plan* p, void* dev, size_t bytes) {
     p->aux.Lm = reinterpret_cast<float2*>(q + sb);
     p->aux.v = reinterpret_cast<float*>(q + 2 * sb);
   }
+  p->has_gs = bytes >= ws_gs(p->g);
+  if (p->has_gs) p->aux.v2 = reinterpret_cast<float*>(base + ws_adj(p->g));
   p->begun = false;
   p->w_valid = false;
   return EVX_OK;
@@ -408,6 +414,24 @@ evx_status evx_ch_adjoint_step(evx_plan* p, const float* c_n, float* lam,
   TimedLauncher l = launcher(p, s);
   sched_adjoint(l, p->g, p->t, c_n, lam, p->aux, co, dkappa, dM, p->remap);
   return finish(l, "adjoint step");
+}
+
+evx_status evx_gs_step(evx_plan* p, float* u, float* v, int nsteps, const evx_gs_params* q,
+                       void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!u || !v || !q) return fail(EVX_ERR_ARG, "NULL argument");
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  if (!(q->dt > 0) || !(q->Du >= 0) || !(q->Dv >= 0))
+    return fail(EVX_ERR_ARG, "params need dt > 0, Du >= 0, Dv >= 0");
+  if (!p->has_gs)
+    return fail(EVX_ERR_NOMEM, "workspace too small for Gray-Scott (EVX_OP_GRAY_SCOTT)");
+  const GsCoef co{float(q->dt), float(q->dt * q->Du), float(q->dt * q->Dv), float(q->F),
+                  float(q->k)};
+  TimedLauncher l = launcher(p, s);
+  sched_gray_scott(l, p->g, p->t, u, v, p->aux, p->W, co, nsteps, p->remap);
+  p->w_valid = false;  // W served as scratch
+  return finish(l, "gray-scott step");
 }
 
 evx_status evx_ch_diagnostics(evx_plan* p, const float* c, const evx_ch_params* q, double* out,

@@ -22,6 +22,24 @@ __global__ __launch_bounds__(AUX_THREADS) void combine_kernel(CombineArgs a) {
   combine_body(a, threadIdx.x, blockIdx.x, gridDim.x);
 }
 
+__global__ __launch_bounds__(AUX_THREADS) void gs_react_kernel(GsReactArgs a) {
+  gs_react_body(a, threadIdx.x, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(AUX_THREADS) void gs_update_kernel(GsUpdateArgs a) {
+  gs_update_body(a, threadIdx.x, blockIdx.x, gridDim.x);
+}
+
+hipError_t evx_launch_gs_react(const GsReactArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(gs_react_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t evx_launch_gs_update(const GsUpdateArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(gs_update_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t evx_launch_spec(const SpecArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(spec_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
   return hipGetLastError();

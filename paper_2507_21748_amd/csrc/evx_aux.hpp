@@ -179,6 +179,62 @@ EVX_DEV void final_body(const FinalArgs& a, int tid, double* red) {
   }
 }
 
+// Gray-Scott reaction terms in real space: ru = -u v^2 + F (1 - u), rv = u v^2 - (F + k) v.
+struct GsReactArgs {
+  const float* u;
+  const float* v;
+  float* ru;
+  float* rv;
+  long long n;
+  float F, k;
+};
+
+EVX_DEV void gs_react_body(const GsReactArgs& a, int tid, int bid, int nblk) {
+  const long long stride = (long long)nblk * AUX_THREADS;
+  for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
+    const float u = a.u[i], v = a.v[i];
+    const float uv2 = u * v * v;
+    a.ru[i] = -uv2 + a.F * (1.0f - u);
+    a.rv[i] = uv2 - (a.F + a.k) * v;
+  }
+}
+
+// Gray-Scott spectral update of both species (diffusion implicit, reaction explicit):
+// U <- (U + dt RU) / (1 + dt Du K2), V <- (V + dt RV) / (1 + dt Dv K2), in the layout of the
+// spectral buffers (periodic x: complex half-spectrum rows; cosine x: two real bins per float2).
+struct GsUpdateArgs {
+  float2* U;
+  float2* V;
+  const float2* RU;
+  const float2* RV;
+  long long n;
+  int ny, pitch, ncols, bc;
+  const float *k2x, *k2y, *k2z;
+  float dt, dt_du, dt_dv;
+};
+
+EVX_DEV void gs_update_body(const GsUpdateArgs& a, int tid, int bid, int nblk) {
+  const long long stride = (long long)nblk * AUX_THREADS;
+  for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
+    const long long r = i / a.pitch;
+    const int xc = int(i - r * a.pitch);
+    if (xc >= a.ncols) continue;  // row padding
+    const float kyz = a.k2y[int(r % a.ny)] + a.k2z[int(r / a.ny)];
+    float ka, kb;
+    if (a.bc == BC_PERIODIC) {
+      ka = kb = a.k2x[xc] + kyz;
+    } else {
+      ka = a.k2x[2 * xc] + kyz;
+      kb = a.k2x[2 * xc + 1] + kyz;
+    }
+    const float2 U = a.U[i], V = a.V[i], RU = a.RU[i], RV = a.RV[i];
+    a.U[i] = make_float2((U.x + a.dt * RU.x) / (1.0f + a.dt_du * ka),
+                         (U.y + a.dt * RU.y) / (1.0f + a.dt_du * kb));
+    a.V[i] = make_float2((V.x + a.dt * RV.x) / (1.0f + a.dt_dv * ka),
+                         (V.y + a.dt * RV.y) / (1.0f + a.dt_dv * kb));
+  }
+}
+
 // lam <- lam - f''(c) v  (f'' = 3c^2 - 1)
 struct CombineArgs {
   float* lam;

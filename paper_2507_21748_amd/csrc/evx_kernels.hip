@@ -73,7 +73,7 @@ static hipError_t col_go_batch(const ColArgs& a, const PassBatch& p, hipStream_t
   using C = ColCfg<N>;
   const long long nblk = (a.nseq + C::B - 1) / C::B;
   if (nblk <= 0) return hipSuccess;
-  if (p.n < 1 || p.n > 3) return hipErrorInvalidValue;
+  if (p.n < 1 || p.n > kMaxBatch) return hipErrorInvalidValue;
   const long long lane_bytes = col_lane_bytes<N>(a);
   if (nblk > 0x7fffffffLL || a.nseq > 0x7fffffffLL || lane_bytes >= (long long)kDeadLane)
     return hipErrorInvalidConfiguration;
@@ -89,7 +89,7 @@ static hipError_t row_go_batch(const RowArgs& a, const PassBatch& p, hipStream_t
   using C = RowCfg<NH, BC>;
   const long long nblk = (a.nrows + C::ROWS - 1) / C::ROWS;
   if (nblk <= 0) return hipSuccess;
-  if (p.n < 1 || p.n > 3) return hipErrorInvalidValue;
+  if (p.n < 1 || p.n > kMaxBatch) return hipErrorInvalidValue;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((row_kernel_batch<NH, BC, MODE>), dim3(unsigned(nblk), unsigned(p.n)),
                      dim3(C::THREADS), 0, s, a, p);

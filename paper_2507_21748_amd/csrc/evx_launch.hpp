@@ -22,6 +22,8 @@ hipError_t evx_launch_spec(const SpecArgs& a, hipStream_t s);
 hipError_t evx_launch_realsum(const RealSumArgs& a, hipStream_t s);
 hipError_t evx_launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t evx_launch_combine(const CombineArgs& a, hipStream_t s);
+hipError_t evx_launch_gs_react(const GsReactArgs& a, hipStream_t s);
+hipError_t evx_launch_gs_update(const GsUpdateArgs& a, hipStream_t s);
 
 // Records the first launch error; the schedule keeps enqueuing nothing after one.
 struct HipLauncher {
@@ -70,6 +72,12 @@ struct HipLauncher {
   }
   void combine(const CombineArgs& a) {
     if (err == hipSuccess && !bad_len) err = evx_launch_combine(a, stream);
+  }
+  void gs_react(const GsReactArgs& a) {
+    if (err == hipSuccess && !bad_len) err = evx_launch_gs_react(a, stream);
+  }
+  void gs_update(const GsUpdateArgs& a) {
+    if (err == hipSuccess && !bad_len) err = evx_launch_gs_update(a, stream);
   }
   void row(int n, int bc, int mode, const RowArgs& a) {
     if (err != hipSuccess || bad_len) return;

@@ -87,12 +87,13 @@ EVX_HD float dirichlet_sign(long long r, int i, int ny, int mask) {
   return (par & 1) ? -1.0f : 1.0f;
 }
 
-// One launch of the same transform pass over up to three independent (in, out) buffer pairs: the
-// grid's y index selects the pair (the small-grid adjoint runs its transforms this way, which
-// halves its launches).
+// One launch of the same transform pass over up to four independent (in, out) buffer pairs: the
+// grid's y index selects the pair (the small-grid adjoint and the two-species model run their
+// transforms this way, which halves their launches).
+constexpr int kMaxBatch = 4;
 struct PassBatch {
-  const void* in[3];
-  void* out[3];
+  const void* in[kMaxBatch];
+  void* out[kMaxBatch];
   int n;
 };
 EVX_HD void bind_batch(ColArgs& a, const PassBatch& b, int k) {

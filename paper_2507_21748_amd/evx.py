@@ -12,7 +12,7 @@ from dataclasses import dataclass
 import torch
 
 __all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME", "SEMI_IMPLICIT",
-           "ETD1", "CAHN_HILLIARD", "ALLEN_CAHN"]
+           "ETD1", "CAHN_HILLIARD", "ALLEN_CAHN", "GSParams", "OP_GRAY_SCOTT"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -20,7 +20,7 @@ _LIB = None
 BC = {"periodic": 0, "zero_flux": 1, "dirichlet": 2}
 SCHEME = {"spectral": 0, "stencil7": 1}
 
-OP_STEP, OP_DIAG, OP_ADJOINT = 1, 2, 4
+OP_STEP, OP_DIAG, OP_ADJOINT, OP_GRAY_SCOTT = 1, 2, 4, 8
 
 
 class EvxError(RuntimeError):
@@ -51,6 +51,24 @@ class CHParams:
         return _Params(self.dt, self.M, self.kappa, self.A, self.integrator, self.model)
 
 
+class _GSParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("Du", ctypes.c_double), ("Dv", ctypes.c_double),
+                ("F", ctypes.c_double), ("k", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class GSParams:
+    """Gray-Scott: du/dt = Du lap u - u v^2 + F (1 - u), dv/dt = Dv lap v + u v^2 - (F + k) v."""
+    dt: float = 1.0
+    Du: float = 0.2
+    Dv: float = 0.1
+    F: float = 0.04
+    k: float = 0.06
+
+    def c(self) -> _GSParams:
+        return _GSParams(self.dt, self.Du, self.Dv, self.F, self.k)
+
+
 def lib_path() -> str:
     return os.path.join(_PKG, "libevx.so")
 
@@ -68,6 +86,8 @@ _PROTOS = {
                        ctypes.POINTER(ctypes.c_size_t)],
     "evx_ch_begin": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_advance": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params), ctypes.c_void_p],
+    "evx_gs_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                    ctypes.POINTER(_GSParams), ctypes.c_void_p],
     "evx_ch_advance_record": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
                               ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_end": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -187,6 +207,16 @@ class Plan:
         p = params.c()
         _check(_LIB.evx_ch_advance(self._h, int(nsteps), ctypes.byref(p), _stream_handle(stream)),
                "evx_ch_advance")
+
+    def gs_step(self, u: torch.Tensor, v: torch.Tensor, nsteps: int, params: GSParams,
+                stream=None):
+        """Advance the Gray-Scott fields u, v (float32 device tensors of the grid) nsteps in place;
+        the plan needs ops including OP_GRAY_SCOTT."""
+        p = params.c()
+        _check(_LIB.evx_gs_step(self._h, _dev_ptr(u, numel=self.voxels),
+                                _dev_ptr(v, numel=self.voxels), int(nsteps), ctypes.byref(p),
+                                _stream_handle(stream)), "evx_gs_step")
+        return u, v
 
     def advance_record(self, nsteps: int, params: CHParams, traj: torch.Tensor, stream=None):
         """Advance nsteps, writing c^n at the start of each step to traj[n] (float32 device tensor

@@ -13,6 +13,7 @@
 //        evx_emu adj nx ny nz bc scheme dx dt M kappa A c.f32 lam.f32 out_lam.f32 out_grad.f64
 //   one adjoint step (lam <- dL/dc^n, out_grad = [dL/dkappa, dL/dM] of the step).
 //        evx_emu diag nx ny nz bc scheme dx kappa c.f32 out.f64   (mass, energy)
+//        evx_emu gs nx ny nz bc scheme dx dt Du Dv F k nsteps u v out_u out_v   (Gray-Scott)
 #include <barrier>
 #include <cstdio>
 #include <cstdlib>
@@ -151,6 +152,16 @@ struct EmuLauncher {
       combine_body(a, tid, bid, nb);
     });
   }
+  void gs_react(const GsReactArgs& a) {
+    run_grid(AUX_BLOCKS, AUX_THREADS, 1, [&](int tid, int bid, int nb, float2*) {
+      gs_react_body(a, tid, bid, nb);
+    });
+  }
+  void gs_update(const GsUpdateArgs& a) {
+    run_grid(AUX_BLOCKS, AUX_THREADS, 1, [&](int tid, int bid, int nb, float2*) {
+      gs_update_body(a, tid, bid, nb);
+    });
+  }
   void row(int n, int bc, int mode, const RowArgs& a) {
     switch (n) {
 #define EVX_CASE(N)                                   \
@@ -226,7 +237,38 @@ static int run_aux(int argc, char** argv) {
   return 0;
 }
 
+// evx_emu gs nx ny nz bc scheme dx dt Du Dv F k nsteps u.f32 v.f32 out_u.f32 out_v.f32
+static int run_gs(int argc, char** argv) {
+  if (argc != 18) return 2;
+  const int nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
+  const int bc = std::atoi(argv[5]), scheme = std::atoi(argv[6]);
+  const double dx = std::atof(argv[7]), dt = std::atof(argv[8]), Du = std::atof(argv[9]);
+  const double Dv = std::atof(argv[10]), F = std::atof(argv[11]), k = std::atof(argv[12]);
+  const int nsteps = std::atoi(argv[13]);
+  const Geom g = geom_of(nx, ny, nz, bc, scheme, dx);
+  const HostTables h = make_tables(g);
+  TablePtrs t{h.tw_x.data(), h.tw_y.data(), h.tw_z.data(), h.post_x.data(),
+              h.mk_y.empty() ? nullptr : h.mk_y.data(), h.mk_z.empty() ? nullptr : h.mk_z.data(),
+              h.k2_x.data(), h.k2_y.data(), h.k2_z.data()};
+  std::vector<float> u(g.V), v(g.V), ru(g.V), rv(g.V);
+  if (!read_f32(argv[14], u) || !read_f32(argv[15], v)) return 4;
+  std::vector<float2> A(g.spec), B(g.spec), Lm(g.spec), W(g.spec);
+  AdjointBufs b{};
+  b.A = A.data();
+  b.B = B.data();
+  b.Lm = Lm.data();
+  b.v = ru.data();
+  b.v2 = rv.data();
+  const GsCoef co{float(dt), float(dt * Du), float(dt * Dv), float(F), float(k)};
+  EmuLauncher l;
+  sched_gray_scott(l, g, t, u.data(), v.data(), b, W.data(), co, nsteps, 1);
+  if (!write_all(argv[16], u.data(), u.size()) || !write_all(argv[17], v.data(), v.size()))
+    return 5;
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc > 1 && std::strcmp(argv[1], "gs") == 0) return run_gs(argc, argv);
   if (argc > 1 && (std::strcmp(argv[1], "adj") == 0 || std::strcmp(argv[1], "diag") == 0))
     return run_aux(argc, argv);
   if (argc < 15 || argc > 17) {
