@@ -81,6 +81,8 @@ TRACE_COMMANDS = {
                     "-d {d}/kt -o kt -- python3 {root}/bench.py --extra-only surrogate512",
     "inverse128": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv "
                   "-d {d}/kt -o kt -- python3 {root}/bench.py --extra-only inverse128",
+    "varmob256": "timeout -k 10 300 rocprofv3 --kernel-trace --stats --output-format csv "
+                 "-d {d}/kt -o kt -- python3 {root}/bench.py --extra-only varmob256",
 }
 
 
@@ -304,6 +306,25 @@ def gray_scott_workload(evx, torch, n: int = 256, steps: int = 100):
             "finite": bool(torch.isfinite(u).all().item() and torch.isfinite(v).all().item())}
 
 
+def varmob_workload(evx, torch, n: int = 256, steps: int = 100):
+    """The variable-mobility Cahn-Hilliard step (M = D0 phi (1 - phi)) on a 256^3 periodic
+    spectral grid, phi a 0.5 +- 0.2 quench: ms per step (two stencil kernels, forward transform,
+    spectral multiply, inverse transform, add)."""
+    from paper_2507_21748_amd.inputs import quench_field
+    shape = (n, n, n)
+    plan = evx.Plan(shape, "periodic", "spectral", ops=evx.OP_STEP | evx.OP_VAR_MOBILITY)
+    phi = torch.from_numpy(quench_field(shape, 0.5, 0.2, seed=13)).cuda()
+    prm = evx.VMParams(dt=0.5, D0=1.0, gamma0=1.0, eps=2.0, M0=0.25)
+    plan.vm_step(phi, 5, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.vm_step(phi, steps, prm)
+    torch.cuda.synchronize()
+    secs = (time.perf_counter() - t0) / steps
+    return {"grid": [n, n, n], "ms_per_step": 1e3 * secs,
+            "finite": bool(torch.isfinite(phi).all().item())}
+
+
 def surrogate_workload(torch, w, reps: int = 5):
     """One coarse-stepper application (4 convolution layers, residual, mass projection) on the
     512^3 field: ms per application and the convolution flop rate (114,048 flop/voxel)."""
@@ -404,6 +425,9 @@ def main():
         print(json.dumps({"surrogate512_application":
                           surrogate_workload(torch, WORKLOADS["surrogate512"])}))
         return
+    if args.extra_only == "varmob256":
+        print(json.dumps({"varmob256": varmob_workload(evx, torch, steps=20)}))
+        return
     if args.extra_only == "inverse128":
         print(json.dumps({"inverse128_gradient":
                           adjoint_workload(evx, torch, WORKLOADS["inverse128"])}))
@@ -473,6 +497,7 @@ def main():
         extra["ch256_dirichlet"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
                                     "ms_per_step": r["ms_per_step"]}
         extra["gray_scott256"] = gray_scott_workload(evx, torch)
+        extra["varmob256"] = varmob_workload(evx, torch)
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
         extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
         line["extra"] = extra

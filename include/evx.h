@@ -19,8 +19,8 @@
  *
  * The same passes also run Dirichlet boundaries (DST-II) and per-axis boundary mixes (evx_bc,
  * evx_plan_create_axes), an exponential (ETD1) integrator and the Allen-Cahn model (the
- * integrator and model fields of evx_ch_params), and the Gray-Scott two-species model
- * (evx_gs_step).
+ * integrator and model fields of evx_ch_params), the Gray-Scott two-species model
+ * (evx_gs_step) and the paper's variable-mobility Cahn-Hilliard form (evx_vm_step).
  *
  * Conventions for every entry point:
  *   - Arrays are C order (nz, ny, nx), x fastest, FP32, in device memory of the device that was
@@ -100,7 +100,13 @@ typedef struct evx_ch_params {
 } evx_ch_params;
 
 /* Workspace users (bit mask for evx_plan_workspace_bytes). */
-enum { EVX_OP_STEP = 1, EVX_OP_DIAG = 2, EVX_OP_ADJOINT = 4, EVX_OP_GRAY_SCOTT = 8 };
+enum {
+  EVX_OP_STEP = 1,
+  EVX_OP_DIAG = 2,
+  EVX_OP_ADJOINT = 4,
+  EVX_OP_GRAY_SCOTT = 8,
+  EVX_OP_VAR_MOBILITY = 16
+};
 
 typedef struct evx_plan evx_plan;
 
@@ -127,7 +133,8 @@ evx_status evx_plan_destroy(evx_plan* plan);
  * whole column blocks of the z transform, i.e. about 8 bytes per voxel; EVX_OP_DIAG adds one
  * spectral buffer and 16 KB
  * of partial sums; EVX_OP_ADJOINT adds three spectral buffers, one real field and the partial
- * sums (about 24 bytes per voxel in total). */
+ * sums (about 24 bytes per voxel in total); EVX_OP_GRAY_SCOTT and EVX_OP_VAR_MOBILITY add one
+ * more real field to that (about 28 bytes per voxel). */
 evx_status evx_plan_workspace_bytes(const evx_plan* plan, int ops, size_t* bytes);
 
 /* Hand the plan a device buffer of at least evx_plan_workspace_bytes(plan, ops) bytes,
@@ -187,6 +194,9 @@ evx_status evx_ch_adjoint_step(evx_plan* plan, const float* c_n, float* lam,
  * out[1] = dx^3 [sum f(c) + (kappa/2) sum c (-L c)], L the plan's discrete Laplacian.
  * c: device, V floats (read).  out: two device doubles (written).  Only params->kappa is used.
  * Needs a workspace sized with EVX_OP_DIAG or EVX_OP_ADJOINT. */
+evx_status evx_ch_diagnostics(evx_plan* plan, const float* c, const evx_ch_params* params,
+                              double* out, void* hip_stream);
+
 /* Gray-Scott two-species model (the paper's reaction-diffusion example, appendix
  * "Reaction-diffusion systems"):
  *   du/dt = Du lap u - u v^2 + F (1 - u),   dv/dt = Dv lap v + u v^2 - (F + k) v,
@@ -207,8 +217,29 @@ typedef struct evx_gs_params {
 evx_status evx_gs_step(evx_plan* plan, float* u, float* v, int nsteps, const evx_gs_params* params,
                        void* hip_stream);
 
-evx_status evx_ch_diagnostics(evx_plan* plan, const float* c, const evx_ch_params* params,
-                              double* out, void* hip_stream);
+/* Variable-mobility Cahn-Hilliard (the paper's second-order phase transformation, appendix
+ * "Phase transformations of first and second order", eq. cahn-hilliard):
+ *   dphi/dt = div(M grad mu),  mu = gamma0 g(phi) - 2 gamma0 eps lap phi,
+ *   M = D0 phi (1 - phi),      g = (18 / eps) phi (1 - phi) (1 - 2 phi),
+ * stepped in the increment form of appendix "Semi-implicit timestepping":
+ *   phi' = phi + T^{-1}[ dt / (1 + 2 dt gamma0 eps M0 K2^2) T[ div(M grad mu) ] ],
+ * M0 the constant reference mobility of the implicit part.  The right-hand side is evaluated by
+ * finite differences in real space (7-point Laplacian; conservative face fluxes with the face
+ * mobility the mean of the two cells'); periodic axes wrap, zero-flux axes mirror the edge cell.
+ * K2 follows the plan's scheme.  phi: caller-owned real field (C order, V floats), advanced
+ * nsteps in place.  Dirichlet axes return EVX_ERR_UNSUPPORTED.  Needs a workspace sized for
+ * EVX_OP_VAR_MOBILITY (the Gray-Scott size; EVX_ERR_NOMEM otherwise); the stepper's own buffers
+ * are untouched.  Per step: two stencil kernels, the forward transform, one spectral multiply,
+ * the inverse transform and the add. */
+typedef struct evx_vm_params {
+  double dt;
+  double D0;
+  double gamma0;
+  double eps;
+  double M0;
+} evx_vm_params;
+evx_status evx_vm_step(evx_plan* plan, float* phi, int nsteps, const evx_vm_params* params,
+                       void* hip_stream);
 
 /* Distance of two fields on the plan's grid (used to judge surrogate predictions against the
  * solver): out[0] = sum (a - b)^2, out[1] = sum b^2, FP64, fixed-order reduction.  a, b: device,

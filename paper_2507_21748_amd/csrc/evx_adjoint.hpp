@@ -165,4 +165,40 @@ void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* 
   }
 }
 
+// Variable-mobility Cahn-Hilliard in the paper's increment form (appendix "Semi-implicit
+// timestepping"): phi <- phi + T^{-1}[dt / (1 + c4 K2^2) T[div(M grad mu)]], the right-hand side
+// from the two stencil passes.  Scratch: v (mu, then the increment), v2 (the right-hand side), A.
+struct VmCoef {
+  float dt, c4, c_g, c_lap, c_flux;
+};
+
+template <class L>
+void sched_varmob(L& l, const Geom& g, const TablePtrs& t, float* phi, const AdjointBufs& b,
+                  const VmCoef& co, int nsteps, int remap) {
+  const int per = (g.bc == BC_PERIODIC ? 1 : 0) | (g.bcy == BC_PERIODIC ? 2 : 0) |
+                  (g.bcz == BC_PERIODIC ? 4 : 0);
+  const VmStencilArgs mu{phi, nullptr, b.v, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
+  const VmStencilArgs rhs{phi, b.v, b.v2, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
+  VmUpdateArgs ua{};
+  ua.R = b.A;
+  ua.ny = g.ny;
+  ua.nz = g.nz;
+  ua.pitch = g.pitch;
+  ua.ncols = g.ncols;
+  ua.bc = g.bc;
+  ua.k2x = t.k2_x;
+  ua.k2y = t.k2_y;
+  ua.k2z = t.k2_z;
+  ua.dt = co.dt;
+  ua.c4 = co.c4;
+  for (int n = 0; n < nsteps; ++n) {
+    l.vm_mu(mu);
+    l.vm_rhs(rhs);
+    sched_forward(l, g, t, b.v2, b.A, false, remap);
+    l.vm_update(ua);
+    sched_inverse(l, g, t, b.A, b.v, remap);
+    l.vm_add(VmAddArgs{phi, b.v, g.V});
+  }
+}
+
 }  // namespace evx

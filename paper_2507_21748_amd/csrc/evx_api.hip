@@ -271,9 +271,10 @@ evx_status evx_plan_destroy(evx_plan* p) {
 
 evx_status evx_plan_workspace_bytes(const evx_plan* p, int ops, size_t* bytes) {
   if (!p || !bytes) return fail(EVX_ERR_ARG, "NULL argument");
-  if (ops & ~(EVX_OP_STEP | EVX_OP_DIAG | EVX_OP_ADJOINT | EVX_OP_GRAY_SCOTT))
+  if (ops & ~(EVX_OP_STEP | EVX_OP_DIAG | EVX_OP_ADJOINT | EVX_OP_GRAY_SCOTT |
+              EVX_OP_VAR_MOBILITY))
     return fail(EVX_ERR_ARG, "unknown workspace ops 0x%x", ops);
-  *bytes = (ops & EVX_OP_GRAY_SCOTT) ? ws_gs(p->g)
+  *bytes = (ops & (EVX_OP_GRAY_SCOTT | EVX_OP_VAR_MOBILITY)) ? ws_gs(p->g)
            : (ops & EVX_OP_ADJOINT)  ? ws_adj(p->g)
            : (ops & EVX_OP_DIAG)     ? ws_diag(p->g)
                                      : ws_step(p->g);
@@ -432,6 +433,27 @@ evx_status evx_gs_step(evx_plan* p, float* u, float* v, int nsteps, const evx_gs
   sched_gray_scott(l, p->g, p->t, u, v, p->aux, p->W, co, nsteps, p->remap);
   p->w_valid = false;  // W served as scratch
   return finish(l, "gray-scott step");
+}
+
+evx_status evx_vm_step(evx_plan* p, float* phi, int nsteps, const evx_vm_params* q, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!phi || !q) return fail(EVX_ERR_ARG, "NULL argument");
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  if (!(q->dt > 0) || !(q->D0 >= 0) || !(q->gamma0 >= 0) || !(q->eps > 0) || !(q->M0 >= 0))
+    return fail(EVX_ERR_ARG, "params need dt > 0, eps > 0 and D0, gamma0, M0 >= 0");
+  if (p->g.flip != 0)
+    return fail(EVX_ERR_UNSUPPORTED, "variable-mobility step: periodic or zero-flux axes only");
+  if (!p->has_gs)
+    return fail(EVX_ERR_NOMEM,
+                "workspace too small for the variable-mobility step (EVX_OP_VAR_MOBILITY)");
+  const double h2 = p->g.dx * p->g.dx;
+  const VmCoef co{float(q->dt), float(2.0 * q->dt * q->gamma0 * q->eps * q->M0),
+                  float(q->gamma0 * 18.0 / q->eps), float(2.0 * q->gamma0 * q->eps / h2),
+                  float(q->D0 / (2.0 * h2))};
+  TimedLauncher l = launcher(p, s);
+  sched_varmob(l, p->g, p->t, phi, p->aux, co, nsteps, p->remap);
+  return finish(l, "variable-mobility step");
 }
 
 evx_status evx_ch_diagnostics(evx_plan* p, const float* c, const evx_ch_params* q, double* out,

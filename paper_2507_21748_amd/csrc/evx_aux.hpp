@@ -235,6 +235,111 @@ EVX_DEV void gs_update_body(const GsUpdateArgs& a, int tid, int bid, int nblk) {
   }
 }
 
+// Variable-mobility Cahn-Hilliard (paper, appendix "Phase transformations of first and second
+// order", eq. cahn-hilliard, stepped as in "Semi-implicit timestepping"): the finite-difference
+// right-hand side div(M grad mu), mu = gamma0 g(phi) - 2 gamma0 eps lap phi, M = D0 phi (1 - phi),
+// g = (18 / eps) phi (1 - phi) (1 - 2 phi), in two real-space passes over the natural (z, y, x)
+// layout.  Periodic axes wrap; zero-flux axes mirror the edge cell into its ghost, so mu's ghost
+// equals the edge value and a boundary face carries no flux.
+struct VmStencilArgs {
+  const float* phi;
+  const float* mu;  // second pass only
+  float* out;       // mu (first pass) or div(M grad mu) (second pass)
+  int nx, ny, nz;
+  int per;          // periodic axes: bit 0 x, bit 1 y, bit 2 z
+  float c_g;        // gamma0 * 18 / eps
+  float c_lap;      // 2 gamma0 eps / dx^2
+  float c_flux;     // D0 / (2 dx^2): the face mobility is the mean of the two cells'
+};
+
+// Stencil blocks: 64 x 4 threads over (x, y) of one z plane; launch grid
+// (ceil(nx / 64), ceil(ny / 4), nz), one voxel per thread.
+constexpr int VM_BX = 64, VM_BY = 4;
+
+EVX_DEV int vm_wrap(int j, int n, bool per) {
+  if (per) return j < 0 ? j + n : (j >= n ? j - n : j);
+  return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+// Voxel i = (z ny + y) nx + x of thread tid in block (bx, by, bz) and its six neighbours;
+// false for threads past the grid's x or y extent.  Offsets are 32-bit: a grid holds at most
+// 1024^3 = 2^30 voxels.
+EVX_DEV bool vm_voxel(const VmStencilArgs& a, int tid, int bx, int by, int bz, int& i, int nb[6]) {
+  const int x = bx * VM_BX + tid % VM_BX, y = by * VM_BY + tid / VM_BX;
+  if (x >= a.nx || y >= a.ny) return false;
+  const int plane = a.nx * a.ny;
+  const int zo = bz * plane;
+  const int row = zo + y * a.nx;
+  const int xy = y * a.nx + x;
+  i = row + x;
+  nb[0] = row + vm_wrap(x + 1, a.nx, a.per & 1);
+  nb[1] = row + vm_wrap(x - 1, a.nx, a.per & 1);
+  nb[2] = zo + vm_wrap(y + 1, a.ny, a.per & 2) * a.nx + x;
+  nb[3] = zo + vm_wrap(y - 1, a.ny, a.per & 2) * a.nx + x;
+  nb[4] = vm_wrap(bz + 1, a.nz, a.per & 4) * plane + xy;
+  nb[5] = vm_wrap(bz - 1, a.nz, a.per & 4) * plane + xy;
+  return true;
+}
+
+EVX_DEV void vm_mu_body(const VmStencilArgs& a, int tid, int bx, int by, int bz) {
+  int i, nb[6];
+  if (!vm_voxel(a, tid, bx, by, bz, i, nb)) return;
+  const float p = a.phi[i];
+  float s = 0.0f;
+  for (int d = 0; d < 6; ++d) s += a.phi[nb[d]];
+  a.out[i] = a.c_g * p * (1.0f - p) * (1.0f - 2.0f * p) - a.c_lap * (s - 6.0f * p);
+}
+
+EVX_DEV void vm_rhs_body(const VmStencilArgs& a, int tid, int bx, int by, int bz) {
+  int i, nb[6];
+  if (!vm_voxel(a, tid, bx, by, bz, i, nb)) return;
+  const float p = a.phi[i], m = p * (1.0f - p), u = a.mu[i];
+  float acc = 0.0f;
+  for (int d = 0; d < 6; ++d) {
+    const float q = a.phi[nb[d]];
+    acc += (m + q * (1.0f - q)) * (a.mu[nb[d]] - u);
+  }
+  a.out[i] = a.c_flux * acc;
+}
+
+// Spectral multiplier of the increment form, in place: R <- dt R / (1 + c4 K2^2) with
+// c4 = 2 dt gamma0 eps M0 (the implicit part is the constant-mobility fourth-order term).
+struct VmUpdateArgs {
+  float2* R;
+  int ny, nz, pitch, ncols, bc;
+  const float *k2x, *k2y, *k2z;
+  float dt, c4;
+};
+
+// Launch grid (ceil(ncols / AUX_THREADS), ny, nz): one spectral value (float2) per thread.
+EVX_DEV void vm_update_body(const VmUpdateArgs& a, int tid, int bx, int y, int z) {
+  const int xc = bx * AUX_THREADS + tid;
+  if (xc >= a.ncols) return;
+  const long long i = ((long long)z * a.ny + y) * a.pitch + xc;
+  const float kyz = a.k2y[y] + a.k2z[z];
+  float ka, kb;
+  if (a.bc == BC_PERIODIC) {
+    ka = kb = a.k2x[xc] + kyz;
+  } else {
+    ka = a.k2x[2 * xc] + kyz;
+    kb = a.k2x[2 * xc + 1] + kyz;
+  }
+  const float2 R = a.R[i];
+  a.R[i] = make_float2(a.dt * R.x / (1.0f + a.c4 * ka * ka), a.dt * R.y / (1.0f + a.c4 * kb * kb));
+}
+
+// phi <- phi + d (the increment of the step).
+struct VmAddArgs {
+  float* phi;
+  const float* d;
+  long long n;
+};
+
+EVX_DEV void vm_add_body(const VmAddArgs& a, int tid, int bid, int nblk) {
+  const long long stride = (long long)nblk * AUX_THREADS;
+  for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) a.phi[i] += a.d[i];
+}
+
 // lam <- lam - f''(c) v  (f'' = 3c^2 - 1)
 struct CombineArgs {
   float* lam;

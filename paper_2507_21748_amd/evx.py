@@ -12,7 +12,8 @@ from dataclasses import dataclass
 import torch
 
 __all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME", "SEMI_IMPLICIT",
-           "ETD1", "CAHN_HILLIARD", "ALLEN_CAHN", "GSParams", "OP_GRAY_SCOTT"]
+           "ETD1", "CAHN_HILLIARD", "ALLEN_CAHN", "GSParams", "OP_GRAY_SCOTT",
+           "VMParams", "OP_VAR_MOBILITY"]
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -20,7 +21,7 @@ _LIB = None
 BC = {"periodic": 0, "zero_flux": 1, "dirichlet": 2}
 SCHEME = {"spectral": 0, "stencil7": 1}
 
-OP_STEP, OP_DIAG, OP_ADJOINT, OP_GRAY_SCOTT = 1, 2, 4, 8
+OP_STEP, OP_DIAG, OP_ADJOINT, OP_GRAY_SCOTT, OP_VAR_MOBILITY = 1, 2, 4, 8, 16
 
 
 class EvxError(RuntimeError):
@@ -69,6 +70,26 @@ class GSParams:
         return _GSParams(self.dt, self.Du, self.Dv, self.F, self.k)
 
 
+class _VMParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("D0", ctypes.c_double), ("gamma0", ctypes.c_double),
+                ("eps", ctypes.c_double), ("M0", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class VMParams:
+    """Variable-mobility Cahn-Hilliard: dphi/dt = div(M grad mu), M = D0 phi (1 - phi),
+    mu = gamma0 (18 / eps) phi (1 - phi) (1 - 2 phi) - 2 gamma0 eps lap phi; M0 is the constant
+    mobility of the implicit part."""
+    dt: float = 0.05
+    D0: float = 1.0
+    gamma0: float = 1.0
+    eps: float = 2.0
+    M0: float = 0.25
+
+    def c(self) -> _VMParams:
+        return _VMParams(self.dt, self.D0, self.gamma0, self.eps, self.M0)
+
+
 def lib_path() -> str:
     return os.path.join(_PKG, "libevx.so")
 
@@ -88,6 +109,8 @@ _PROTOS = {
     "evx_ch_advance": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params), ctypes.c_void_p],
     "evx_gs_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                     ctypes.POINTER(_GSParams), ctypes.c_void_p],
+    "evx_vm_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_VMParams),
+                    ctypes.c_void_p],
     "evx_ch_advance_record": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
                               ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_end": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -217,6 +240,14 @@ class Plan:
                                 _dev_ptr(v, numel=self.voxels), int(nsteps), ctypes.byref(p),
                                 _stream_handle(stream)), "evx_gs_step")
         return u, v
+
+    def vm_step(self, phi: torch.Tensor, nsteps: int, params: VMParams, stream=None):
+        """Advance the variable-mobility Cahn-Hilliard field phi (float32 device tensor of the
+        grid) nsteps in place; the plan needs ops including OP_VAR_MOBILITY."""
+        p = params.c()
+        _check(_LIB.evx_vm_step(self._h, _dev_ptr(phi, numel=self.voxels), int(nsteps),
+                                ctypes.byref(p), _stream_handle(stream)), "evx_vm_step")
+        return phi
 
     def advance_record(self, nsteps: int, params: CHParams, traj: torch.Tensor, stream=None):
         """Advance nsteps, writing c^n at the start of each step to traj[n] (float32 device tensor

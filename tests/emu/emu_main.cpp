@@ -162,6 +162,31 @@ struct EmuLauncher {
       gs_update_body(a, tid, bid, nb);
     });
   }
+  // The stencil and update kernels launch 3D grids (gx, gy, gz); block bid runs as
+  // (bid % gx, bid / gx % gy, bid / (gx gy)).
+  template <class Body>
+  static void grid3(int gx, int gy, int gz, int threads, Body body) {
+    run_grid(gx * gy * gz, threads, 1, [&](int tid, int bid, int, float2*) {
+      body(tid, bid % gx, bid / gx % gy, bid / (gx * gy));
+    });
+  }
+  void vm_mu(const VmStencilArgs& a) {
+    grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
+          [&](int tid, int bx, int by, int bz) { vm_mu_body(a, tid, bx, by, bz); });
+  }
+  void vm_rhs(const VmStencilArgs& a) {
+    grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
+          [&](int tid, int bx, int by, int bz) { vm_rhs_body(a, tid, bx, by, bz); });
+  }
+  void vm_update(const VmUpdateArgs& a) {
+    grid3((a.ncols + AUX_THREADS - 1) / AUX_THREADS, a.ny, a.nz, AUX_THREADS,
+          [&](int tid, int bx, int y, int z) { vm_update_body(a, tid, bx, y, z); });
+  }
+  void vm_add(const VmAddArgs& a) {
+    run_grid(AUX_BLOCKS, AUX_THREADS, 1, [&](int tid, int bid, int nb, float2*) {
+      vm_add_body(a, tid, bid, nb);
+    });
+  }
   void row(int n, int bc, int mode, const RowArgs& a) {
     switch (n) {
 #define EVX_CASE(N)                                   \
@@ -267,8 +292,38 @@ static int run_gs(int argc, char** argv) {
   return 0;
 }
 
+// evx_emu vm nx ny nz bc scheme dx dt D0 gamma0 eps M0 nsteps phi.f32 out.f32
+static int run_vm(int argc, char** argv) {
+  if (argc != 16) return 2;
+  const int nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
+  const int bc = std::atoi(argv[5]), scheme = std::atoi(argv[6]);
+  const double dx = std::atof(argv[7]), dt = std::atof(argv[8]), D0 = std::atof(argv[9]);
+  const double gamma0 = std::atof(argv[10]), eps = std::atof(argv[11]), M0 = std::atof(argv[12]);
+  const int nsteps = std::atoi(argv[13]);
+  const Geom g = geom_of(nx, ny, nz, bc, scheme, dx);
+  const HostTables h = make_tables(g);
+  TablePtrs t{h.tw_x.data(), h.tw_y.data(), h.tw_z.data(), h.post_x.data(),
+              h.mk_y.empty() ? nullptr : h.mk_y.data(), h.mk_z.empty() ? nullptr : h.mk_z.data(),
+              h.k2_x.data(), h.k2_y.data(), h.k2_z.data()};
+  std::vector<float> phi(g.V), v(g.V), v2(g.V);
+  if (!read_f32(argv[14], phi)) return 4;
+  std::vector<float2> A(g.spec);
+  AdjointBufs b{};
+  b.A = A.data();
+  b.v = v.data();
+  b.v2 = v2.data();
+  const double h2 = dx * dx;
+  const VmCoef co{float(dt), float(2.0 * dt * gamma0 * eps * M0), float(gamma0 * 18.0 / eps),
+                  float(2.0 * gamma0 * eps / h2), float(D0 / (2.0 * h2))};
+  EmuLauncher l;
+  sched_varmob(l, g, t, phi.data(), b, co, nsteps, 1);
+  if (!write_all(argv[15], phi.data(), phi.size())) return 5;
+  return 0;
+}
+
 int main(int argc, char** argv) {
   if (argc > 1 && std::strcmp(argv[1], "gs") == 0) return run_gs(argc, argv);
+  if (argc > 1 && std::strcmp(argv[1], "vm") == 0) return run_vm(argc, argv);
   if (argc > 1 && (std::strcmp(argv[1], "adj") == 0 || std::strcmp(argv[1], "diag") == 0))
     return run_aux(argc, argv);
   if (argc < 15 || argc > 17) {
