@@ -229,8 +229,9 @@ evx_status evx_gs_step(evx_plan* plan, float* u, float* v, int nsteps, const evx
  * K2 follows the plan's scheme.  phi: caller-owned real field (C order, V floats), advanced
  * nsteps in place.  Dirichlet axes return EVX_ERR_UNSUPPORTED.  Needs a workspace sized for
  * EVX_OP_VAR_MOBILITY (the Gray-Scott size; EVX_ERR_NOMEM otherwise); the stepper's own buffers
- * are untouched.  Per step: two stencil kernels, the forward transform, one spectral multiply,
- * the inverse transform and the add. */
+ * are untouched.  Per step: two stencil kernels, the forward x and y passes, one z pass holding
+ * the multiplier between its forward and inverse transforms, the inverse y and x passes, and the
+ * add. */
 typedef struct evx_vm_params {
   double dt;
   double D0;

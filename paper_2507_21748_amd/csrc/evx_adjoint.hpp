@@ -167,7 +167,8 @@ void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* 
 
 // Variable-mobility Cahn-Hilliard in the paper's increment form (appendix "Semi-implicit
 // timestepping"): phi <- phi + T^{-1}[dt / (1 + c4 K2^2) T[div(M grad mu)]], the right-hand side
-// from the two stencil passes.  Scratch: v (mu, then the increment), v2 (the right-hand side), A.
+// from the two stencil passes; the multiplier sits between the forward and inverse z transforms
+// of one column pass.  Scratch: v (mu, then the increment), v2 (the right-hand side), A.
 struct VmCoef {
   float dt, c4, c_g, c_lap, c_flux;
 };
@@ -179,24 +180,15 @@ void sched_varmob(L& l, const Geom& g, const TablePtrs& t, float* phi, const Adj
                   (g.bcz == BC_PERIODIC ? 4 : 0);
   const VmStencilArgs mu{phi, nullptr, b.v, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
   const VmStencilArgs rhs{phi, b.v, b.v2, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
-  VmUpdateArgs ua{};
-  ua.R = b.A;
-  ua.ny = g.ny;
-  ua.nz = g.nz;
-  ua.pitch = g.pitch;
-  ua.ncols = g.ncols;
-  ua.bc = g.bc;
-  ua.k2x = t.k2_x;
-  ua.k2y = t.k2_y;
-  ua.k2z = t.k2_z;
-  ua.dt = co.dt;
-  ua.c4 = co.c4;
+  const StepCoef zc{0.0f, co.c4, co.dt};  // the z pass reads dt from dt_m, c4 from dt_m_kappa
   for (int n = 0; n < nsteps; ++n) {
     l.vm_mu(mu);
     l.vm_rhs(rhs);
-    sched_forward(l, g, t, b.v2, b.A, false, remap);
-    l.vm_update(ua);
-    sched_inverse(l, g, t, b.A, b.v, remap);
+    l.row(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, b.v2, b.A, nullptr));
+    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, b.A, b.A, remap));
+    l.col(g.nz, g.bcz, COL_Z_VM, z_args(g, t, b.A, b.A, nullptr, zc, remap));
+    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, b.A, b.A, remap));
+    l.row(g.row_len, g.bc, ROW_INV, x_args(g, t, b.A, nullptr, nullptr, b.v));
     l.vm_add(VmAddArgs{phi, b.v, g.V});
   }
 }

@@ -302,32 +302,6 @@ EVX_DEV void vm_rhs_body(const VmStencilArgs& a, int tid, int bx, int by, int bz
   a.out[i] = a.c_flux * acc;
 }
 
-// Spectral multiplier of the increment form, in place: R <- dt R / (1 + c4 K2^2) with
-// c4 = 2 dt gamma0 eps M0 (the implicit part is the constant-mobility fourth-order term).
-struct VmUpdateArgs {
-  float2* R;
-  int ny, nz, pitch, ncols, bc;
-  const float *k2x, *k2y, *k2z;
-  float dt, c4;
-};
-
-// Launch grid (ceil(ncols / AUX_THREADS), ny, nz): one spectral value (float2) per thread.
-EVX_DEV void vm_update_body(const VmUpdateArgs& a, int tid, int bx, int y, int z) {
-  const int xc = bx * AUX_THREADS + tid;
-  if (xc >= a.ncols) return;
-  const long long i = ((long long)z * a.ny + y) * a.pitch + xc;
-  const float kyz = a.k2y[y] + a.k2z[z];
-  float ka, kb;
-  if (a.bc == BC_PERIODIC) {
-    ka = kb = a.k2x[xc] + kyz;
-  } else {
-    ka = a.k2x[2 * xc] + kyz;
-    kb = a.k2x[2 * xc + 1] + kyz;
-  }
-  const float2 R = a.R[i];
-  a.R[i] = make_float2(a.dt * R.x / (1.0f + a.c4 * ka * ka), a.dt * R.y / (1.0f + a.c4 * kb * kb));
-}
-
 // phi <- phi + d (the increment of the step).
 struct VmAddArgs {
   float* phi;

@@ -107,6 +107,7 @@ static hipError_t col_mode(int mode, const ColArgs& a, hipStream_t s) {
     case COL_Z_ETD: return col_go<N, BC, COL_Z_ETD>(a, s);
     case COL_Z_AC: return col_go<N, BC, COL_Z_AC>(a, s);
     case COL_Z_AC_ETD: return col_go<N, BC, COL_Z_AC_ETD>(a, s);
+    case COL_Z_VM: return col_go<N, BC, COL_Z_VM>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -32,7 +32,8 @@ enum : int {
   COL_Z_INV_STATE = 4, // state -> inverse -> out
   COL_Z_ETD = 5,       // as COL_Z_UPDATE with the exponential (ETD1) update
   COL_Z_AC = 6,        // as COL_Z_UPDATE for the Allen-Cahn model (semi-implicit)
-  COL_Z_AC_ETD = 7     // Allen-Cahn, exponential (ETD1) update
+  COL_Z_AC_ETD = 7,    // Allen-Cahn, exponential (ETD1) update
+  COL_Z_VM = 8         // in -> forward -> x dt / (1 + c4 K2^2) -> inverse -> out (no state)
 };
 
 // row (x) pass modes
@@ -293,7 +294,9 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   constexpr int E = C::E, TPS = C::TPS, B = C::B;
   constexpr bool upd =
       MODE == COL_Z_UPDATE || MODE == COL_Z_ETD || MODE == COL_Z_AC || MODE == COL_Z_AC_ETD;
-  constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || upd;
+  constexpr bool vm = MODE == COL_Z_VM;
+  constexpr bool kt = upd || vm;  // needs the K2 tables
+  constexpr bool has_fwd = MODE == COL_FWD || MODE == COL_Z_INIT || kt;
   constexpr bool has_inv = MODE != COL_FWD;
   constexpr bool zf = BC == BC_ZERO_FLUX;
   const int b = tid % B;
@@ -308,8 +311,8 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   TwStage<N, C::THREADS> tws;
   tws.load(a.tw, tid);
   float* const k2l = reinterpret_cast<float*>(lds + C::K2);
-  TableStage<(upd ? N : 0), C::THREADS, float> k2s;
-  if constexpr (upd) k2s.load(a.k2r, tid);
+  TableStage<(kt ? N : 0), C::THREADS, float> k2s;
+  if constexpr (kt) k2s.load(a.k2r, tid);
 
   float2 x[E];
   if constexpr (MODE == COL_Z_INV_STATE) {
@@ -324,7 +327,7 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
     static_for<E>([&](auto e) { x[e] = evx_buf_load2(ct.res(a.in, a.row_stride, e, nb), ct.lo); });
   }
   float kca = 0.f, kcb = 0.f;
-  if constexpr (upd) {
+  if constexpr (kt) {
     const int o = ct.live ? ct.outer : 0, cc = ct.live ? ct.col : 0;
     const float ko = a.k2o[o];
     if constexpr (zf) {
@@ -356,6 +359,19 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   if constexpr (MODE == COL_Z_INIT) {
     static_for<E>([&](auto e) {
       evx_buf_store2(ct.sres(a.state, e), ct.so, x[e]);
+    });
+  }
+
+  if constexpr (vm) {
+    // Increment multiplier of the variable-mobility step, x <- dt x / (1 + c4 K2^2): dt travels
+    // in dt_m and c4 = 2 dt gamma0 eps M0 in dt_m_kappa.  No state.
+    evx_sync();  // K2 table visible
+    static_for<E>([&](auto e) {
+      const int k = t + TPS * decltype(e)::value;
+      const float kr = k2l[k];
+      const float K2a = kca + kr, K2b = kcb + kr;
+      x[e] = make_float2(a.dt_m * x[e].x / (1.0f + a.dt_m_kappa * K2a * K2a),
+                         a.dt_m * x[e].y / (1.0f + a.dt_m_kappa * K2b * K2b));
     });
   }
 

@@ -92,6 +92,7 @@ struct EmuLauncher {
       case COL_Z_ETD: col_t<N, BC, COL_Z_ETD>(a); break;
       case COL_Z_AC: col_t<N, BC, COL_Z_AC>(a); break;
       case COL_Z_AC_ETD: col_t<N, BC, COL_Z_AC_ETD>(a); break;
+      case COL_Z_VM: col_t<N, BC, COL_Z_VM>(a); break;
       default: col_t<N, BC, COL_Z_INV_STATE>(a); break;
     }
   }
@@ -177,10 +178,6 @@ struct EmuLauncher {
   void vm_rhs(const VmStencilArgs& a) {
     grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
           [&](int tid, int bx, int by, int bz) { vm_rhs_body(a, tid, bx, by, bz); });
-  }
-  void vm_update(const VmUpdateArgs& a) {
-    grid3((a.ncols + AUX_THREADS - 1) / AUX_THREADS, a.ny, a.nz, AUX_THREADS,
-          [&](int tid, int bx, int y, int z) { vm_update_body(a, tid, bx, y, z); });
   }
   void vm_add(const VmAddArgs& a) {
     run_grid(AUX_BLOCKS, AUX_THREADS, 1, [&](int tid, int bid, int nb, float2*) {
