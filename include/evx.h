@@ -230,8 +230,8 @@ evx_status evx_gs_step(evx_plan* plan, float* u, float* v, int nsteps, const evx
  * nsteps in place.  Dirichlet axes return EVX_ERR_UNSUPPORTED.  Needs a workspace sized for
  * EVX_OP_VAR_MOBILITY (the Gray-Scott size; EVX_ERR_NOMEM otherwise); the stepper's own buffers
  * are untouched.  Per step: two stencil kernels, the forward x and y passes, one z pass holding
- * the multiplier between its forward and inverse transforms, the inverse y and x passes, and the
- * add. */
+ * the multiplier between its forward and inverse transforms, the inverse y pass and an inverse x
+ * pass that adds the increment to phi. */
 typedef struct evx_vm_params {
   double dt;
   double D0;

@@ -168,7 +168,8 @@ void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* 
 // Variable-mobility Cahn-Hilliard in the paper's increment form (appendix "Semi-implicit
 // timestepping"): phi <- phi + T^{-1}[dt / (1 + c4 K2^2) T[div(M grad mu)]], the right-hand side
 // from the two stencil passes; the multiplier sits between the forward and inverse z transforms
-// of one column pass.  Scratch: v (mu, then the increment), v2 (the right-hand side), A.
+// of one column pass, and the inverse x pass adds the increment to phi.  Scratch: v (mu), v2 (the
+// right-hand side), A.
 struct VmCoef {
   float dt, c4, c_g, c_lap, c_flux;
 };
@@ -188,8 +189,7 @@ void sched_varmob(L& l, const Geom& g, const TablePtrs& t, float* phi, const Adj
     l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, b.A, b.A, remap));
     l.col(g.nz, g.bcz, COL_Z_VM, z_args(g, t, b.A, b.A, nullptr, zc, remap));
     l.col(g.ny, g.bcy, COL_INV, y_args(g, t, b.A, b.A, remap));
-    l.row(g.row_len, g.bc, ROW_INV, x_args(g, t, b.A, nullptr, nullptr, b.v));
-    l.vm_add(VmAddArgs{phi, b.v, g.V});
+    l.row(g.row_len, g.bc, ROW_INV_ADD, x_args(g, t, b.A, nullptr, nullptr, phi));
   }
 }
 

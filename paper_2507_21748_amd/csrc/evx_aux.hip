@@ -38,10 +38,6 @@ __global__ __launch_bounds__(VM_BX * VM_BY) void vm_rhs_kernel(VmStencilArgs a) 
   vm_rhs_body(a, threadIdx.x, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-__global__ __launch_bounds__(AUX_THREADS) void vm_add_kernel(VmAddArgs a) {
-  vm_add_body(a, threadIdx.x, blockIdx.x, gridDim.x);
-}
-
 static dim3 vm_grid(const VmStencilArgs& a) {
   return dim3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz);
 }
@@ -53,11 +49,6 @@ hipError_t evx_launch_vm_mu(const VmStencilArgs& a, hipStream_t s) {
 
 hipError_t evx_launch_vm_rhs(const VmStencilArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(vm_rhs_kernel, vm_grid(a), dim3(VM_BX * VM_BY), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t evx_launch_vm_add(const VmAddArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(vm_add_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -302,18 +302,6 @@ EVX_DEV void vm_rhs_body(const VmStencilArgs& a, int tid, int bx, int by, int bz
   a.out[i] = a.c_flux * acc;
 }
 
-// phi <- phi + d (the increment of the step).
-struct VmAddArgs {
-  float* phi;
-  const float* d;
-  long long n;
-};
-
-EVX_DEV void vm_add_body(const VmAddArgs& a, int tid, int bid, int nblk) {
-  const long long stride = (long long)nblk * AUX_THREADS;
-  for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) a.phi[i] += a.d[i];
-}
-
 // lam <- lam - f''(c) v  (f'' = 3c^2 - 1)
 struct CombineArgs {
   float* lam;

@@ -118,6 +118,7 @@ static hipError_t row_mode(int mode, const RowArgs& a, hipStream_t s) {
     case ROW_FUSED: return row_go<NH, BC, ROW_FUSED>(a, s);
     case ROW_FWD: return row_go<NH, BC, ROW_FWD>(a, s);
     case ROW_INV: return row_go<NH, BC, ROW_INV>(a, s);
+    case ROW_INV_ADD: return row_go<NH, BC, ROW_INV_ADD>(a, s);
     case ROW_FWD_FP: return row_go<NH, BC, ROW_FWD_FP>(a, s);
     case ROW_FUSED_REC: return row_go<NH, BC, ROW_FUSED_REC>(a, s);
     default: return hipErrorInvalidValue;

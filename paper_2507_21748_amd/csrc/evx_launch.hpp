@@ -26,7 +26,6 @@ hipError_t evx_launch_gs_react(const GsReactArgs& a, hipStream_t s);
 hipError_t evx_launch_gs_update(const GsUpdateArgs& a, hipStream_t s);
 hipError_t evx_launch_vm_mu(const VmStencilArgs& a, hipStream_t s);
 hipError_t evx_launch_vm_rhs(const VmStencilArgs& a, hipStream_t s);
-hipError_t evx_launch_vm_add(const VmAddArgs& a, hipStream_t s);
 
 // Records the first launch error; the schedule keeps enqueuing nothing after one.
 struct HipLauncher {
@@ -87,9 +86,6 @@ struct HipLauncher {
   }
   void vm_rhs(const VmStencilArgs& a) {
     if (err == hipSuccess && !bad_len) err = evx_launch_vm_rhs(a, stream);
-  }
-  void vm_add(const VmAddArgs& a) {
-    if (err == hipSuccess && !bad_len) err = evx_launch_vm_add(a, stream);
   }
   void row(int n, int bc, int mode, const RowArgs& a) {
     if (err != hipSuccess || bad_len) return;

@@ -42,7 +42,8 @@ enum : int {
   ROW_FWD = 1,    // real row -> forward x -> complex row
   ROW_INV = 2,    // complex row -> inverse x -> real row
   ROW_FWD_FP = 3, // real row -> f'(c) -> forward x -> complex row (adjoint: T[f'(c)])
-  ROW_FUSED_REC = 4  // ROW_FUSED that also stores the real row it passes through (out_r)
+  ROW_FUSED_REC = 4, // ROW_FUSED that also stores the real row it passes through (out_r)
+  ROW_INV_ADD = 5    // ROW_INV that adds the real row to out_r instead of storing it
 };
 
 struct ColArgs {
@@ -460,12 +461,19 @@ EVX_DEV void copy_in(const float2* EVX_RESTRICT src, long long valid, float2* ld
   });
 }
 
-template <int COUNT, int T>
+template <int COUNT, int T, bool ADD = false>
 EVX_DEV void copy_out(float2* EVX_RESTRICT dst, long long valid, const float2* lds, int tid) {
   constexpr int IT = (COUNT + T - 1) / T;
   static_for<IT>([&](auto I) {
     const int i = tid + T * decltype(I)::value;
-    if (i < COUNT && i < valid) dst[i] = lds[i];
+    if (i < COUNT && i < valid) {
+      if constexpr (ADD) {
+        const float2 o = dst[i], v = lds[i];
+        dst[i] = make_float2(o.x + v.x, o.y + v.y);
+      } else {
+        dst[i] = lds[i];
+      }
+    }
   });
 }
 
@@ -489,7 +497,7 @@ EVX_DEV void rows_in(const float2* EVX_RESTRICT src, long long valid_rows, float
   });
 }
 
-template <int ROWS, int P, int S, int NLIVE, int T>
+template <int ROWS, int P, int S, int NLIVE, int T, bool ADD = false>
 EVX_DEV void rows_out(float2* EVX_RESTRICT dst, long long valid_rows, const float2* lds, int tid) {
   static_assert(T % ROWS == 0, "rows must split the block evenly");
   constexpr int TR = T / ROWS, IT = (P + TR - 1) / TR;
@@ -497,7 +505,15 @@ EVX_DEV void rows_out(float2* EVX_RESTRICT dst, long long valid_rows, const floa
   if (row >= valid_rows) return;
   static_for<IT>([&](auto I) {
     const int c = c0 + TR * decltype(I)::value;
-    if (c < P) dst[row * P + c] = (c < NLIVE) ? lds[row * S + c] : make_float2(0.f, 0.f);
+    if constexpr (ADD) {  // real rows only: NLIVE == P, no padding
+      static_assert(NLIVE == P, "adding rows have no padding");
+      if (c < P) {
+        const float2 o = dst[row * P + c], v = lds[row * S + c];
+        dst[row * P + c] = make_float2(o.x + v.x, o.y + v.y);
+      }
+    } else {
+      if (c < P) dst[row * P + c] = (c < NLIVE) ? lds[row * S + c] : make_float2(0.f, 0.f);
+    }
   });
 }
 
@@ -595,15 +611,15 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       evx_sync();
       fft_regs<NH, +1, B>(x, lds, b, t, twl);
       static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
-      if constexpr (MODE == ROW_INV || MODE == ROW_FUSED_REC) {
+      if constexpr (MODE == ROW_INV || MODE == ROW_INV_ADD || MODE == ROW_FUSED_REC) {
         const float sg = a.flip ? dirichlet_sign(r0 + b, 0, a.ny, a.flip) : 1.0f;
         static_for<E>([&](auto e) {
           lds[b * NH + t + TPS * decltype(e)::value] = a.flip ? cscale(x[e], sg) : x[e];
         });
         evx_sync();
-        copy_out<B * NH, T>(reinterpret_cast<float2*>(a.out_r) + r0 * NH, (a.nrows - r0) * NH,
-                            lds, tid);
-        if constexpr (MODE == ROW_INV) return;
+        copy_out<B * NH, T, MODE == ROW_INV_ADD>(reinterpret_cast<float2*>(a.out_r) + r0 * NH,
+                                                 (a.nrows - r0) * NH, lds, tid);
+        if constexpr (MODE == ROW_INV || MODE == ROW_INV_ADD) return;
         evx_sync();  // the forward transform reuses the staging area
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
@@ -675,7 +691,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
       evx_sync();
       fft_regs<NX, +1, B>(x, lds, b, t, twl);
       static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
-      if constexpr (MODE == ROW_INV || MODE == ROW_FUSED_REC) {
+      if constexpr (MODE == ROW_INV || MODE == ROW_INV_ADD || MODE == ROW_FUSED_REC) {
         static_for<E>([&](auto e) {
           const int n = t + TPS * decltype(e)::value;
           const int s = makhoul_src<NX>(n);
@@ -690,14 +706,16 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, float2* lds) {
         });
         evx_sync();
         if constexpr (C::ZPAD) {
-          rows_out<2 * B, NX / 2, ZS / 2, NX / 2, T>(reinterpret_cast<float2*>(a.out_r) +
+          rows_out<2 * B, NX / 2, ZS / 2, NX / 2, T, MODE == ROW_INV_ADD>(
+              reinterpret_cast<float2*>(a.out_r) +
                                                          r0 * (NX / 2),
                                                      a.nrows - r0, lds, tid);
         } else {
-          copy_out<B * NX, T>(reinterpret_cast<float2*>(a.out_r) + r0 * (NX / 2),
-                              (a.nrows - r0) * (NX / 2), lds, tid);
+          copy_out<B * NX, T, MODE == ROW_INV_ADD>(reinterpret_cast<float2*>(a.out_r) +
+                                                       r0 * (NX / 2),
+                                                   (a.nrows - r0) * (NX / 2), lds, tid);
         }
-        if constexpr (MODE == ROW_INV) return;
+        if constexpr (MODE == ROW_INV || MODE == ROW_INV_ADD) return;
         evx_sync();  // the forward transform reuses the staging area
       }
       static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });

@@ -102,6 +102,7 @@ struct EmuLauncher {
       case ROW_FUSED: row_t<NH, BC, ROW_FUSED>(a); break;
       case ROW_FWD: row_t<NH, BC, ROW_FWD>(a); break;
       case ROW_FWD_FP: row_t<NH, BC, ROW_FWD_FP>(a); break;
+      case ROW_INV_ADD: row_t<NH, BC, ROW_INV_ADD>(a); break;
       case ROW_FUSED_REC: row_t<NH, BC, ROW_FUSED_REC>(a); break;
       default: row_t<NH, BC, ROW_INV>(a); break;
     }
@@ -178,11 +179,6 @@ struct EmuLauncher {
   void vm_rhs(const VmStencilArgs& a) {
     grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
           [&](int tid, int bx, int by, int bz) { vm_rhs_body(a, tid, bx, by, bz); });
-  }
-  void vm_add(const VmAddArgs& a) {
-    run_grid(AUX_BLOCKS, AUX_THREADS, 1, [&](int tid, int bid, int nb, float2*) {
-      vm_add_body(a, tid, bid, nb);
-    });
   }
   void row(int n, int bc, int mode, const RowArgs& a) {
     switch (n) {
