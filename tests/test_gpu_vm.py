@@ -55,12 +55,13 @@ def test_one_and_twenty_steps(evx_gpu, shape, bc, scheme):
     assert abs(float(np.mean(twenty, dtype=np.float64)) - float(np.mean(phi0, dtype=np.float64))) < 1e-6
 
 
-def test_full_size_against_oracle(evx_gpu):
-    """128^3 periodic, two steps, every voxel against the oracle."""
+@pytest.mark.parametrize("bc,scheme", [("periodic", "spectral"), ("zero_flux", "stencil7")])
+def test_full_size_against_oracle(evx_gpu, bc, scheme):
+    """128^3, two steps, every voxel against the oracle."""
     shape = (128, 128, 128)
     phi0 = quench_field(shape, 0.5, 0.2, seed=82)
-    out = gpu_vm(evx_gpu, phi0, "periodic", "spectral", 2, P)
-    ref = vm.vm_run(phi0, 2, P, "periodic", "spectral")
+    out = gpu_vm(evx_gpu, phi0, bc, scheme, 2, P)
+    ref = vm.vm_run(phi0, 2, P, bc, scheme)
     assert rel_l2(out, ref) <= 1e-5
     assert np.max(np.abs(out - ref)) <= 1e-4
 
