@@ -198,8 +198,9 @@ evx_status evx_ch_diagnostics(evx_plan* plan, const float* c, const evx_ch_param
                               double* out, void* hip_stream);
 
 /* Gray-Scott two-species model (the paper's reaction-diffusion example, appendix
- * "Reaction-diffusion systems"):
- *   du/dt = Du lap u - u v^2 + F (1 - u),   dv/dt = Dv lap v + u v^2 - (F + k) v,
+ * "Reaction-diffusion systems", eq. gray-scott, u = c_A, v = c_B, feed rate F, kill rate k as
+ * printed there):
+ *   du/dt = Du lap u - u v^2 + F (1 - u),   dv/dt = Dv lap v + u v^2 - k v,
  * stepped with the same symbol rule: diffusion implicit, reaction explicit,
  *   U' = (U + dt T[R_u]) / (1 + dt Du K2),  V' = (V + dt T[R_v]) / (1 + dt Dv K2).
  * u, v: caller-owned real fields (C order, V floats each), advanced nsteps in place on the plan's

@@ -1,8 +1,11 @@
 """FP64 CPU oracle for the Gray-Scott two-species model on the same transforms.
 
 TEST INFRASTRUCTURE ONLY (see oracle/ch.py).  The paper's two-species reaction-diffusion example
-(appendix "Reaction-diffusion systems"):
-    du/dt = D_u lap u - u v^2 + F (1 - u),    dv/dt = D_v lap v + u v^2 - (F + k) v,
+(appendix "Reaction-diffusion systems", eq. gray-scott), with u = c_A, v = c_B, F the feed rate and
+k the kill rate exactly as printed there:
+    du/dt = D_u lap u - u v^2 + F (1 - u),    dv/dt = D_v lap v + u v^2 - k v.
+(The Pearson form often quoted elsewhere writes the kill term as -(F + k') v; it is the same model
+with k = F + k'.)
 stepped semi-implicitly with the symbol rule of the appendix: diffusion implicit (S = -D K2 per
 species), reaction explicit:
     U' = (U + dt T[R_u]) / (1 + dt D_u K2),   V' = (V + dt T[R_v]) / (1 + dt D_v K2),
@@ -27,13 +30,13 @@ class GSParams:
     Du: float = 0.2
     Dv: float = 0.1
     F: float = 0.04
-    k: float = 0.06
+    k: float = 0.10
 
 
 def reaction(u, v, p: GSParams):
-    """(R_u, R_v) = (-u v^2 + F (1 - u), u v^2 - (F + k) v)."""
+    """(R_u, R_v) = (-u v^2 + F (1 - u), u v^2 - k v)."""
     uv2 = u * v * v
-    return -uv2 + p.F * (1.0 - u), uv2 - (p.F + p.k) * v
+    return -uv2 + p.F * (1.0 - u), uv2 - p.k * v
 
 
 def gs_step(u, v, p: GSParams, bc, scheme: str):

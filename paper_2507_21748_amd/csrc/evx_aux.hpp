@@ -179,7 +179,8 @@ EVX_DEV void final_body(const FinalArgs& a, int tid, double* red) {
   }
 }
 
-// Gray-Scott reaction terms in real space: ru = -u v^2 + F (1 - u), rv = u v^2 - (F + k) v.
+// Gray-Scott reaction terms in real space (feed F, kill k): ru = -u v^2 + F (1 - u),
+// rv = u v^2 - k v.
 struct GsReactArgs {
   const float* u;
   const float* v;
@@ -195,7 +196,7 @@ EVX_DEV void gs_react_body(const GsReactArgs& a, int tid, int bid, int nblk) {
     const float u = a.u[i], v = a.v[i];
     const float uv2 = u * v * v;
     a.ru[i] = -uv2 + a.F * (1.0f - u);
-    a.rv[i] = uv2 - (a.F + a.k) * v;
+    a.rv[i] = uv2 - a.k * v;
   }
 }
 

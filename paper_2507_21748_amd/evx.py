@@ -59,12 +59,13 @@ class _GSParams(ctypes.Structure):
 
 @dataclass(frozen=True)
 class GSParams:
-    """Gray-Scott: du/dt = Du lap u - u v^2 + F (1 - u), dv/dt = Dv lap v + u v^2 - (F + k) v."""
+    """Gray-Scott (feed F, kill k): du/dt = Du lap u - u v^2 + F (1 - u),
+    dv/dt = Dv lap v + u v^2 - k v."""
     dt: float = 1.0
     Du: float = 0.2
     Dv: float = 0.1
     F: float = 0.04
-    k: float = 0.06
+    k: float = 0.10
 
     def c(self) -> _GSParams:
         return _GSParams(self.dt, self.Du, self.Dv, self.F, self.k)

@@ -166,6 +166,78 @@ def test_energy_monotone_decay(bc, scheme):
     assert np.max(np.abs(c)) < 1.29    # inside the range where the stability bound holds
 
 
+def _mean_f_cos(cbar, a, c2, c4):
+    """Grid mean of f(cbar + a q) for an oscillating factor q with mean 0, zero odd moments,
+    mean(q^2) = c2 and mean(q^4) = c4: f = (c^4 - 2 c^2 + 1) / 4 expanded in powers of a q."""
+    m2 = cbar ** 2 + a * a * c2
+    m4 = cbar ** 4 + 6.0 * cbar ** 2 * a * a * c2 + a ** 4 * c4
+    return 0.25 * (m4 - 2.0 * m2 + 1.0)
+
+
+def _cos_grid(shape, modes, bc):
+    """Product over axes of cos(theta_axis): periodic theta = 2 pi m j / n, zero flux
+    theta = pi m (j + 1/2) / n (m = 0 gives a constant factor 1)."""
+    q = np.ones(shape)
+    for ax, (n, m) in enumerate(zip(shape, modes)):
+        j = np.arange(n, dtype=np.float64)
+        th = 2.0 * np.pi * m * j / n if bc == "periodic" else np.pi * m * (j + 0.5) / n
+        sh = [1, 1, 1]
+        sh[ax] = n
+        q = q * np.cos(th).reshape(sh)
+    return q
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("modes", [(0, 0, 3), (2, 0, 1), (1, 3, 2)])
+def test_energy_of_cosine_mode_closed_form(bc, scheme, modes):
+    """A cosine mode c = cbar + a prod cos(theta) is an eigenvector of every discrete Laplacian
+    here (eigenvalue -K2, the sum of the per-axis values), so the gradient term of the free
+    energy is (kappa/2) K2 a^2 V mean(q^2) dx^3, and the grid moments of the cosine product are
+    those of the continuum (1/2, 3/8 per active axis) as long as 2m and 4m do not alias.  So
+    E = dx^3 V [mean f + (kappa/2) K2 a^2 mean(q^2)] in closed form.  A dropped or rescaled
+    kappa, a wrong f or a wrong K2 fails it."""
+    shape, dx, cbar, a = (12, 10, 16), 0.7, 0.3, 0.4
+    p = CHParams(dx=dx, kappa=1.7)
+    c = cbar + a * _cos_grid(shape, modes, bc)
+    act = sum(1 for m in modes if m)
+    c2, c4 = 0.5 ** act, 0.375 ** act
+    K2 = sum(ch.axis_k2(n, dx, bc, scheme)[m] for n, m in zip(shape, modes))
+    V = float(np.prod(shape))
+    ref = dx ** 3 * V * (_mean_f_cos(cbar, a, c2, c4) + 0.5 * p.kappa * K2 * a * a * c2)
+    got = ch.energy(c, p, bc, scheme)
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_stencil_energy_equals_face_loop(bc):
+    """7-point scheme: E = dx^3 [sum f(c) + (kappa/2) sum over faces ((c_b - c_a)/dx)^2] with
+    every face between two cells counted once; periodic axes wrap, zero-flux axes have no
+    boundary faces (mirror ghosts carry no difference).  Plain Python loops over cells and
+    faces."""
+    shape, dx = (3, 4, 5), 0.9
+    p = CHParams(dx=dx, kappa=1.3)
+    c = quench_field(shape, 0.1, 0.6, seed=31).astype(np.float64)
+    nz, ny, nx = shape
+    bulk = 0.0
+    grad = 0.0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                v = c[z, y, x]
+                bulk += 0.25 * (v * v - 1.0) ** 2
+                for (dz, dy, dxx) in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+                    z2, y2, x2 = z + dz, y + dy, x + dxx
+                    if bc == "periodic":
+                        z2, y2, x2 = z2 % nz, y2 % ny, x2 % nx
+                    elif z2 >= nz or y2 >= ny or x2 >= nx:
+                        continue
+                    grad += ((c[z2, y2, x2] - v) / dx) ** 2
+    ref = dx ** 3 * (bulk + 0.5 * p.kappa * grad)
+    got = ch.energy(c, p, bc, "stencil7")
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
 def test_energy_decay_fails_without_stabilisation():
     """Sanity of the energy pin: with A = 0 and a large step the explicit treatment of f' is
     unstable and the energy rises, so the monotone-decay test can fail."""
