@@ -50,7 +50,8 @@ typedef enum evx_status {
   EVX_ERR_UNSUPPORTED = 3, /* valid request this build does not implement */
   EVX_ERR_NOMEM = 4,       /* workspace missing or too small, or table allocation failed */
   EVX_ERR_HIP = 5,         /* a HIP runtime call or kernel launch failed */
-  EVX_ERR_STATE = 6        /* call out of order (e.g. advance before begin) */
+  EVX_ERR_STATE = 6,       /* call out of order (e.g. advance before begin) */
+  EVX_ERR_NONFINITE = 7    /* check_finite was set and the state holds a NaN or an Inf */
 } evx_status;
 
 /* Boundary conditions on the cell-centred grid.  EVX_BC_DIRICHLET: c (and its even derivatives)
@@ -89,7 +90,13 @@ typedef enum evx_model { EVX_MODEL_CAHN_HILLIARD = 0, EVX_MODEL_ALLEN_CAHN = 1 }
  * per call (not plan fields) so gradient loops over kappa and M never re-plan.  For Cahn-Hilliard
  * A multiplies dt K2 alone (not M): P = 1 + A dt K2.  integrator is an evx_integrator and model an
  * evx_model (both 0 -- semi-implicit Cahn-Hilliard -- when the struct is zero-initialised past
- * A); the adjoint supports that combination only (EVX_ERR_UNSUPPORTED otherwise). */
+ * A); the adjoint supports that combination only (EVX_ERR_UNSUPPORTED otherwise).
+ * check_finite != 0 asks evx_ch_advance / evx_ch_advance_record / evx_ch_step to check the new
+ * state for NaN and Inf once their nsteps have been enqueued (one extra read of the work buffer,
+ * which holds the state's values transformed along z, so a non-finite state value shows up there
+ * too): the call then synchronises the stream and returns EVX_ERR_NONFINITE if one is found (the
+ * state is left as computed; evx_ch_step skips its final inverse transform).  With 0 (the
+ * default) no call synchronises. */
 typedef struct evx_ch_params {
   double dt;
   double M;
@@ -97,6 +104,7 @@ typedef struct evx_ch_params {
   double A;
   int integrator;
   int model;
+  int check_finite;
 } evx_ch_params;
 
 /* Workspace users (bit mask for evx_plan_workspace_bytes). */

@@ -30,6 +30,7 @@ evx_status hip_fail(hipError_t e, const char* what) {
 
 }  // namespace
 
+
 struct evx_plan {
   Geom g;
   int device = 0;
@@ -40,6 +41,7 @@ struct evx_plan {
   float2* S = nullptr;
   float2* W = nullptr;
   AdjointBufs aux{};      // diagnostics / adjoint scratch (inside the workspace)
+  int* finite_flags = nullptr;  // AUX_BLOCKS slots of the non-finite check (in the table block)
   bool has_diag = false;
   bool has_adj = false;
   bool has_gs = false;
@@ -161,6 +163,23 @@ TimedLauncher launcher(evx_plan* p, void* s) {
 
 bool axis_ok(int n) { return fft_len_supported(n); }
 
+// The optional failure check after a batch of steps: scan the work buffer W (live columns) for
+// NaN / Inf, then synchronise and OR the per-block flags on the host.
+evx_status check_state_finite(evx_plan* p, const float2* W, void* s) {
+  hipStream_t st = static_cast<hipStream_t>(s);
+  const FiniteArgs a{W, p->g.spec, p->g.pitch, p->g.ncols, p->finite_flags};
+  hipError_t e = evx_launch_finite(a, st);
+  if (e != hipSuccess) return hip_fail(e, "non-finite check");
+  int host[AUX_BLOCKS];
+  e = hipMemcpyAsync(host, p->finite_flags, sizeof(host), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "non-finite flags copy");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "non-finite check sync");
+  for (int b = 0; b < AUX_BLOCKS; ++b)
+    if (host[b]) return fail(EVX_ERR_NONFINITE, "the state holds a NaN or an Inf");
+  return EVX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -174,6 +193,7 @@ const char* evx_status_string(evx_status s) {
     case EVX_ERR_NOMEM: return "workspace missing or too small / out of memory";
     case EVX_ERR_HIP: return "HIP runtime error";
     case EVX_ERR_STATE: return "call out of order";
+    case EVX_ERR_NONFINITE: return "non-finite value (NaN or Inf) in the state";
   }
   return "unknown status";
 }
@@ -227,7 +247,8 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
       {h.mk_z.data(), h.mk_z.size() * sizeof(float2), 0},
       {h.k2_x.data(), h.k2_x.size() * sizeof(float), 0},
       {h.k2_y.data(), h.k2_y.size() * sizeof(float), 0},
-      {h.k2_z.data(), h.k2_z.size() * sizeof(float), 0}};
+      {h.k2_z.data(), h.k2_z.size() * sizeof(float), 0},
+      {nullptr, AUX_BLOCKS * sizeof(int), 0}};  // non-finite flags (device-written)
   size_t total = 0;
   for (auto& q : parts) {
     q.off = total;
@@ -235,7 +256,7 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
   }
   std::vector<unsigned char> host(total, 0);
   for (auto& q : parts)
-    if (q.bytes) std::memcpy(host.data() + q.off, q.src, q.bytes);
+    if (q.bytes && q.src) std::memcpy(host.data() + q.off, q.src, q.bytes);
   e = hipMalloc(&p->tables, total);
   if (e != hipSuccess) {
     delete p;
@@ -257,6 +278,7 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
   p->t.k2_x = reinterpret_cast<const float*>(at(6));
   p->t.k2_y = reinterpret_cast<const float*>(at(7));
   p->t.k2_z = reinterpret_cast<const float*>(at(8));
+  p->finite_flags = reinterpret_cast<int*>(at(9));
   *out = p;
   return EVX_OK;
 }
@@ -357,7 +379,9 @@ evx_status evx_ch_advance(evx_plan* p, int nsteps, const evx_ch_params* q, void*
   }
   TimedLauncher l = launcher(p, s);
   sched_advance(l, p->g, p->t, p->S, p->W, coef_of(q), nsteps, p->remap, zmode_of(q));
-  return finish(l, "advance");
+  st = finish(l, "advance");
+  if (st == EVX_OK && q->check_finite) st = check_state_finite(p, p->W, s);
+  return st;
 }
 
 evx_status evx_ch_advance_record(evx_plan* p, int nsteps, const evx_ch_params* q, float* traj,
@@ -374,7 +398,9 @@ evx_status evx_ch_advance_record(evx_plan* p, int nsteps, const evx_ch_params* q
   TimedLauncher l = launcher(p, s);
   sched_advance_record(l, p->g, p->t, p->S, p->W, coef_of(q), nsteps, p->remap, zmode_of(q),
                        traj);
-  return finish(l, "advance_record");
+  st = finish(l, "advance_record");
+  if (st == EVX_OK && q->check_finite) st = check_state_finite(p, p->W, s);
+  return st;
 }
 
 evx_status evx_ch_end(evx_plan* p, float* c, void* s) {

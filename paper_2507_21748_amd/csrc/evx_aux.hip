@@ -22,6 +22,16 @@ __global__ __launch_bounds__(AUX_THREADS) void combine_kernel(CombineArgs a) {
   combine_body(a, threadIdx.x, blockIdx.x, gridDim.x);
 }
 
+__global__ __launch_bounds__(AUX_THREADS) void finite_kernel(FiniteArgs a) {
+  __shared__ int red[AUX_THREADS];
+  finite_body<AUX_THREADS>(a, threadIdx.x, blockIdx.x, gridDim.x, red);
+}
+
+hipError_t evx_launch_finite(const FiniteArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(finite_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(AUX_THREADS) void gs_react_kernel(GsReactArgs a) {
   gs_react_body(a, threadIdx.x, blockIdx.x, gridDim.x);
 }

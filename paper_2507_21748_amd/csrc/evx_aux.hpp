@@ -179,6 +179,43 @@ EVX_DEV void final_body(const FinalArgs& a, int tid, double* red) {
   }
 }
 
+// Non-finite check of a spectral buffer (the stepper's optional failure check): block b writes
+// flag[b] = 1 if one of its grid-stride elements (live columns only: row padding is skipped) has
+// an all-ones exponent (Inf or NaN), else 0.  Every block writes its own slot, so no clearing and
+// no atomics are needed, and the host ORs the AUX_BLOCKS slots.
+struct FiniteArgs {
+  const float2* w;
+  long long n;     // float2 elements
+  int pitch;       // float2 per row
+  int ncols;       // of them holding data
+  int* flag;       // AUX_BLOCKS slots
+};
+
+EVX_DEV bool evx_nonfinite(float v) {
+  unsigned u;
+  __builtin_memcpy(&u, &v, 4);
+  return (u & 0x7f800000u) == 0x7f800000u;
+}
+
+template <int T>
+EVX_DEV void finite_body(const FiniteArgs& a, int tid, int bid, int nblk, int* red) {
+  int bad = 0;
+  const long long stride = (long long)nblk * T;
+  for (long long i = (long long)bid * T + tid; i < a.n; i += stride) {
+    const int xc = int(i % a.pitch);
+    if (xc >= a.ncols) continue;
+    const float2 v = a.w[i];
+    bad |= int(evx_nonfinite(v.x) || evx_nonfinite(v.y));
+  }
+  red[tid] = bad;
+  evx_sync();
+  for (int h = T / 2; h > 0; h >>= 1) {
+    if (tid < h) red[tid] |= red[tid + h];
+    evx_sync();
+  }
+  if (tid == 0) a.flag[bid] = red[0];
+}
+
 // Gray-Scott reaction terms in real space (feed F, kill k): ru = -u v^2 + F (1 - u),
 // rv = u v^2 - k v.
 struct GsReactArgs {

@@ -23,6 +23,7 @@ hipError_t evx_launch_realsum(const RealSumArgs& a, hipStream_t s);
 hipError_t evx_launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t evx_launch_combine(const CombineArgs& a, hipStream_t s);
 hipError_t evx_launch_gs_react(const GsReactArgs& a, hipStream_t s);
+hipError_t evx_launch_finite(const FiniteArgs& a, hipStream_t s);
 hipError_t evx_launch_gs_update(const GsUpdateArgs& a, hipStream_t s);
 hipError_t evx_launch_vm_mu(const VmStencilArgs& a, hipStream_t s);
 hipError_t evx_launch_vm_rhs(const VmStencilArgs& a, hipStream_t s);

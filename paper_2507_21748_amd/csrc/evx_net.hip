@@ -960,13 +960,16 @@ __global__ __launch_bounds__(LOSS_BLOCKS) void loss_final(const double* partial,
   if (threadIdx.x == 0) *loss = (add ? *loss : 0.0) + scale * red[0];
 }
 
+// Adam (Kingma & Ba).  omb1 = 1 - b1 and omb2 = 1 - b2 come from the host in FP64 and are rounded
+// once: 1 - 0.999f in FP32 would be 1.3e-5 off 0.001 (0.999 is not representable).
 __global__ void adam_kernel(float* p, float* m, float* v, const float* g, long long n, float lr,
-                            float b1, float b2, float eps, float c1, float c2) {
+                            float b1, float b2, float omb1, float omb2, float eps, float c1,
+                            float c2) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -1356,8 +1359,8 @@ evx_status evx_surrogate_train_step(evx_net* n, const float* x, const float* y, 
   }
   const double c1 = 1.0 - std::pow(0.9, double(step)), c2 = 1.0 - std::pow(0.999, double(step));
   hipLaunchKernelGGL(adam_kernel, dim3(unsigned((NPARAM + 255) / 256)), dim3(256), 0, s, params,
-                     adam_m, adam_v, b.grads, NPARAM, lr, 0.9f, 0.999f, 1e-8f, float(c1),
-                     float(c2));
+                     adam_m, adam_v, b.grads, NPARAM, lr, 0.9f, 0.999f, float(1.0 - 0.9),
+                     float(1.0 - 0.999), 1e-8f, float(c1), float(c2));
   NET_TRY(hipGetLastError());
   return evx_surrogate_set_params(n, params, stream);
 }

@@ -32,7 +32,8 @@ class EvxError(RuntimeError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("M", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("A", ctypes.c_double), ("integrator", ctypes.c_int), ("model", ctypes.c_int)]
+                ("A", ctypes.c_double), ("integrator", ctypes.c_int), ("model", ctypes.c_int),
+                ("check_finite", ctypes.c_int)]
 
 
 SEMI_IMPLICIT, ETD1 = 0, 1  # evx_integrator
@@ -47,9 +48,11 @@ class CHParams:
     A: float = 2.0
     integrator: int = SEMI_IMPLICIT
     model: int = CAHN_HILLIARD
+    check_finite: bool = False  # advance synchronises and raises on a NaN / Inf state
 
     def c(self) -> _Params:
-        return _Params(self.dt, self.M, self.kappa, self.A, self.integrator, self.model)
+        return _Params(self.dt, self.M, self.kappa, self.A, self.integrator, self.model,
+                       int(bool(self.check_finite)))
 
 
 class _GSParams(ctypes.Structure):

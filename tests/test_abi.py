@@ -35,9 +35,23 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_status_strings(lib):
-    for s in range(7):
+    for s in range(8):
         assert lib.evx_status_string(s)
     assert lib.evx_status_string(99) == b"unknown status"
+
+
+def test_nonfinite_status_and_params_layout(lib):
+    """The failure check's status code and the params struct (check_finite after model) agree
+    between the header, the library and the binding."""
+    import re
+    from paper_2507_21748_amd import evx
+    text = open(HEADER).read()
+    assert re.search(r"EVX_ERR_NONFINITE\s*=\s*7", text)
+    assert b"non-finite" in lib.evx_status_string(7)
+    body = re.search(r"typedef struct evx_ch_params \{(.*?)\} evx_ch_params;", text, re.S).group(1)
+    fields = re.findall(r"(double|int)\s+(\w+);", body)
+    assert [n for _, n in fields] == [n for n, _ in evx._Params._fields_]
+    assert ctypes.sizeof(evx._Params) == 48
 
 
 @pytest.mark.parametrize("nx,ny,nz,bc", [

@@ -300,3 +300,36 @@ def test_400_zero_flux_random_one_step(evx_gpu):
     got = gpu_run(evx_gpu, c0, "zero_flux", "stencil7", 1, p)
     ref = ch.ch_step(c0.astype(np.float64), p, "zero_flux", "stencil7")
     assert rel_l2(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("bc", ["periodic", "zero_flux"])
+def test_nonfinite_state_is_reported(evx_gpu, bc):
+    """check_finite: a NaN or an Inf in the field makes the step return EVX_ERR_NONFINITE (7);
+    a finite field passes the check with results bitwise equal to an unchecked run."""
+    shape = (16, 24, 32)
+    c0 = quench_field(shape, 0.0, 0.05, seed=7)
+    checked = evx_gpu.CHParams(dt=0.5, check_finite=True)
+    plain = evx_gpu.CHParams(dt=0.5)
+    plan = evx_gpu.Plan(shape, bc, "spectral")
+    a = torch.from_numpy(c0).cuda()
+    b = torch.from_numpy(c0).cuda()
+    plan.step(a, 3, checked)
+    plan.step(b, 3, plain)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        c = torch.from_numpy(c0).cuda()
+        c[5, 7, 11] = bad
+        with pytest.raises(evx_gpu.EvxError) as ei:
+            plan.step(c, 2, checked)
+        assert ei.value.status == 7
+        c = torch.from_numpy(c0).cuda()
+        c[5, 7, 11] = bad
+        plan.step(c, 2, plain)  # unchecked: no status, the field is simply non-finite
+        torch.cuda.synchronize()
+        assert not bool(torch.isfinite(c).all())
+    # a step that makes a finite state overflow is caught at the end of the batch
+    big = torch.from_numpy(c0 * 1e13).cuda()
+    with pytest.raises(evx_gpu.EvxError) as ei:
+        plan.step(big, 4, evx_gpu.CHParams(dt=0.5, A=0.0, check_finite=True))
+    assert ei.value.status == 7

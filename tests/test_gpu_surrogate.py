@@ -106,6 +106,42 @@ def test_train_step_layers_match_oracle(evx_gpu, n):
         assert np.linalg.norm(got_b - gb) <= 1e-4 * np.linalg.norm(gb) + 1e-12, li
 
 
+def test_adam_update_matches_oracle(evx_gpu):
+    """Three training steps at a real learning rate: each step's parameters and Adam moments on
+    the GPU equal the oracle's Adam update (Kingma & Ba, with bias correction) applied in FP64 to
+    the GPU's own parameters, moments and summed gradient before that step, to FP32 rounding."""
+    from paper_2507_21748_amd.surrogate import Net
+    n, halo, lr = 20, 4, 3e-3
+    net = Net(_params(5))
+    x = torch.from_numpy(quench_field((n, n, n), 0.0, 0.6, seed=51)).cuda()[None].contiguous()
+    y = torch.from_numpy(quench_field((n, n, n), 0.0, 0.6, seed=52)).cuda()[None].contiguous()
+
+    def close(got, ref, scale):
+        """FP32 evaluation of a few terms whose magnitudes sum to `scale`: within 1e-6 of it
+        (a handful of FP32 roundings, 6e-8 each), so a cancelling sum is not held to a
+        relative bound on its small result."""
+        got = got.cpu().numpy().astype(np.float64)
+        tol = 1e-6 * scale + 1e-30
+        assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+    for step in range(1, 4):
+        th0 = net.params.cpu().numpy().astype(np.float64)
+        m0 = net.m.cpu().numpy().astype(np.float64)
+        v0 = net.v.cpu().numpy().astype(np.float64)
+        net.train_step(x, y, halo, lr=lr)
+        torch.cuda.synchronize()
+        assert net.step == step
+        g = net.train_buffers(n)["grads"].cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(g) > 0
+        th_ref, m_ref, v_ref = S.adam_update(th0, m0, v0, g, step, lr)
+        close(net.m, m_ref, 0.9 * np.abs(m0) + 0.1 * np.abs(g))
+        close(net.v, v_ref, 0.999 * v0 + 0.001 * g * g)
+        close(net.params, th_ref, np.abs(th0) + np.abs(th_ref - th0))
+        # the update moved the parameters by about lr per element (Adam's normalised step)
+        moved = np.abs(th_ref - th0)
+        assert np.median(moved) > 0.1 * lr
+
+
 def test_gelu_over_wide_preactivations(evx_gpu):
     """First-layer weights scaled up so that its BF16 pre-activations reach past +-8 and down to
     below 2^-8 in magnitude: the stored activations equal bf16(GELU(z)) of the FP64 oracle on every
