@@ -184,6 +184,20 @@ evx_status evx_ch_restore(evx_plan* plan, void* hip_stream);
 evx_status evx_ch_step(evx_plan* plan, float* c, int nsteps, const evx_ch_params* params,
                        void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): evx_ch_step without a caller workspace.  The state and
+ * work buffers live in a static device array of 64 MiB held by every device the library runs on
+ * until the process ends, so grids whose two spectral buffers (evx_plan_workspace_bytes with
+ * EVX_OP_STEP: about 8 bytes per voxel) exceed 64 MiB -- about 8 M voxels, e.g. 192^3 zero flux
+ * or 128 x 256 x 256 periodic -- return EVX_ERR_NOMEM.  The call allocates nothing: it enqueues the
+ * same kernels as evx_ch_step (results are bitwise equal) on the given stream.  The plan's own
+ * workspace, state and begin/advance/end state are neither needed nor touched.  Every call on a
+ * device shares that device's array and overwrites it, so calls that overlap on one device (two
+ * streams, two threads) race; serialise them.  check_finite synchronises as in evx_ch_step.
+ * Errors as evx_ch_step. */
+evx_status evx_ch_step_noalloc(evx_plan* plan, float* c, int nsteps, const evx_ch_params* params,
+                               void* hip_stream);
+
 /* Adjoint of one step (gradients for inverse problems; the paper's Statement of Need names
  * backpropagation through the solver for parameter estimation).  With
  * c^{n+1} = A c^n - B f'(c^n), A = T^{-1} diag(G P) T, B = T^{-1} diag(dt M K2 G) T:

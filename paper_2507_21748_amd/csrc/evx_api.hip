@@ -2,6 +2,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,39 @@ evx_status hip_fail(hipError_t e, const char* what) {
 
 }  // namespace
 
+// Device scratch of the allocation-free step (evx_ch_step_noalloc): the state and work buffers of
+// one grid.  Each device holds its own copy for the life of the process.  Host code never uses
+// this name as an address: the per-device address comes from hipGetSymbolAddress at plan
+// creation (resolve_scratch) and only that pointer reaches kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};  // per device: its copy of `scratch`
+
+// Once per device, with that device current: look up its copy of the scratch array.
+evx_status resolve_scratch(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(EVX_ERR_UNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                kMaxDevices);
+  if (g_scratch_dev[dev]) return EVX_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  g_scratch_dev[dev] = static_cast<unsigned char*>(ptr);
+  return EVX_OK;
+}
+
+unsigned char* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (dev >= 0 && dev < kMaxDevices) ? g_scratch_dev[dev] : nullptr;
+}
+
+}  // namespace
 
 struct evx_plan {
   Geom g;
@@ -235,6 +269,13 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
+  {
+    const evx_status se = resolve_scratch(p->device);
+    if (se != EVX_OK) {
+      delete p;
+      return se;
+    }
+  }
   const HostTables h = make_tables(p->g);
   // one allocation: every table at a 256-byte aligned offset
   struct Part { const void* src; size_t bytes; size_t off; };
@@ -425,6 +466,35 @@ evx_status evx_ch_step(evx_plan* p, float* c, int nsteps, const evx_ch_params* q
   if ((st = evx_ch_begin(p, c, s)) != EVX_OK) return st;
   if ((st = evx_ch_advance(p, nsteps, q, s)) != EVX_OK) return st;
   return evx_ch_end(p, c, s);
+}
+
+evx_status evx_ch_step_noalloc(evx_plan* p, float* c, int nsteps, const evx_ch_params* q,
+                               void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if ((st = check_params(q)) != EVX_OK) return st;
+  if (!c) return fail(EVX_ERR_ARG, "c is NULL");
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  const size_t need = ws_step(p->g);
+  if (need > kScratchBytes)
+    return fail(EVX_ERR_NOMEM,
+                "allocation-free step: the grid's state and work buffers need %zu bytes, the "
+                "static scratch holds %zu",
+                need, kScratchBytes);
+  unsigned char* base = scratch_of(p->device);
+  if (!base) return fail(EVX_ERR_STATE, "scratch address of device %d not resolved", p->device);
+  float2* S = reinterpret_cast<float2*>(base);
+  float2* W = reinterpret_cast<float2*>(base + state_bytes(p->g));
+  HipLauncher l;  // no pass timing: its events would be created on demand
+  l.stream = static_cast<hipStream_t>(s);
+  sched_begin(l, p->g, p->t, c, S, W, p->remap);
+  sched_advance(l, p->g, p->t, S, W, coef_of(q), nsteps, p->remap, zmode_of(q));
+  if (l.bad_len) return fail(EVX_ERR_SIZE, "step_noalloc: transform length has no kernel");
+  if (l.err != hipSuccess) return hip_fail(l.err, "step_noalloc");
+  if (q->check_finite && (st = check_state_finite(p, W, s)) != EVX_OK) return st;
+  sched_end(l, p->g, p->t, c, W, p->remap);
+  if (l.err != hipSuccess) return hip_fail(l.err, "step_noalloc end");
+  return EVX_OK;
 }
 
 evx_status evx_ch_adjoint_step(evx_plan* p, const float* c_n, float* lam,

@@ -121,6 +121,8 @@ _PROTOS = {
     "evx_ch_restore": [ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
                     ctypes.c_void_p],
+    "evx_ch_step_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                            ctypes.POINTER(_Params), ctypes.c_void_p],
     "evx_plan_enable_pass_timing": [ctypes.c_void_p, ctypes.c_int],
     "evx_plan_read_pass_times": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_longlong)],
