@@ -195,14 +195,17 @@ def copy_probe(torch, gib: float, reps: int = 3):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # HIP events on the stream the copy runs on (torch's current stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(reps):
         b.copy_(a)
-    torch.cuda.synchronize()
-    secs = (time.perf_counter() - t0) / reps
+    e1.record()
+    e1.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3 / reps
     del a, b
     torch.cuda.empty_cache()
-    return {"bytes_each_way": n * 4, "gbs": 2 * n * 4 / secs / 1e9}
+    return {"bytes_each_way": n * 4, "gbs": 2 * n * 4 / secs / 1e9, "timed_with": "hip events"}
 
 
 def pass_bytes(shape, bc):
@@ -365,13 +368,42 @@ def surrogate_workload(torch, w, reps: int = 5):
     return res
 
 
+def surrogate_experiment(torch):
+    """The metric's third leg, surrogate against plain stepping at equal error: the network is
+    trained on the GPU (600 Adam steps, batches of 4 windows of 72^3 from 256^3 solver
+    trajectories), then a 512^3 quench is rolled to T = 500 by the network under each
+    verification mode and by the plain solver at dt 0.5, 1, 2.5 and 5; errors are relative L2
+    against the solver at dt 0.5."""
+    from paper_2507_21748_amd import experiment
+    net, info = experiment.train_network()
+    res = experiment.surrogate_vs_plain(net)
+    res["training"] = info
+    del net
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline():
     """FP64 oracle on this host: 2 timed steps (after 1 untimed) of a 512^3 periodic quench with
     the same physics and IC recipe as the benchmark workload."""
     import numpy as np
     from oracle import ch
     from paper_2507_21748_amd.inputs import quench_field
-    cores = min(16, os.cpu_count() or 1)
+    # the host threads this process may use: OMP_NUM_THREADS where the host sets it (a GPU box
+    # gives one GPU's processes a share of its cores), else every core the OS reports
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     ch.WORKERS = cores
     p = ch.CHParams(dt=0.5)
     c = quench_field((512, 512, 512), 0.0, 0.05, 3).astype(np.float64)
@@ -382,7 +414,7 @@ def cpu_baseline():
         c = ch.ch_step(c, p, "periodic", "spectral")
     dt = time.perf_counter() - t0
     return {"value": 512 ** 3 * nsteps / dt, "unit": "voxel-steps/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "FP64 oracle (scipy.fft), 2 steps of a 512^3 periodic spectral quench "
                       "(mean 0, amp 0.05, dt 0.5) after 1 warm-up step"}
 
@@ -500,6 +532,7 @@ def main():
         extra["varmob256"] = varmob_workload(evx, torch)
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
         extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
+        extra["surrogate_vs_plain"] = surrogate_experiment(torch)
         line["extra"] = extra
     if not args.no_cpu_baseline:
         cb = cpu_baseline()

@@ -56,7 +56,7 @@ inline SpecArgs spec_args(const Geom& g, const TablePtrs& t, const AdjointBufs& 
   a.nx = g.nx;
   a.ny = g.ny;
   a.nz = g.nz;
-  a.pitch = g.pitch;
+  a.ypitch = g.ypitch;
   a.ncols = g.ncols;
   a.bc = g.bc;
   a.bcy = g.bcy;
@@ -147,7 +147,8 @@ void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* 
     ua.RV = RV;
     ua.n = g.spec;
     ua.ny = g.ny;
-    ua.pitch = g.pitch;
+    ua.ypitch = g.ypitch;
+    ua.nz = g.nz;
     ua.ncols = g.ncols;
     ua.bc = g.bc;
     ua.k2x = t.k2_x;

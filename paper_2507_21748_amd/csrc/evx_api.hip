@@ -201,7 +201,7 @@ bool axis_ok(int n) { return fft_len_supported(n); }
 // NaN / Inf, then synchronise and OR the per-block flags on the host.
 evx_status check_state_finite(evx_plan* p, const float2* W, void* s) {
   hipStream_t st = static_cast<hipStream_t>(s);
-  const FiniteArgs a{W, p->g.spec, p->g.pitch, p->g.ncols, p->finite_flags};
+  const FiniteArgs a{W, p->g.spec, p->g.ny, p->g.ypitch, p->g.nz, p->g.ncols, p->finite_flags};
   hipError_t e = evx_launch_finite(a, st);
   if (e != hipSuccess) return hip_fail(e, "non-finite check");
   int host[AUX_BLOCKS];

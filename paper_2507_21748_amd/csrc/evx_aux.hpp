@@ -26,7 +26,7 @@ struct SpecArgs {
   float2* F;        // in: T[f'(c^n)];  out: dt M K2 G Lam   (the B operator's multiplier)
   float2* L;        // in: T[lam^{n+1}]; out: G P Lam        (the A operator's multiplier)
   long long n;      // float2 elements of a spectral buffer
-  int nx, ny, nz, pitch, ncols, bc;  // pitch: float2 per row; ncols: of them holding data
+  int nx, ny, nz, ypitch, ncols, bc;  // grouped spectral layout; ncols x columns hold data
   int bcy, bcz;                      // y and z transform families (x periodic may mix them)
   const float *k2x, *k2y, *k2z;
   float a_dt, dt_m_kappa, dt_m, dt, dt_kappa;
@@ -61,11 +61,9 @@ EVX_DEV void spec_body(const SpecArgs& a, int tid, int bid, int nblk, double* re
   double s0 = 0.0, s1 = 0.0;
   const long long stride = (long long)nblk * AUX_THREADS;
   for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
-    const long long r = i / a.pitch;
-    const int xc = int(i - r * a.pitch);
-    if (xc >= a.ncols) continue;  // row padding
-    const int y = int(r % a.ny);
-    const int z = int(r / a.ny);
+    const SpecPos sp = spec_pos(i, a.ny, a.ypitch, a.nz, a.ncols);
+    if (!sp.live) continue;  // pad row or dead column
+    const int xc = sp.x, y = sp.y, z = sp.z;
     const float kyz = a.k2y[y] + a.k2z[z];
     const float2 Cv = a.C[i];
     float2 Fv = make_float2(0.f, 0.f), Lv = make_float2(0.f, 0.f);
@@ -185,9 +183,8 @@ EVX_DEV void final_body(const FinalArgs& a, int tid, double* red) {
 // no atomics are needed, and the host ORs the AUX_BLOCKS slots.
 struct FiniteArgs {
   const float2* w;
-  long long n;     // float2 elements
-  int pitch;       // float2 per row
-  int ncols;       // of them holding data
+  long long n;     // float2 elements (grouped spectral layout)
+  int ny, ypitch, nz, ncols;
   int* flag;       // AUX_BLOCKS slots
 };
 
@@ -202,8 +199,7 @@ EVX_DEV void finite_body(const FiniteArgs& a, int tid, int bid, int nblk, int* r
   int bad = 0;
   const long long stride = (long long)nblk * T;
   for (long long i = (long long)bid * T + tid; i < a.n; i += stride) {
-    const int xc = int(i % a.pitch);
-    if (xc >= a.ncols) continue;
+    if (!spec_pos(i, a.ny, a.ypitch, a.nz, a.ncols).live) continue;
     const float2 v = a.w[i];
     bad |= int(evx_nonfinite(v.x) || evx_nonfinite(v.y));
   }
@@ -246,7 +242,7 @@ struct GsUpdateArgs {
   const float2* RU;
   const float2* RV;
   long long n;
-  int ny, pitch, ncols, bc;
+  int ny, ypitch, nz, ncols, bc;
   const float *k2x, *k2y, *k2z;
   float dt, dt_du, dt_dv;
 };
@@ -254,10 +250,10 @@ struct GsUpdateArgs {
 EVX_DEV void gs_update_body(const GsUpdateArgs& a, int tid, int bid, int nblk) {
   const long long stride = (long long)nblk * AUX_THREADS;
   for (long long i = (long long)bid * AUX_THREADS + tid; i < a.n; i += stride) {
-    const long long r = i / a.pitch;
-    const int xc = int(i - r * a.pitch);
-    if (xc >= a.ncols) continue;  // row padding
-    const float kyz = a.k2y[int(r % a.ny)] + a.k2z[int(r / a.ny)];
+    const SpecPos sp = spec_pos(i, a.ny, a.ypitch, a.nz, a.ncols);
+    if (!sp.live) continue;  // pad row or dead column
+    const int xc = sp.x;
+    const float kyz = a.k2y[sp.y] + a.k2z[sp.z];
     float ka, kb;
     if (a.bc == BC_PERIODIC) {
       ka = kb = a.k2x[xc] + kyz;

@@ -23,6 +23,8 @@ namespace evx_emu {
 extern thread_local std::barrier<>* block_barrier;
 }
 inline void evx_sync() { evx_emu::block_barrier->arrive_and_wait(); }
+// A value the caller knows to be the same in every lane of a wave (kept in scalar registers).
+inline int evx_wave_uniform(int v) { return v; }
 inline float evx_rcp(float x) { return 1.0f / x; }
 
 // Buffer resource: a byte range [base, base + nbytes); accesses at or past nbytes read zero and
@@ -53,6 +55,8 @@ inline void evx_buf_store2(evx_buf r, unsigned off, float2 v) {
 #define EVX_RESTRICT __restrict__
 
 __device__ __forceinline__ void evx_sync() { __syncthreads(); }
+// A value the caller knows to be the same in every lane of a wave (kept in scalar registers).
+__device__ __forceinline__ int evx_wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float evx_rcp(float x) { return 1.0f / x; }
 
 // Buffer resource over [base, base + nbytes) (raw, stride 0; word 3 = 0x00020000, the gfx9

@@ -32,14 +32,14 @@ constexpr int row_threads() {
 template <int NH, int BC, int MODE>
 __global__ __launch_bounds__((row_threads<NH, BC>())) void row_kernel(RowArgs a) {
   __shared__ float2 lds[RowCfg<NH, BC>::LDS];
-  rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, lds);
+  rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, gridDim.x, lds);
 }
 
 template <int NH, int BC, int MODE>
 __global__ __launch_bounds__((row_threads<NH, BC>())) void row_kernel_batch(RowArgs a, PassBatch p) {
   __shared__ float2 lds[RowCfg<NH, BC>::LDS];
   bind_batch(a, MODE == ROW_INV, p, blockIdx.y);
-  rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, lds);
+  rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, gridDim.x, lds);
 }
 
 template <int N, int BC, int MODE>

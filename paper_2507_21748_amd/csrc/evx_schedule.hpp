@@ -51,10 +51,11 @@ struct Geom {
   int scheme = 0;        // 0 spectral, 1 stencil7
   double dx = 1.0;       // grid spacing baked into the K2 tables
   long long V = 0;       // voxels
-  int ncols = 0;         // float2 columns per row of a spectral buffer holding data
-  int pitch = 0;         // float2 per row of a spectral buffer (ncols rounded up, periodic)
+  int ncols = 0;         // float2 x columns of a spectral buffer holding data
+  int ngx = 0;           // x groups of 8 columns (grouped spectral layout, evx_passes.hpp)
+  int ypitch = 0;        // rows per (group, z) slab: ny + kSpecYPad
   int row_len = 0;       // x-pass FFT length: nx/2 (periodic) or nx (zero flux)
-  long long spec = 0;    // float2 per spectral buffer (work W)
+  long long spec = 0;    // float2 per spectral buffer (work W): ngx nz ypitch 8
   long long state = 0;   // float2 of the state S (tile-major; whole z-pass tiles)
   long long nrows = 0;   // ny * nz
 };
@@ -77,9 +78,10 @@ inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int sc
   g.V = (long long)nx * ny * nz;
   g.ncols = (bc == BC_PERIODIC) ? nx / 2 + 1 : nx / 2;
   g.row_len = (bc == BC_PERIODIC) ? nx / 2 : nx;
-  g.pitch = (bc == BC_PERIODIC) ? spectral_pitch(nx / 2) : nx / 2;
-  g.spec = (long long)nz * ny * g.pitch;
-  const long long bz = col_block_seqs(nz), nseq_z = (long long)ny * g.pitch;
+  g.ngx = (g.ncols + 7) / 8;
+  g.ypitch = ny + kSpecYPad;
+  g.spec = (long long)g.ngx * nz * g.ypitch * 8;
+  const long long bz = col_block_seqs(nz), nseq_z = (long long)g.ngx * ny * 8;
   g.state = bz > 0 ? (nseq_z + bz - 1) / bz * bz * nz : g.spec;
   g.nrows = (long long)ny * nz;
   return g;
@@ -172,33 +174,44 @@ struct StepCoef {
   float a_dt, dt_m_kappa, dt_m;
 };
 
+inline SpecGeom spec_geom(const Geom& g) {
+  return SpecGeom{(long long)g.nz * g.ypitch * 8, (long long)g.ypitch * 8, g.ny};
+}
+
+// y pass: outer index (x group, z); the points of a column are 8 float2 apart, so a block's
+// columns are one contiguous run of ny x 64 bytes.
 inline ColArgs y_args(const Geom& g, const TablePtrs& t, const float2* in, float2* out,
                       int remap) {
   ColArgs a{};
   a.in = in;
   a.out = out;
-  a.nseq = (long long)g.pitch * g.nz;
-  a.ncols = g.pitch;
+  a.nseq = (long long)g.ngx * g.nz * 8;
+  a.n_lo = g.nz;
   a.nlive = g.ncols;
-  a.row_stride = g.pitch;
-  a.outer_stride = (long long)g.pitch * g.ny;
+  a.stride_lo = (long long)g.ypitch * 8;
+  a.stride_hi = (long long)g.nz * g.ypitch * 8;
+  a.x_lo = 0;
+  a.row_stride = 8;
   a.tw = t.tw_y;
   a.mk = t.mk_y;
   a.remap = remap;
   return a;
 }
 
+// z pass: outer index (x group, y); points ypitch x 64 bytes apart.
 inline ColArgs z_args(const Geom& g, const TablePtrs& t, const float2* in, float2* out,
                       float2* state, StepCoef c, int remap) {
   ColArgs a{};
   a.in = in;
   a.out = out;
   a.state = state;
-  a.nseq = (long long)g.pitch * g.ny;
-  a.ncols = g.pitch;
+  a.nseq = (long long)g.ngx * g.ny * 8;
+  a.n_lo = g.ny;
   a.nlive = g.ncols;
-  a.row_stride = (long long)g.pitch * g.ny;
-  a.outer_stride = g.pitch;
+  a.stride_lo = 8;
+  a.stride_hi = (long long)g.nz * g.ypitch * 8;
+  a.x_lo = 0;
+  a.row_stride = (long long)g.ypitch * 8;
   a.tw = t.tw_z;
   a.mk = t.mk_z;
   a.k2c = t.k2_x;
@@ -219,6 +232,7 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   a.in_r = in_r;
   a.out_c = out_c;
   a.out_r = out_r;
+  a.sg = spec_geom(g);
   a.nrows = g.nrows;
   a.tw = t.tw_x;
   a.post = t.post_x;
@@ -227,6 +241,7 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   a.scale = float(1.0 / (double(1 << ncos) * double(g.V)));
   a.flip = g.flip;
   a.ny = g.ny;
+  a.remap = 1;
   return a;
 }
 

@@ -205,46 +205,85 @@ def sample_windows(pairs, batch: int, edge: int, rng: np.random.Generator):
 # ------------------------------------------------------------------------------ rollout
 @dataclass
 class RolloutConfig:
+    """How the solver judges the network.
+
+    Every prediction must keep the mass (|d mean| <= mass_tol) and must not raise the free energy
+    (E_new <= E (1 + energy_rtol)); a prediction failing either is replaced by the solver.  Spot
+    checks compare predictions with the solver's own `stride` steps at relative L2 <= spot_tol,
+    in one of two modes:
+
+    verify = "window": a check covers the checked application alone, from its own start state.
+      Checks are drawn at random (rate 1 / check_every, seeded), and the last application is
+      always checked.  After a failed check every application is checked until one passes, so
+      a failing network never runs unverified.  The applications between checks are accepted on
+      mass and energy alone, which a wrong prediction can pass: fast, but the error of an
+      unchecked window is not bounded.
+    verify = "span": a check runs the solver from the last verified state over every application
+      since (at most check_every of them, and at the end), compares the final states, and on a
+      failure replaces the whole span by the solver's result.  Every state the rollout hands on
+      at a check is then within spot_tol of the solver started from the previous verified state,
+      whatever the network does between checks -- but the solver runs over every window, so the
+      rollout costs at least the plain solver's time.
+    """
     stride: int = 10             # solver steps replaced by one network application
-    check_every: int = 10        # spot-check one application in this many against the solver
+    check_every: int = 10        # mean applications per spot check
     mass_tol: float = 1e-5       # |mean(c_new) - mean(c)| allowed per application
     energy_rtol: float = 1e-6    # E(c_new) <= E(c) (1 + energy_rtol)
-    spot_tol: float = 2e-3       # relative L2 to the solver's 10 steps on a spot check
+    spot_tol: float = 2e-3       # relative L2 to the solver on a spot check
     conserve_mass: bool = True   # remove the mean of every predicted increment
+    verify: str = "span"         # "span" (sound) or "window" (fast; see above)
+    seed: int = 0                # draws of the checked windows
 
 
 @dataclass
 class RolloutStats:
     applications: int = 0
-    accepted: int = 0
+    accepted: int = 0            # predictions the rollout kept
     fallback_mass: int = 0
     fallback_energy: int = 0
-    fallback_spot: int = 0
+    fallback_spot: int = 0       # failed spot checks (their window or span was recomputed)
     spot_checks: int = 0
+    solver_windows: int = 0      # windows of `stride` solver steps run (checks and fallbacks)
     spot_errors: list = field(default_factory=list)
     seconds: float = 0.0
 
 
 def rollout(net: Net, c0: torch.Tensor, napps: int, params: "evx.CHParams",
             cfg: RolloutConfig = RolloutConfig(), plan: "evx.Plan" = None):
-    """napps coarse steps of `stride` solver steps each from c0 (periodic spectral grid).  Every
-    prediction is judged by mass drift and free-energy increase (evx_ch_diagnostics); one in
-    `check_every` is also compared with `stride` solver steps.  A rejected prediction is replaced
-    by the solver's own `stride` steps.  Returns (c, stats)."""
+    """napps coarse steps of `stride` solver steps each from c0 (periodic spectral grid), every
+    prediction judged by the solver (mass, energy, spot checks; see RolloutConfig) and replaced by
+    it when rejected.  Returns (c, stats)."""
+    if cfg.verify not in ("window", "span"):
+        raise ValueError(f"unknown verify mode {cfg.verify!r}")
     shape = tuple(c0.shape)
     if plan is None:
         plan = evx.Plan(shape, "periodic", "spectral", ops=evx.OP_STEP | evx.OP_DIAG)
     V = c0.numel()
+    rng = np.random.default_rng(cfg.seed)
     st = RolloutStats()
     c = c0.clone()
     cand = torch.empty_like(c)
     diag = torch.empty(2, dtype=torch.float64, device=c.device)
     sync = torch.cuda.synchronize if c.is_cuda else (lambda: None)
+
+    def solve(start, windows):
+        out = start.clone()
+        plan.step(out, windows * cfg.stride, params)
+        st.solver_windows += windows
+        return out
+
+    def rel_err(a, b):
+        dd = plan.distance(a, b, out=diag).cpu().numpy()
+        return float(np.sqrt(dd[0] / dd[1]))
+
     sync()
     t0 = time.perf_counter()
     d_cur = plan.diagnostics(c, params).cpu().numpy()
+    strict = True                     # window mode: check until a prediction passes
+    anchor, span = c.clone(), 0       # span mode: last verified state, windows since
     for k in range(napps):
         st.applications += 1
+        last = k == napps - 1
         net.infer(c, cand, conserve_mass=cfg.conserve_mass)
         d_new = plan.diagnostics(cand, params, out=diag).cpu().numpy()
         ok = True
@@ -254,27 +293,49 @@ def rollout(net: Net, c0: torch.Tensor, napps: int, params: "evx.CHParams",
         elif d_new[1] > d_cur[1] * (1 + cfg.energy_rtol):
             st.fallback_energy += 1
             ok = False
-        solver = None
-        if ok and cfg.check_every > 0 and k % cfg.check_every == 0:
-            solver = c.clone()
-            plan.step(solver, cfg.stride, params)
-            dd = plan.distance(cand, solver, out=diag).cpu().numpy()
-            err = float(np.sqrt(dd[0] / dd[1]))
+        if cfg.verify == "window":
+            ref = None
+            if ok and (strict or last or rng.random() < 1.0 / max(cfg.check_every, 1)):
+                ref = solve(c, 1)
+                err = rel_err(cand, ref)
+                st.spot_checks += 1
+                st.spot_errors.append(err)
+                if err > cfg.spot_tol:
+                    st.fallback_spot += 1
+                    ok = False
+                strict = not ok
+            if ok:
+                st.accepted += 1
+                c, cand = cand, c
+                d_cur = d_new
+            else:
+                c = ref if ref is not None else solve(c, 1)
+                d_cur = plan.diagnostics(c, params).cpu().numpy()
+            continue
+        # span mode
+        span += 1
+        if not ok:                    # the span's earlier, unverified windows are redone too
+            c = solve(anchor, span)
+            anchor, span = c.clone(), 0
+            d_cur = plan.diagnostics(c, params).cpu().numpy()
+            continue
+        if span >= cfg.check_every or last:
+            ref = solve(anchor, span)
+            err = rel_err(cand, ref)
             st.spot_checks += 1
             st.spot_errors.append(err)
             if err > cfg.spot_tol:
                 st.fallback_spot += 1
-                ok = False
-        if ok:
-            st.accepted += 1
-            c, cand = cand, c
-            d_cur = d_new
-        else:
-            if solver is None:
-                solver = c.clone()
-                plan.step(solver, cfg.stride, params)
-            c = solver
-            d_cur = plan.diagnostics(c, params).cpu().numpy()
+                c = ref
+                d_cur = plan.diagnostics(c, params).cpu().numpy()
+            else:
+                st.accepted += span
+                c, cand = cand, c
+                d_cur = d_new
+            anchor, span = c.clone(), 0
+            continue
+        c, cand = cand, c             # provisional until the span's check
+        d_cur = d_new
     sync()
     st.seconds = time.perf_counter() - t0
     return c, st

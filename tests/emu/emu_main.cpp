@@ -78,8 +78,8 @@ struct EmuLauncher {
   void row_t(const RowArgs& a) {
     using C = RowCfg<NH, BC>;
     const int nblk = int((a.nrows + C::ROWS - 1) / C::ROWS);
-    run_grid(nblk, C::THREADS, C::LDS, [&](int tid, int bid, int, float2* lds) {
-      rowpass_body<NH, BC, MODE>(a, tid, bid, lds);
+    run_grid(nblk, C::THREADS, C::LDS, [&](int tid, int bid, int nb, float2* lds) {
+      rowpass_body<NH, BC, MODE>(a, tid, bid, nb, lds);
     });
   }
   template <int N, int BC>

@@ -43,10 +43,11 @@ def _build(kind: str) -> str:
         os.makedirs(OUT, exist_ok=True)
         cmd = [gxx, "-std=c++20", "-O1", "-g", SAN[kind], "-DEVX_HOST_EMULATION",
                "-DEVX_AUX_BLOCKS=3", f"-DEVX_FOR_EACH_N(X)={SIZES}", "-I", CSRC, MAIN,
-               "-o", exe + ".tmp", "-pthread"]
+               "-o", exe + f".tmp{os.getpid()}", "-pthread"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr[-4000:]
-        os.replace(exe + ".tmp", exe)
+        # a per-process temporary name: parallel test workers may build the same binary
+        os.replace(exe + f".tmp{os.getpid()}", exe)
     return exe
 
 
