@@ -65,6 +65,17 @@ EVX_HD long long spec_row_offset(const SpecGeom& s, long long r) {
   return z * s.zstride + (r - z * s.ny) * 8;
 }
 
+// The same for row (z0, y0) + j, j small: no division.
+EVX_HD long long spec_row_offset_from(const SpecGeom& s, long long z0, int y0, int j) {
+  int y = y0 + j;
+  long long z = z0;
+  while (y >= s.ny) {
+    y -= s.ny;
+    ++z;
+  }
+  return z * s.zstride + (long long)y * 8;
+}
+
 // column (y or z) pass modes
 enum : int {
   COL_FWD = 0,         // in -> forward transform -> out
@@ -589,6 +600,11 @@ struct SpecRowsCfg {
 // With T a multiple of 8 ROWS (>= 64) a lane keeps its row and column across iterations and the
 // x group is the same for a whole wave: each group's slab is then a buffer resource with a
 // wave-uniform base and the lane adds one 32-bit offset (no per-element 64-bit addresses).
+// Within a wave the 64 lanes move rows 8 w .. 8 w + 7 (w = wave index mod ROWS / 8) of one group,
+// lane l taking column l % 8 of row 2 ((l / 8) % 4) + l / 32: the same 512 contiguous bytes per
+// wave as the plain order, but the two halves of the wave write (and read) the LDS rows
+// {0, 2, 4, 6} and {1, 3, 5, 7}, whose 64-byte segments fall in disjoint banks at the staging
+// strides used here.
 template <int ROWS, int NL, int T>
 struct SpecRowsLane {
   using RC = SpecRowsCfg<ROWS, NL>;
@@ -598,12 +614,14 @@ struct SpecRowsLane {
   unsigned off;     // byte offset of the lane's element from zbase + group, or kDeadLane
   unsigned range;   // bytes addressable from zbase + group: the planes the block's rows reach
   EVX_DEV SpecRowsLane(const SpecGeom& sg, long long r0, long long valid_rows, int tid) {
-    c = tid & 7;
-    row = (tid >> 3) % ROWS;
+    const int l = tid & 63;
+    c = l & 7;
+    row = 8 * ((tid >> 6) % (ROWS / 8)) + 2 * ((l >> 3) & 3) + (l >> 5);
     const long long z0 = r0 / sg.ny;
+    const int y0 = int(r0 - z0 * sg.ny);
     zbase = z0 * sg.zstride;
     range = unsigned((ROWS / sg.ny + 2) * sg.zstride * 8);
-    off = row < valid_rows ? unsigned((spec_row_offset(sg, r0 + row) - zbase + c) * 8)
+    off = row < valid_rows ? unsigned((spec_row_offset_from(sg, 0, y0, row) + c) * 8)
                            : kDeadLane;
   }
   // x group of iteration I (wave-uniform)
@@ -636,12 +654,15 @@ EVX_DEV void spec_rows_in(const float2* EVX_RESTRICT src, const SpecGeom& sg, lo
     return;
   }
   const int c = tid & 7;
+  const long long z0 = r0 / sg.ny;
+  const int y0 = int(r0 - z0 * sg.ny);
   static_for<IT>([&](auto I) {
     const int f = tid + T * decltype(I)::value;
     const int g = f / RC::PER;
     const int row = (f >> 3) % ROWS;
     const bool ok = f < RC::TOT && row < valid_rows && g * 8 + c < NL;
-    r[I] = ok ? src[g * sg.xstride + spec_row_offset(sg, r0 + row) + c] : make_float2(0.f, 0.f);
+    r[I] = ok ? src[g * sg.xstride + spec_row_offset_from(sg, z0, y0, row) + c]
+              : make_float2(0.f, 0.f);
   });
   static_for<IT>([&](auto I) {
     const int f = tid + T * decltype(I)::value;
@@ -670,13 +691,15 @@ EVX_DEV void spec_rows_out(float2* EVX_RESTRICT dst, const SpecGeom& sg, long lo
     return;
   }
   const int c = tid & 7;
+  const long long z0 = r0 / sg.ny;
+  const int y0 = int(r0 - z0 * sg.ny);
   static_for<IT>([&](auto I) {
     const int f = tid + T * decltype(I)::value;
     const int g = f / RC::PER;
     const int row = (f >> 3) % ROWS;
     if (f < RC::TOT && row < valid_rows) {
       const int x = g * 8 + c;
-      dst[g * sg.xstride + spec_row_offset(sg, r0 + row) + c] =
+      dst[g * sg.xstride + spec_row_offset_from(sg, z0, y0, row) + c] =
           x < NL ? lds[row * S + x] : make_float2(0.f, 0.f);
     }
   });
