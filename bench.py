@@ -328,6 +328,24 @@ def varmob_workload(evx, torch, n: int = 256, steps: int = 100):
             "finite": bool(torch.isfinite(phi).all().item())}
 
 
+def rd_workload(evx, torch, n: int = 256, steps: int = 100):
+    """Single-species reaction-diffusion (logistic reaction, D = 1) on a 256^3 periodic spectral
+    grid: ms per step (the stepper's four passes, the fused x pass evaluating the reaction)."""
+    from paper_2507_21748_amd.inputs import quench_field
+    shape = (n, n, n)
+    plan = evx.Plan(shape, "periodic", "spectral")
+    c = torch.from_numpy(quench_field(shape, 0.2, 0.1, seed=15)).cuda()
+    prm = evx.RDParams(dt=0.5, D=1.0)
+    plan.rd_step(c, 5, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.rd_step(c, steps, prm)
+    torch.cuda.synchronize()
+    secs = (time.perf_counter() - t0) / steps
+    return {"grid": [n, n, n], "ms_per_step": 1e3 * secs,
+            "finite": bool(torch.isfinite(c).all().item())}
+
+
 def surrogate_workload(torch, w, reps: int = 5):
     """One coarse-stepper application (4 convolution layers, residual, mass projection) on the
     512^3 field: ms per application and the convolution flop rate (114,048 flop/voxel)."""
@@ -530,6 +548,7 @@ def main():
                                     "ms_per_step": r["ms_per_step"]}
         extra["gray_scott256"] = gray_scott_workload(evx, torch)
         extra["varmob256"] = varmob_workload(evx, torch)
+        extra["reaction_diffusion256"] = rd_workload(evx, torch)
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
         extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
         extra["surrogate_vs_plain"] = surrogate_experiment(torch)

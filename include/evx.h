@@ -240,6 +240,28 @@ typedef struct evx_gs_params {
 evx_status evx_gs_step(evx_plan* plan, float* u, float* v, int nsteps, const evx_gs_params* params,
                        void* hip_stream);
 
+/* Single-species reaction-diffusion (the paper's eq. reaction-diffusion, appendix
+ * "Reaction-diffusion systems") with a constant diffusivity and a cubic reaction:
+ *   dc/dt = D lap c + f(c),   f(c) = a0 + a1 c + a2 c^2 + a3 c^3,
+ * stepped with the symbol rule of appendix "Semi-implicit timestepping": the diffusion symbol
+ * -D K2 implicit, the reaction explicit, with an optional linear stabilisation A >= 0 (A = 0 is
+ * the appendix's increment form):
+ *   C' = ((1 + A dt) C + dt T[f(c)]) / (1 + A dt + dt D K2).
+ * c: caller-owned real field (C order, V floats), advanced nsteps in place on the plan's grid,
+ * boundaries and scheme.  It runs the stepper's four passes (the fused x pass evaluates -f, the z
+ * pass the update) on the plan's state and work buffers (workspace EVX_OP_STEP), so it replaces
+ * any state a previous evx_ch_begin left there.  Dirichlet axes need an odd reaction
+ * (a0 = a2 = 0: the transform runs on the sign-alternated field) -> EVX_ERR_UNSUPPORTED
+ * otherwise.  EVX_ERR_ARG unless dt > 0, D >= 0, A >= 0. */
+typedef struct evx_rd_params {
+  double dt;
+  double D;
+  double A;
+  double a0, a1, a2, a3;
+} evx_rd_params;
+evx_status evx_rd_step(evx_plan* plan, float* c, int nsteps, const evx_rd_params* params,
+                       void* hip_stream);
+
 /* Variable-mobility Cahn-Hilliard (the paper's second-order phase transformation, appendix
  * "Phase transformations of first and second order", eq. cahn-hilliard):
  *   dphi/dt = div(M grad mu),  mu = gamma0 g(phi) - 2 gamma0 eps lap phi,

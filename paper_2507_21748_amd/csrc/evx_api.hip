@@ -531,6 +531,29 @@ evx_status evx_gs_step(evx_plan* p, float* u, float* v, int nsteps, const evx_gs
   return finish(l, "gray-scott step");
 }
 
+evx_status evx_rd_step(evx_plan* p, float* c, int nsteps, const evx_rd_params* q, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if (!c || !q) return fail(EVX_ERR_ARG, "NULL argument");
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  if (!(q->dt > 0) || !(q->D >= 0) || !(q->A >= 0))
+    return fail(EVX_ERR_ARG, "params need dt > 0, D >= 0, A >= 0");
+  if (p->g.flip != 0 && (q->a0 != 0.0 || q->a2 != 0.0))
+    return fail(EVX_ERR_UNSUPPORTED,
+                "reaction-diffusion on Dirichlet axes needs an odd reaction (a0 = a2 = 0)");
+  if (!p->S) return fail(EVX_ERR_NOMEM, "no workspace set");
+  // the z pass's Allen-Cahn update with M = 1, kappa = D; the x pass evaluates -f
+  const StepCoef co{float(q->A * q->dt), float(q->dt * q->D), float(q->dt)};
+  const float poly[4] = {float(-q->a0), float(-q->a1), float(-q->a2), float(-q->a3)};
+  TimedLauncher l = launcher(p, s);
+  sched_begin(l, p->g, p->t, c, p->S, p->W, p->remap);
+  sched_advance_rd(l, p->g, p->t, p->S, p->W, co, poly, nsteps, p->remap);
+  sched_end(l, p->g, p->t, c, p->W, p->remap);
+  p->begun = false;  // the state is the reaction-diffusion field's, not a Cahn-Hilliard one
+  p->w_valid = false;
+  return finish(l, "reaction-diffusion step");
+}
+
 evx_status evx_vm_step(evx_plan* p, float* phi, int nsteps, const evx_vm_params* q, void* s) {
   evx_status st = check_plan(p);
   if (st != EVX_OK) return st;

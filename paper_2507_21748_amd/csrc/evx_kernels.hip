@@ -121,6 +121,7 @@ static hipError_t row_mode(int mode, const RowArgs& a, hipStream_t s) {
     case ROW_INV_ADD: return row_go<NH, BC, ROW_INV_ADD>(a, s);
     case ROW_FWD_FP: return row_go<NH, BC, ROW_FWD_FP>(a, s);
     case ROW_FUSED_REC: return row_go<NH, BC, ROW_FUSED_REC>(a, s);
+    case ROW_FUSED_POLY: return row_go<NH, BC, ROW_FUSED_POLY>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -96,7 +96,8 @@ enum : int {
   ROW_INV = 2,    // complex row -> inverse x -> real row
   ROW_FWD_FP = 3, // real row -> f'(c) -> forward x -> complex row (adjoint: T[f'(c)])
   ROW_FUSED_REC = 4, // ROW_FUSED that also stores the real row it passes through (out_r)
-  ROW_INV_ADD = 5    // ROW_INV that adds the real row to out_r instead of storing it
+  ROW_INV_ADD = 5,   // ROW_INV that adds the real row to out_r instead of storing it
+  ROW_FUSED_POLY = 6 // ROW_FUSED with the cubic poly(c) of RowArgs in place of f'(c)
 };
 
 // A column pass transforms nseq = 8 nouter sequences: sequence s is column s % 8 of outer index
@@ -139,6 +140,7 @@ struct RowArgs {
   int flip;            // Dirichlet axes (bit 0 x, 1 y, 2 z): real rows carry (-1)^(their index)
   int ny;              // rows r = j + ny l (for the sign)
   int remap;           // XCD-aware block order (consecutive row blocks on one XCD)
+  float poly[4];       // ROW_FUSED_POLY: poly(c) = poly[0] + poly[1] c + poly[2] c^2 + poly[3] c^3
 };
 
 // (-1)^(i [x Dirichlet] + j [y Dirichlet] + l [z Dirichlet]) of point i of row r = j + ny l
@@ -183,6 +185,21 @@ EVX_DEV int remap_block(int bid, int nblk, int on) {
 }
 
 EVX_DEV float fprime(float c) { return c * c * c - c; }
+
+// The fused x pass's pointwise nonlinearity: f'(c) = c^3 - c, or a cubic polynomial (Horner form
+// with explicit fused multiply-adds) for the reaction-diffusion step.
+template <int MODE>
+EVX_DEV float2 row_nonlin(const RowArgs& a, float2 v) {
+  if constexpr (MODE == ROW_FUSED_POLY) {
+    auto p = [&](float c) {
+      return __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(a.poly[3], c, a.poly[2]), c, a.poly[1]),
+                            c, a.poly[0]);
+    };
+    return make_float2(p(v.x), p(v.y));
+  } else {
+    return make_float2(fprime(v.x), fprime(v.y));
+  }
+}
 
 // Index of the cell-centred input point that becomes point n of Makhoul's reordered sequence
 // (v_n = x_{2n} for 2n < N, else x_{2N-2n-1}).
@@ -809,7 +826,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, int nblk, float2* 
         if constexpr (MODE == ROW_INV || MODE == ROW_INV_ADD) return;
         evx_sync();  // the forward transform reuses the staging area
       }
-      static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
+      static_for<E>([&](auto e) { x[e] = row_nonlin<MODE>(a, x[e]); });
     }
     // ---------------------------------------------------------------- forward x (R2C)
     fft_regs<NH, -1, B>(x, lds, b, t, twl);
@@ -907,7 +924,7 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, int nblk, float2* 
         if constexpr (MODE == ROW_INV || MODE == ROW_INV_ADD) return;
         evx_sync();  // the forward transform reuses the staging area
       }
-      static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
+      static_for<E>([&](auto e) { x[e] = row_nonlin<MODE>(a, x[e]); });
     }
     fft_regs<NX, -1, B>(x, lds, b, t, twl);
     static_for<E>([&](auto e) { lds[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });

@@ -268,6 +268,22 @@ void sched_advance(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W
   }
 }
 
+// Reaction-diffusion (dc/dt = D lap c + f(c), f cubic): the same four passes, the fused x pass
+// evaluating poly = -f (ROW_FUSED_POLY) and the z pass the Allen-Cahn form of the update with
+// M = 1, kappa = D: C' = ((1 + A dt) C + dt T[f]) / (1 + A dt + dt D K2).
+template <class L>
+void sched_advance_rd(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, StepCoef c,
+                      const float poly[4], int nsteps, int remap) {
+  RowArgs xa = x_args(g, t, W, nullptr, W, nullptr);
+  for (int k = 0; k < 4; ++k) xa.poly[k] = poly[k];
+  for (int n = 0; n < nsteps; ++n) {
+    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
+    l.row(g.row_len, g.bc, ROW_FUSED_POLY, xa);
+    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.nz, g.bcz, COL_Z_AC, z_args(g, t, W, W, S, c, remap));
+  }
+}
+
 // As sched_advance, also recording the real field c^n at the start of each step into
 // traj + n V (the fused x pass stores the row it passes through).
 template <class L>

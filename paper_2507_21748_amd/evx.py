@@ -74,6 +74,28 @@ class GSParams:
         return _GSParams(self.dt, self.Du, self.Dv, self.F, self.k)
 
 
+class _RDParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("D", ctypes.c_double), ("A", ctypes.c_double),
+                ("a0", ctypes.c_double), ("a1", ctypes.c_double), ("a2", ctypes.c_double),
+                ("a3", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class RDParams:
+    """Reaction-diffusion: dc/dt = D lap c + a0 + a1 c + a2 c^2 + a3 c^3 (default: logistic
+    growth c (1 - c)), stabilisation A."""
+    dt: float = 0.5
+    D: float = 1.0
+    A: float = 0.0
+    a0: float = 0.0
+    a1: float = 1.0
+    a2: float = -1.0
+    a3: float = 0.0
+
+    def c(self) -> _RDParams:
+        return _RDParams(self.dt, self.D, self.A, self.a0, self.a1, self.a2, self.a3)
+
+
 class _VMParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("D0", ctypes.c_double), ("gamma0", ctypes.c_double),
                 ("eps", ctypes.c_double), ("M0", ctypes.c_double)]
@@ -114,6 +136,8 @@ _PROTOS = {
     "evx_gs_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                     ctypes.POINTER(_GSParams), ctypes.c_void_p],
     "evx_vm_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_VMParams),
+                    ctypes.c_void_p],
+    "evx_rd_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_RDParams),
                     ctypes.c_void_p],
     "evx_ch_advance_record": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(_Params),
                               ctypes.c_void_p, ctypes.c_void_p],
@@ -254,6 +278,14 @@ class Plan:
         _check(_LIB.evx_vm_step(self._h, _dev_ptr(phi, numel=self.voxels), int(nsteps),
                                 ctypes.byref(p), _stream_handle(stream)), "evx_vm_step")
         return phi
+
+    def rd_step(self, c: torch.Tensor, nsteps: int, params: RDParams, stream=None):
+        """Advance the reaction-diffusion field c (float32 device tensor of the grid) nsteps in
+        place on the plan's state and work buffers."""
+        p = params.c()
+        _check(_LIB.evx_rd_step(self._h, _dev_ptr(c, numel=self.voxels), int(nsteps),
+                                ctypes.byref(p), _stream_handle(stream)), "evx_rd_step")
+        return c
 
     def advance_record(self, nsteps: int, params: CHParams, traj: torch.Tensor, stream=None):
         """Advance nsteps, writing c^n at the start of each step to traj[n] (float32 device tensor

@@ -104,6 +104,7 @@ struct EmuLauncher {
       case ROW_FWD_FP: row_t<NH, BC, ROW_FWD_FP>(a); break;
       case ROW_INV_ADD: row_t<NH, BC, ROW_INV_ADD>(a); break;
       case ROW_FUSED_REC: row_t<NH, BC, ROW_FUSED_REC>(a); break;
+      case ROW_FUSED_POLY: row_t<NH, BC, ROW_FUSED_POLY>(a); break;
       default: row_t<NH, BC, ROW_INV>(a); break;
     }
   }
@@ -314,7 +315,38 @@ static int run_vm(int argc, char** argv) {
   return 0;
 }
 
+// rd nx ny nz bc scheme dx dt D A a0 a1 a2 a3 nsteps in out: reaction-diffusion steps
+int run_rd(int argc, char** argv) {
+  if (argc != 18) {
+    std::fprintf(stderr, "usage: rd nx ny nz bc scheme dx dt D A a0 a1 a2 a3 nsteps in out\n");
+    return 2;
+  }
+  const int nx = std::atoi(argv[2]), ny = std::atoi(argv[3]), nz = std::atoi(argv[4]);
+  const int bc = std::atoi(argv[5]), scheme = std::atoi(argv[6]);
+  const double dx = std::atof(argv[7]), dt = std::atof(argv[8]), D = std::atof(argv[9]);
+  const double A = std::atof(argv[10]);
+  const float poly[4] = {float(-std::atof(argv[11])), float(-std::atof(argv[12])),
+                         float(-std::atof(argv[13])), float(-std::atof(argv[14]))};
+  const int nsteps = std::atoi(argv[15]);
+  const Geom g = geom_of(nx, ny, nz, bc, scheme, dx);
+  const HostTables h = make_tables(g);
+  TablePtrs t{h.tw_x.data(), h.tw_y.data(), h.tw_z.data(), h.post_x.data(),
+              h.mk_y.empty() ? nullptr : h.mk_y.data(), h.mk_z.empty() ? nullptr : h.mk_z.data(),
+              h.k2_x.data(), h.k2_y.data(), h.k2_z.data()};
+  std::vector<float> c(g.V);
+  if (!read_f32(argv[16], c)) return 4;
+  std::vector<float2> S(g.state), W(g.spec);
+  const StepCoef co{float(A * dt), float(dt * D), float(dt)};
+  EmuLauncher l;
+  sched_begin(l, g, t, c.data(), S.data(), W.data(), 1);
+  sched_advance_rd(l, g, t, S.data(), W.data(), co, poly, nsteps, 1);
+  sched_end(l, g, t, c.data(), W.data(), 1);
+  if (!write_all(argv[17], c.data(), c.size())) return 5;
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc > 1 && std::strcmp(argv[1], "rd") == 0) return run_rd(argc, argv);
   if (argc > 1 && std::strcmp(argv[1], "gs") == 0) return run_gs(argc, argv);
   if (argc > 1 && std::strcmp(argv[1], "vm") == 0) return run_vm(argc, argv);
   if (argc > 1 && (std::strcmp(argv[1], "adj") == 0 || std::strcmp(argv[1], "diag") == 0))

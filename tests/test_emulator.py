@@ -235,6 +235,35 @@ def test_emulated_adjoint_step_and_diagnostics(asan, shape, bc, scheme):
     assert abs(o[1] / ch.energy(c.astype(np.float64), p, bc, scheme) - 1) <= 1e-6
 
 
+@pytest.mark.parametrize("shape,bc,scheme", [((16, 12, 16), "periodic", "stencil7"),
+                                             ((8, 24, 16), "zero_flux", "spectral"),
+                                             ((12, 20, 16), ("dirichlet", "zero_flux",
+                                                             "periodic"), "spectral")])
+def test_emulated_reaction_diffusion_matches_oracle(asan, shape, bc, scheme):
+    """The reaction-diffusion schedule (the fused x pass with the cubic reaction, the z pass's
+    update) against the oracle; the Dirichlet mix runs an odd reaction."""
+    from oracle import reaction_diffusion as rd
+    odd = not isinstance(bc, str)
+    p = rd.RDParams(dt=0.4, D=0.8, A=0.5, a0=0.0 if odd else 0.05, a1=0.7,
+                    a2=0.0 if odd else -0.6, a3=-0.9)
+    c0 = quench_field(shape, 0.3, 0.3, seed=35)
+    nz, ny, nx = shape
+    code = {"periodic": 0, "zero_flux": 1, "dirichlet": 2}
+    bcarg = code[bc] if isinstance(bc, str) else \
+        1000 + 100 * code[bc[2]] + 10 * code[bc[1]] + code[bc[0]]
+    with tempfile.TemporaryDirectory() as d:
+        c0.tofile(os.path.join(d, "c"))
+        r = subprocess.run([asan, "rd", str(nx), str(ny), str(nz), str(bcarg),
+                            str(int(scheme == "stencil7")), "1.0", repr(p.dt), repr(p.D),
+                            repr(p.A), repr(p.a0), repr(p.a1), repr(p.a2), repr(p.a3), "3",
+                            os.path.join(d, "c"), os.path.join(d, "o")],
+                           capture_output=True, text=True, timeout=600)
+        assert r.returncode == 0, r.stderr[-4000:]
+        out = np.fromfile(os.path.join(d, "o"), np.float32).reshape(shape)
+    ref = rd.rd_run(c0, 3, p, bc, scheme)
+    assert _rel(out, ref) <= 1e-6
+
+
 @pytest.mark.parametrize("shape,bc,scheme", [((16, 12, 16), "periodic", "spectral"),
                                              ((8, 24, 16), "zero_flux", "stencil7"),
                                              ((12, 20, 16), ("dirichlet", "zero_flux",
