@@ -126,7 +126,10 @@ def test_stencil_laplacian_against_dense():
 
 MIXES = [("dirichlet", "zero_flux", "zero_flux"), ("zero_flux", "dirichlet", "dirichlet"),
          ("zero_flux", "zero_flux", "dirichlet"), ("dirichlet", "periodic", "periodic"),
-         ("zero_flux", "dirichlet", "periodic"), ("periodic", "zero_flux", "periodic")]
+         ("zero_flux", "dirichlet", "periodic"), ("periodic", "zero_flux", "periodic"),
+         # periodic y or z under a non-periodic x
+         ("periodic", "zero_flux", "dirichlet"), ("zero_flux", "periodic", "zero_flux"),
+         ("periodic", "periodic", "dirichlet")]
 
 
 @pytest.mark.parametrize("bcs", MIXES)
@@ -148,13 +151,13 @@ def test_mixed_axes_extension_identity(bcs, scheme):
     assert np.max(np.abs(per - got)) < 1e-13
 
 
-@pytest.mark.parametrize("bcs", MIXES[:3])
+@pytest.mark.parametrize("bcs", MIXES[:3] + MIXES[6:])
 def test_mixed_axes_dense_solve(bcs):
     from tests.test_oracle_ch import _d2_1d
     p = CHParams(dx=0.7, dt=0.3, M=0.8, kappa=1.3, A=2.0)
     c = quench_field((4, 6, 4), 0.1, 0.6, seed=14).astype(np.float64)
     mats = [_d2_dirichlet(n, p.dx, "stencil7") if b == "dirichlet"
-            else _d2_1d(n, p.dx, "zero_flux", "stencil7") for n, b in zip(c.shape, bcs)]
+            else _d2_1d(n, p.dx, b, "stencil7") for n, b in zip(c.shape, bcs)]
     Lz, Ly, Lx = mats
     Iz, Iy, Ix = (np.eye(n) for n in c.shape)
     L = (np.kron(Lz, np.kron(Iy, Ix)) + np.kron(Iz, np.kron(Ly, Ix))
