@@ -125,10 +125,10 @@ typedef struct evx_plan evx_plan;
  * Allocates the device tables on the current device (EVX_ERR_HIP / EVX_ERR_NOMEM on failure).
  * *out is set only on success and is released with evx_plan_destroy. */
 /* As evx_plan_create with a boundary condition per axis (the paper's "BCs x grid conventions x
- * stencils" per direction): a periodic x with any y and z, or any mix of EVX_BC_ZERO_FLUX and
- * EVX_BC_DIRICHLET (each Dirichlet axis carries its own sign and reversed wavenumbers).  A
- * periodic y or z with a non-periodic x returns EVX_ERR_UNSUPPORTED: the x transform then keeps
- * real spectral data, which a complex y or z transform cannot. */
+ * stencils" per direction): any mix of EVX_BC_PERIODIC, EVX_BC_ZERO_FLUX and EVX_BC_DIRICHLET
+ * (each Dirichlet axis carries its own sign and reversed wavenumbers).  A cosine x transform keeps
+ * two real bins per complex column of the spectral buffers, except under a periodic y or z, whose
+ * complex transform needs one complex column per x bin (twice the spectral bytes). */
 evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc bc_x, evx_bc bc_y,
                                 evx_bc bc_z, evx_scheme scheme, double dx);
 evx_status evx_plan_create(evx_plan** out, int nx, int ny, int nz, evx_bc bc, evx_scheme scheme,

@@ -59,6 +59,7 @@ inline SpecArgs spec_args(const Geom& g, const TablePtrs& t, const AdjointBufs& 
   a.ypitch = g.ypitch;
   a.ncols = g.ncols;
   a.bc = g.bc;
+  a.xcplx = g.xcplx;
   a.bcy = g.bcy;
   a.bcz = g.bcz;
   a.k2x = t.k2_x;
@@ -88,7 +89,7 @@ void sched_adjoint(L& l, const Geom& g, const TablePtrs& t, const float* c, floa
   l.col_batch(g.nz, g.bcz, COL_FWD, z_args(g, t, b.A, b.A, nullptr, StepCoef{0, 0, 0}, remap),
               spec3);
   l.spec(spec_args(g, t, b, co, 0));
-  const double norm = (g.bc == BC_PERIODIC) ? 1.0 / double(g.V) : 1.0;
+  const double norm = (g.bc == BC_PERIODIC || g.xcplx) ? 1.0 / double(g.V) : 1.0;
   l.final(FinalArgs{b.partial, AUX_BLOCKS, dk, dM, norm, norm, 1, 1});
   // inverse transforms: Lm -> lam, B -> v
   const PassBatch spec2{{b.Lm, b.B, nullptr}, {b.Lm, b.B, nullptr}, 2};
@@ -107,7 +108,7 @@ void sched_diagnostics(L& l, const Geom& g, const TablePtrs& t, const float* c, 
   sched_forward(l, g, t, c, b.A, false, remap);
   AdjointCoef co{};
   l.spec(spec_args(g, t, b, co, 1));
-  const double norm = (g.bc == BC_PERIODIC) ? 1.0 / double(g.V) : 1.0;
+  const double norm = (g.bc == BC_PERIODIC || g.xcplx) ? 1.0 / double(g.V) : 1.0;
   const double dx3 = g.dx * g.dx * g.dx;
   // out[1] <- dx^3 (kappa/2) sum w K2 |C|^2, then the real-space sums add f(c) and set the mass
   l.final(FinalArgs{b.partial, AUX_BLOCKS, out + 1, nullptr, dx3 * 0.5 * kappa * norm, 0.0, 0, 0});
@@ -151,6 +152,7 @@ void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* 
     ua.nz = g.nz;
     ua.ncols = g.ncols;
     ua.bc = g.bc;
+    ua.xcplx = g.xcplx;
     ua.k2x = t.k2_x;
     ua.k2y = t.k2_y;
     ua.k2z = t.k2_z;

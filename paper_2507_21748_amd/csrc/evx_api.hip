@@ -248,8 +248,6 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
   for (evx_bc b : {bc_x, bc_y, bc_z})
     if (b != EVX_BC_PERIODIC && b != EVX_BC_ZERO_FLUX && b != EVX_BC_DIRICHLET)
       return fail(EVX_ERR_ARG, "bad bc %d", b);
-  if (bc_x != EVX_BC_PERIODIC && (bc_y == EVX_BC_PERIODIC || bc_z == EVX_BC_PERIODIC))
-    return fail(EVX_ERR_UNSUPPORTED, "periodic y or z needs a periodic x");
   const evx_bc bc = bc_x;
   if (scheme != EVX_SCHEME_SPECTRAL && scheme != EVX_SCHEME_STENCIL7)
     return fail(EVX_ERR_ARG, "bad scheme %d", scheme);

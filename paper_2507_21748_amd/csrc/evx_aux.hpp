@@ -27,6 +27,7 @@ struct SpecArgs {
   float2* L;        // in: T[lam^{n+1}]; out: G P Lam        (the A operator's multiplier)
   long long n;      // float2 elements of a spectral buffer
   int nx, ny, nz, ypitch, ncols, bc;  // grouped spectral layout; ncols x columns hold data
+  int xcplx;                          // cosine x with one complex column per bin
   int bcy, bcz;                      // y and z transform families (x periodic may mix them)
   const float *k2x, *k2y, *k2z;
   float a_dt, dt_m_kappa, dt_m, dt, dt_kappa;
@@ -73,11 +74,12 @@ EVX_DEV void spec_body(const SpecArgs& a, int tid, int bid, int nblk, double* re
     }
     float K2[2];
     double w[2];
-    if (a.bc == BC_PERIODIC) {
+    if (a.bc == BC_PERIODIC || a.xcplx) {
       K2[0] = K2[1] = a.k2x[xc] + kyz;
-      // half spectrum along x; a cosine axis weighs its bins n w_k relative to a periodic one
-      // (the 1/V normalisation is applied to the sums)
-      const double wx = (xc == 0 || 2 * xc == a.nx) ? 1.0 : 2.0;
+      // half spectrum along x (or a cosine x bin as a complex column); a cosine axis weighs its
+      // bins n w_k relative to a periodic one (the 1/V normalisation is applied to the sums)
+      const double wx = a.xcplx ? (xc == 0 ? 0.25 : 0.5)
+                                : ((xc == 0 || 2 * xc == a.nx) ? 1.0 : 2.0);
       const double fy = a.bcy == BC_PERIODIC ? 1.0 : (y == 0 ? 0.25 : 0.5);
       const double fz = a.bcz == BC_PERIODIC ? 1.0 : (z == 0 ? 0.25 : 0.5);
       w[0] = w[1] = wx * fy * fz;
@@ -89,7 +91,7 @@ EVX_DEV void spec_body(const SpecArgs& a, int tid, int bid, int nblk, double* re
       w[1] = dct_weight(2 * xc + 1, a.nx) * wyz;
     }
     if (a.mode == 1) {
-      if (a.bc == BC_PERIODIC) {
+      if (a.bc == BC_PERIODIC || a.xcplx) {
         s0 += w[0] * double(K2[0]) * (double(Cv.x) * Cv.x + double(Cv.y) * Cv.y);
       } else {
         s0 += w[0] * double(K2[0]) * double(Cv.x) * Cv.x + w[1] * double(K2[1]) * double(Cv.y) * Cv.y;
@@ -243,6 +245,7 @@ struct GsUpdateArgs {
   const float2* RV;
   long long n;
   int ny, ypitch, nz, ncols, bc;
+  int xcplx;  // cosine x with one complex column per bin
   const float *k2x, *k2y, *k2z;
   float dt, dt_du, dt_dv;
 };
@@ -255,7 +258,7 @@ EVX_DEV void gs_update_body(const GsUpdateArgs& a, int tid, int bid, int nblk) {
     const int xc = sp.x;
     const float kyz = a.k2y[sp.y] + a.k2z[sp.z];
     float ka, kb;
-    if (a.bc == BC_PERIODIC) {
+    if (a.bc == BC_PERIODIC || a.xcplx) {
       ka = kb = a.k2x[xc] + kyz;
     } else {
       ka = a.k2x[2 * xc] + kyz;

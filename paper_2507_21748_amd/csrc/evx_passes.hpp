@@ -140,6 +140,7 @@ struct RowArgs {
   int flip;            // Dirichlet axes (bit 0 x, 1 y, 2 z): real rows carry (-1)^(their index)
   int ny;              // rows r = j + ny l (for the sign)
   int remap;           // XCD-aware block order (consecutive row blocks on one XCD)
+  int xcplx;           // cosine x: spectral columns are complex, one per bin (real data)
   float poly[4];       // ROW_FUSED_POLY: poly(c) = poly[0] + poly[1] c + poly[2] c^2 + poly[3] c^3
 };
 
@@ -648,9 +649,18 @@ struct SpecRowsLane {
   }
 };
 
-template <int ROWS, int S, int NL, int T>
+// RE: the columns are complex values whose real part is the data (a cosine x transform under a
+// periodic y or z): only the real parts are staged, as floats at row stride S.
+template <int ROWS, int S, int NL, int T, bool RE = false>
 EVX_DEV void spec_rows_in(const float2* EVX_RESTRICT src, const SpecGeom& sg, long long r0,
                           long long valid_rows, float2* lds, int tid) {
+  auto put = [&](int row, int x, float2 v) {
+    if constexpr (RE) {
+      reinterpret_cast<float*>(lds)[row * S + x] = v.x;
+    } else {
+      lds[row * S + x] = v;
+    }
+  };
   using RC = SpecRowsCfg<ROWS, NL>;
   using LN = SpecRowsLane<ROWS, NL, T>;
   static_assert(T % 8 == 0, "lanes move whole 8-column pieces");
@@ -666,7 +676,7 @@ EVX_DEV void spec_rows_in(const float2* EVX_RESTRICT src, const SpecGeom& sg, lo
     });
     static_for<IT>([&](auto I) {
       const int g = ln.template group<decltype(I)::value>(tid);
-      if (g < RC::NG && g * 8 + ln.c < NL) lds[ln.row * S + g * 8 + ln.c] = r[I];
+      if (g < RC::NG && g * 8 + ln.c < NL) put(ln.row, g * 8 + ln.c, r[I]);
     });
     return;
   }
@@ -685,13 +695,20 @@ EVX_DEV void spec_rows_in(const float2* EVX_RESTRICT src, const SpecGeom& sg, lo
     const int f = tid + T * decltype(I)::value;
     const int g = f / RC::PER;
     const int row = (f >> 3) % ROWS;
-    if (f < RC::TOT && g * 8 + c < NL) lds[row * S + g * 8 + c] = r[I];
+    if (f < RC::TOT && g * 8 + c < NL) put(row, g * 8 + c, r[I]);
   });
 }
 
-template <int ROWS, int S, int NL, int T>
+template <int ROWS, int S, int NL, int T, bool RE = false>
 EVX_DEV void spec_rows_out(float2* EVX_RESTRICT dst, const SpecGeom& sg, long long r0,
                            long long valid_rows, const float2* lds, int tid) {
+  auto get = [&](int row, int x) {
+    if constexpr (RE) {
+      return make_float2(reinterpret_cast<const float*>(lds)[row * S + x], 0.f);
+    } else {
+      return lds[row * S + x];
+    }
+  };
   using RC = SpecRowsCfg<ROWS, NL>;
   using LN = SpecRowsLane<ROWS, NL, T>;
   static_assert(T % 8 == 0, "lanes move whole 8-column pieces");
@@ -701,7 +718,7 @@ EVX_DEV void spec_rows_out(float2* EVX_RESTRICT dst, const SpecGeom& sg, long lo
     static_for<IT>([&](auto I) {
       const int g = ln.template group<decltype(I)::value>(tid);
       const int x = g * 8 + ln.c;
-      const float2 v = x < NL ? lds[ln.row * S + x] : make_float2(0.f, 0.f);
+      const float2 v = x < NL ? get(ln.row, x) : make_float2(0.f, 0.f);
       evx_buf_store2(evx_make_buf(dst + ln.zbase + g * sg.xstride, ln.range),
                      g < RC::NG ? ln.off : kDeadLane, v);
     });
@@ -717,7 +734,7 @@ EVX_DEV void spec_rows_out(float2* EVX_RESTRICT dst, const SpecGeom& sg, long lo
     if (f < RC::TOT && row < valid_rows) {
       const int x = g * 8 + c;
       dst[g * sg.xstride + spec_row_offset_from(sg, z0, y0, row) + c] =
-          x < NL ? lds[row * S + x] : make_float2(0.f, 0.f);
+          x < NL ? get(row, x) : make_float2(0.f, 0.f);
     }
   });
 }
@@ -858,7 +875,10 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, int nblk, float2* 
     constexpr int SS = C::ZPAD ? ZS / 2 : NX / 2;  // LDS row stride in float2
     // rows are NX floats (NX even) = NX/2 float2; r0 is even
     if constexpr (!real_in) {
-      spec_rows_in<2 * B, SS, NX / 2, T>(a.in_c, a.sg, r0, a.nrows - r0, lds, tid);
+      if (a.xcplx)  // complex columns, one per bin (a periodic y or z follows)
+        spec_rows_in<2 * B, ZS, NX, T, true>(a.in_c, a.sg, r0, a.nrows - r0, lds, tid);
+      else
+        spec_rows_in<2 * B, SS, NX / 2, T>(a.in_c, a.sg, r0, a.nrows - r0, lds, tid);
     } else if constexpr (C::ZPAD) {
       rows_in<2 * B, NX / 2, ZS / 2, NX / 2, T>(
           reinterpret_cast<const float2*>(a.in_r) + r0 * (NX / 2), a.nrows - r0, lds, tid);
@@ -946,7 +966,10 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, int nblk, float2* 
       st[(2 * b + 1) * ZS + k] = y[e].y;
     });
     evx_sync();
-    spec_rows_out<2 * B, SS, NX / 2, T>(a.out_c, a.sg, r0, a.nrows - r0, lds, tid);
+    if (a.xcplx)
+      spec_rows_out<2 * B, ZS, NX, T, true>(a.out_c, a.sg, r0, a.nrows - r0, lds, tid);
+    else
+      spec_rows_out<2 * B, SS, NX / 2, T>(a.out_c, a.sg, r0, a.nrows - r0, lds, tid);
   }
 }
 

@@ -51,6 +51,7 @@ struct Geom {
   int scheme = 0;        // 0 spectral, 1 stencil7
   double dx = 1.0;       // grid spacing baked into the K2 tables
   long long V = 0;       // voxels
+  int xcplx = 0;         // cosine x under a periodic y or z: one complex column per x bin
   int ncols = 0;         // float2 x columns of a spectral buffer holding data
   int ngx = 0;           // x groups of 8 columns (grouped spectral layout, evx_passes.hpp)
   int ypitch = 0;        // rows per (group, z) slab: ny + kSpecYPad
@@ -76,7 +77,10 @@ inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int sc
   g.scheme = scheme;
   g.dx = dx;
   g.V = (long long)nx * ny * nz;
-  g.ncols = (bc == BC_PERIODIC) ? nx / 2 + 1 : nx / 2;
+  // a cosine x keeps two real bins per float2 column, unless a periodic y or z transform follows,
+  // whose complex output needs one complex column per bin
+  g.xcplx = (bc != BC_PERIODIC && (g.bcy == BC_PERIODIC || g.bcz == BC_PERIODIC)) ? 1 : 0;
+  g.ncols = (bc == BC_PERIODIC) ? nx / 2 + 1 : (g.xcplx ? nx : nx / 2);
   g.row_len = (bc == BC_PERIODIC) ? nx / 2 : nx;
   g.ngx = (g.ncols + 7) / 8;
   g.ypitch = ny + kSpecYPad;
@@ -221,7 +225,7 @@ inline ColArgs z_args(const Geom& g, const TablePtrs& t, const float2* in, float
   a.dt_m_kappa = c.dt_m_kappa;
   a.dt_m = c.dt_m;
   a.remap = remap;
-  a.xcomplex = g.bc == BC_PERIODIC ? 1 : 0;
+  a.xcomplex = (g.bc == BC_PERIODIC || g.xcplx) ? 1 : 0;
   return a;
 }
 
@@ -233,6 +237,7 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   a.out_c = out_c;
   a.out_r = out_r;
   a.sg = spec_geom(g);
+  a.xcplx = g.xcplx;
   a.nrows = g.nrows;
   a.tw = t.tw_x;
   a.post = t.post_x;

@@ -117,9 +117,13 @@ def test_emulated_allen_cahn_matches_oracle(asan, shape, bc, scheme, n, etd1):
 
 
 @pytest.mark.parametrize("bcs", [("dirichlet", "zero_flux", "dirichlet"),
-                                 ("zero_flux", "dirichlet", "periodic")])
+                                 ("zero_flux", "dirichlet", "periodic"),
+                                 ("periodic", "zero_flux", "dirichlet"),
+                                 ("zero_flux", "periodic", "zero_flux"),
+                                 ("periodic", "periodic", "zero_flux")])
 def test_emulated_mixed_axes_match_oracle(asan, bcs):
-    """Per-axis boundaries (z, y, x) against the oracle, with and without a periodic x."""
+    """Per-axis boundaries (z, y, x) against the oracle, with and without a periodic x, and
+    with a periodic y or z under a cosine x (one complex column per x bin)."""
     shape = (12, 20, 16)
     p = CHParams(dt=0.5, M=0.9, kappa=1.1, A=2.0)
     c0 = quench_field(shape, 0.1, 0.3, seed=17)
@@ -201,7 +205,9 @@ def test_planted_missing_barrier_is_caught(tmp_path):
                                              ((12, 20, 16), ("zero_flux", "dirichlet",
                                                              "periodic"), "stencil7"),
                                              ((12, 20, 16), ("dirichlet", "zero_flux",
-                                                             "dirichlet"), "spectral")])
+                                                             "dirichlet"), "spectral"),
+                                             ((12, 20, 16), ("periodic", "dirichlet",
+                                                             "zero_flux"), "stencil7")])
 def test_emulated_adjoint_step_and_diagnostics(asan, shape, bc, scheme):
     """One adjoint step (lam, dL/dkappa, dL/dM) and the mass/energy diagnostics of the emulated
     kernels against the oracle's adjoint and energy."""

@@ -125,7 +125,10 @@ def test_with_other_integrators_and_models(evx_gpu, which):
 
 MIXES = [("dirichlet", "zero_flux", "zero_flux"), ("zero_flux", "dirichlet", "dirichlet"),
          ("zero_flux", "zero_flux", "dirichlet"), ("zero_flux", "dirichlet", "periodic"),
-         ("periodic", "zero_flux", "periodic"), ("dirichlet", "periodic", "periodic")]
+         ("periodic", "zero_flux", "periodic"), ("dirichlet", "periodic", "periodic"),
+         # a periodic y or z under a cosine x: one complex column per x bin
+         ("periodic", "zero_flux", "dirichlet"), ("zero_flux", "periodic", "zero_flux"),
+         ("periodic", "periodic", "zero_flux")]
 
 
 @pytest.mark.parametrize("bcs", MIXES)
@@ -156,7 +159,44 @@ def test_mixed_axes_extension_identity_on_gpu(evx_gpu):
     assert rel_l2(got, per) <= 2e-5
 
 
-def test_periodic_mixed_with_other_axes_is_unsupported(evx_gpu):
-    with pytest.raises(evx_gpu.EvxError) as e:
-        evx_gpu.Plan((16, 16, 16), ("periodic", "zero_flux", "zero_flux"), "spectral")
-    assert e.value.status == 3
+def test_periodic_yz_under_cosine_x_extension_identity_on_gpu(evx_gpu):
+    """z periodic, y zero flux, x Dirichlet at 64 x 48 x 96 for 5 steps = periodic
+    64 x 96 x 192 on the extension even in y and odd in x (both on the GPU)."""
+    p = OParams(dt=0.5)
+    bcs = ("periodic", "zero_flux", "dirichlet")
+    c0 = quench_field((64, 48, 96), 0.0, 0.3, seed=68)
+    e = c0
+    for ax, b in enumerate(bcs):
+        if b != "periodic":
+            e = np.concatenate([e, (-1.0 if b == "dirichlet" else 1.0) * np.flip(e, axis=ax)],
+                               axis=ax)
+    per = gpu_run(evx_gpu, e.astype(np.float32), "periodic", "spectral", 5, p)[:64, :48, :96]
+    got = gpu_run(evx_gpu, c0, bcs, "spectral", 5, p)
+    assert rel_l2(got, per) <= 2e-5
+
+
+@pytest.mark.parametrize("bcs", [("periodic", "zero_flux", "zero_flux"),
+                                 ("zero_flux", "periodic", "dirichlet")])
+def test_periodic_yz_under_cosine_x_diagnostics_and_adjoint(evx_gpu, bcs):
+    """Mass, energy and one adjoint step on the complex-column layout against the oracle."""
+    from oracle import adjoint as oadj
+    shape = (16, 24, 32)
+    p = OParams(dt=0.5, M=0.8, kappa=1.3, A=2.0)
+    c0 = quench_field(shape, 0.1, 0.3, seed=69)
+    plan = evx_gpu.Plan(shape, bcs, "stencil7", ops=evx_gpu.OP_ADJOINT)
+    c = torch.from_numpy(c0).cuda()
+    d = plan.diagnostics(c, evx_gpu.CHParams(dt=p.dt, M=p.M, kappa=p.kappa, A=p.A)).cpu().numpy()
+    c64 = c0.astype(np.float64)
+    assert abs(d[0] - ch.mass(c64)) <= 1e-6 * np.sum(np.abs(c64))
+    assert abs(d[1] / ch.energy(c64, p, bcs, "stencil7") - 1) <= 1e-6
+    lam0 = quench_field(shape, 0.0, 1.0, seed=70)
+    c1 = ch.ch_step(c64, p, bcs, "stencil7")
+    target = c1 - lam0.astype(np.float64) / 2          # so that dL/dc^1 = lam0
+    _, ref_lam, ref_dk, ref_dM = oadj.adjoint_gradients(c0, target, 1, p, bcs, "stencil7")
+    lam = torch.from_numpy(lam0).cuda()
+    dk = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dM = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan.adjoint_step(c, lam, evx_gpu.CHParams(dt=p.dt, M=p.M, kappa=p.kappa, A=p.A), dk, dM)
+    torch.cuda.synchronize()
+    assert rel_l2(lam.cpu().numpy(), ref_lam) <= 1e-5
+    assert abs(dk.item() / ref_dk - 1) <= 1e-5 and abs(dM.item() / ref_dM - 1) <= 1e-5
