@@ -22,8 +22,10 @@ What it computes (paper, Appendix "Semi-implicit timestepping" and "Phase transf
     with the discrete Laplacian L that T diagonalises.
 
 T is the 3D DFT (periodic), the separable DCT-II (zero flux on a cell-centred grid, where the
-update has homogeneous Neumann data) or the separable DST-II (Dirichlet: c and its even
-derivatives vanish at the outer cell faces).  The appendix notes that the update inherits
+update has homogeneous Neumann data), the separable DST-II (Dirichlet: c and its even
+derivatives vanish at the outer cell faces) or the separable DCT-I (zero flux on a vertex-centred
+grid, "zero_flux_vertex": n points x_j = j dx including both boundary vertices, mirrored about
+them).  The appendix notes that the update inherits
 homogeneous boundary data, which is what makes a fast transform applicable.  K2 is the eigenvalue of -L: k^2 for the
 spectral Laplacian or (4/dx^2) sin^2(k dx/2) for the 7-point stencil, summed over the three axes.
 
@@ -90,7 +92,9 @@ def axis_k2(n: int, dx: float, bc: str, scheme: str) -> np.ndarray:
 
     periodic:  k = 2 pi m' / (n dx), m' = m for m <= n/2 else m - n;
     zero flux: k = pi m / (n dx), m = 0..n-1 (cosine modes of the cell-centred grid);
-    dirichlet: k = pi m / (n dx), m = 1..n (sine modes: zero at the outer cell faces).
+    dirichlet: k = pi m / (n dx), m = 1..n (sine modes: zero at the outer cell faces);
+    zero_flux_vertex: k = pi m / ((n - 1) dx), m = 0..n-1 (cosine modes of the vertex grid, whose
+    n points span (n - 1) dx).
     spectral:  k^2;   stencil7: (4 / dx^2) sin^2(k dx / 2), the symbol of the 3-point
     second difference (7 points in 3D).
     """
@@ -102,6 +106,8 @@ def axis_k2(n: int, dx: float, bc: str, scheme: str) -> np.ndarray:
         k = np.pi * m / (n * dx)
     elif bc == "dirichlet":
         k = np.pi * (m + 1.0) / (n * dx)
+    elif bc == "zero_flux_vertex":
+        k = np.pi * m / ((n - 1) * dx)
     else:
         raise ValueError(f"unknown bc {bc!r}")
     if scheme == "spectral":
@@ -118,7 +124,8 @@ def axis_bcs(bc):
     if isinstance(bc, str):
         return (bc, bc, bc)
     bcs = tuple(bc)
-    if len(bcs) != 3 or any(b not in ("periodic", "zero_flux", "dirichlet") for b in bcs):
+    if len(bcs) != 3 or any(b not in ("periodic", "zero_flux", "dirichlet", "zero_flux_vertex")
+                            for b in bcs):
         raise ValueError(f"bad per-axis bc {bc!r}")
     return bcs
 
@@ -135,11 +142,13 @@ def k2_grid(shape, dx: float, bc, scheme: str) -> np.ndarray:
 def T(c, bc: str):
     """Forward transform, unnormalised: full complex 3D DFT (periodic), 3D DCT-II (zero flux) or
     3D DST-II (Dirichlet)."""
-    if not isinstance(bc, str):  # per-axis DFT / DCT-II / DST-II
+    if not isinstance(bc, str):  # per-axis DFT / DCT-II / DST-II / DCT-I
         out = np.asarray(c)
         for ax, b in enumerate(axis_bcs(bc)):
             if b == "periodic":
                 out = sfft.fft(out, axis=ax, workers=WORKERS)
+            elif b == "zero_flux_vertex":
+                out = sfft.dct(out, type=1, axis=ax, workers=WORKERS)
             else:
                 f = sfft.dst if b == "dirichlet" else sfft.dct
                 out = f(out, type=2, axis=ax, workers=WORKERS)
@@ -148,6 +157,8 @@ def T(c, bc: str):
         return sfft.fftn(c, workers=WORKERS)
     if bc == "dirichlet":
         return sfft.dstn(c, type=2, workers=WORKERS)
+    if bc == "zero_flux_vertex":
+        return sfft.dctn(c, type=1, workers=WORKERS)
     return sfft.dctn(c, type=2, workers=WORKERS)
 
 
@@ -162,12 +173,16 @@ def Tinv(C, bc: str, keep_complex: bool = False):
         for ax, b in enumerate(axis_bcs(bc)):
             if b == "periodic":
                 out = sfft.ifft(out, axis=ax, workers=WORKERS)
+            elif b == "zero_flux_vertex":
+                out = sfft.idct(out, type=1, axis=ax, workers=WORKERS)
             else:
                 f = sfft.idst if b == "dirichlet" else sfft.idct
                 out = f(out, type=2, axis=ax, workers=WORKERS)
         return out if (keep_complex or not np.iscomplexobj(out)) else out.real
     if bc == "dirichlet":
         return sfft.idstn(C, type=2, workers=WORKERS)
+    if bc == "zero_flux_vertex":
+        return sfft.idctn(C, type=1, workers=WORKERS)
     return sfft.idctn(C, type=2, workers=WORKERS)
 
 
@@ -267,7 +282,8 @@ def ac_growth_factor(K2, cbar: float, p: CHParams, etd1: bool = False):
 def laplacian(u, dx: float, bc: str, scheme: str):
     """Discrete Laplacian L u.  stencil7: real-space 3-point second difference per axis with
     periodic wrap or, on the cell-centred grid, a mirrored ghost cell (zero flux: u_{-1} = u_0,
-    u_n = u_{n-1}; Dirichlet: u_{-1} = -u_0, u_n = -u_{n-1}, zero at the faces).  spectral:
+    u_n = u_{n-1}; Dirichlet: u_{-1} = -u_0, u_n = -u_{n-1}, zero at the faces); on the vertex
+    grid the mirror is about the boundary vertex (u_{-1} = u_1, u_n = u_{n-2}).  spectral:
     multiplier -K2 through T."""
     if scheme == "spectral":
         return Tinv(-k2_grid(u.shape, dx, bc, scheme) * T(u, bc), bc)
@@ -279,7 +295,7 @@ def laplacian(u, dx: float, bc: str, scheme: str):
         else:
             pad = [(0, 0)] * 3
             pad[ax] = (1, 1)
-            ue = np.pad(u, pad, mode="edge")
+            ue = np.pad(u, pad, mode="reflect" if bca == "zero_flux_vertex" else "edge")
             sl_up = [slice(None)] * 3
             sl_dn = [slice(None)] * 3
             sl_up[ax] = slice(2, None)

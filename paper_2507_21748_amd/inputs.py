@@ -43,7 +43,7 @@ def mode_field(shape, mean: float, delta: float, m=(1, 0, 0), bc: str = "periodi
 
     m = (mz, my, mx) integer mode numbers.  Periodic: cos(2 pi (mx x/nx + my y/ny + mz z/nz)) at
     grid points x = i dx.  Zero-flux (cell-centred): product of cos(pi m (i + 1/2) / n) over the
-    three axes.
+    three axes; zero-flux vertex-centred: product of cos(pi m i / (n - 1)).
     """
     nz, ny, nx = (int(s) for s in shape)
     iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
@@ -54,6 +54,9 @@ def mode_field(shape, mean: float, delta: float, m=(1, 0, 0), bc: str = "periodi
     elif bc == "zero_flux":
         mode = (np.cos(np.pi * mx * (ix + 0.5) / nx) * np.cos(np.pi * my * (iy + 0.5) / ny)
                 * np.cos(np.pi * mz * (iz + 0.5) / nz))
+    elif bc == "zero_flux_vertex":  # points i dx, i = 0..n-1, both ends on the boundary
+        mode = (np.cos(np.pi * mx * ix / (nx - 1)) * np.cos(np.pi * my * iy / (ny - 1))
+                * np.cos(np.pi * mz * iz / (nz - 1)))
     else:
         raise ValueError(bc)
     return (mean + delta * mode).astype(np.float32)
