@@ -546,6 +546,14 @@ def main():
         r = run_workload(evx, torch, wd, 200, 10, timing=False)
         extra["ch256_dirichlet"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
                                     "ms_per_step": r["ms_per_step"]}
+        # vertex-centred zero flux (DCT-I as the periodic transform of the even extension) on
+        # 257^3 points: 512-point y and z transforms, a 256-point complex x row
+        wv = dataclasses.replace(WORKLOADS["ch256_zeroflux"], name="ch257_vertex",
+                                 shape=(257, 257, 257), bc="zero_flux_vertex")
+        r = run_workload(evx, torch, wv, 200, 10, timing=False)
+        extra["ch257_vertex"] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
+                                 "ms_per_step": r["ms_per_step"],
+                                 "workspace_bytes": r["workspace_bytes"]}
         extra["gray_scott256"] = gray_scott_workload(evx, torch)
         extra["varmob256"] = varmob_workload(evx, torch)
         extra["reaction_diffusion256"] = rd_workload(evx, torch)

@@ -54,15 +54,22 @@ typedef enum evx_status {
   EVX_ERR_NONFINITE = 7    /* check_finite was set and the state holds a NaN or an Inf */
 } evx_status;
 
-/* Boundary conditions on the cell-centred grid.  EVX_BC_DIRICHLET: c (and its even derivatives)
- * vanish at the outer cell faces, i.e. the DST-II basis -- the homogeneous data the update
- * inherits, which the paper notes is what makes a fast transform applicable.  It runs the
- * zero-flux kernels on (-1)^(i+j+l) c (DST-II(x)[k] = DCT-II((-1)^n x)[N-1-k]) with the
- * wavenumbers in reversed order; f' is odd, so the sign cancels inside the step. */
+/* Boundary conditions (the paper's "boundary conditions x grid conventions" per axis).  On the
+ * cell-centred grid (points (j + 1/2) dx): EVX_BC_ZERO_FLUX mirrors the field about the outer
+ * faces (DCT-II); EVX_BC_DIRICHLET: c (and its even derivatives) vanish at the outer cell faces,
+ * i.e. the DST-II basis -- the homogeneous data the update inherits, which the paper notes is
+ * what makes a fast transform applicable.  It runs the zero-flux kernels on (-1)^(i+j+l) c
+ * (DST-II(x)[k] = DCT-II((-1)^n x)[N-1-k]) with the wavenumbers in reversed order; f' is odd, so
+ * the sign cancels inside the step.  EVX_BC_ZERO_FLUX_VERTEX: zero flux on a vertex-centred grid
+ * (n points j dx including both boundary vertices, the field mirrored about them; wavenumbers
+ * pi m / ((n - 1) dx)): the DCT-I, run as the periodic transform of the even extension of length
+ * 2 (n - 1), which must be a supported length (n - 1 itself for x); evx_ch_diagnostics,
+ * evx_ch_adjoint_step and evx_vm_step refuse such plans (EVX_ERR_UNSUPPORTED). */
 typedef enum evx_bc {
   EVX_BC_PERIODIC = 0,
   EVX_BC_ZERO_FLUX = 1,
-  EVX_BC_DIRICHLET = 2
+  EVX_BC_DIRICHLET = 2,
+  EVX_BC_ZERO_FLUX_VERTEX = 3
 } evx_bc;
 typedef enum evx_scheme { EVX_SCHEME_SPECTRAL = 0, EVX_SCHEME_STENCIL7 = 1 } evx_scheme;
 

@@ -22,15 +22,15 @@ void sched_forward(L& l, const Geom& g, const TablePtrs& t, const float* c, floa
                    bool fprime_first, int remap) {
   l.row(g.row_len, g.bc, fprime_first ? ROW_FWD_FP : ROW_FWD,
         x_args(g, t, nullptr, c, out, nullptr));
-  l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, out, out, remap));
-  l.col(g.nz, g.bcz, COL_FWD, z_args(g, t, out, out, nullptr, StepCoef{0, 0, 0}, remap));
+  l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, out, out, remap));
+  l.col(g.fz, g.bcz, COL_FWD, z_args(g, t, out, out, nullptr, StepCoef{0, 0, 0}, remap));
 }
 
 // Full inverse transform of a spectral buffer (consumed) into a real field.
 template <class L>
 void sched_inverse(L& l, const Geom& g, const TablePtrs& t, float2* in, float* c, int remap) {
-  l.col(g.nz, g.bcz, COL_INV, z_args(g, t, in, in, nullptr, StepCoef{0, 0, 0}, remap));
-  l.col(g.ny, g.bcy, COL_INV, y_args(g, t, in, in, remap));
+  l.col(g.fz, g.bcz, COL_INV, z_args(g, t, in, in, nullptr, StepCoef{0, 0, 0}, remap));
+  l.col(g.fy, g.bcy, COL_INV, y_args(g, t, in, in, remap));
   l.row(g.row_len, g.bc, ROW_INV, x_args(g, t, in, nullptr, nullptr, c));
 }
 
@@ -85,17 +85,17 @@ void sched_adjoint(L& l, const Geom& g, const TablePtrs& t, const float* c, floa
   l.row_batch(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, c, b.A, nullptr), rows_fwd);
   l.row(g.row_len, g.bc, ROW_FWD_FP, x_args(g, t, nullptr, c, b.B, nullptr));
   const PassBatch spec3{{b.A, b.B, b.Lm}, {b.A, b.B, b.Lm}, 3};
-  l.col_batch(g.ny, g.bcy, COL_FWD, y_args(g, t, b.A, b.A, remap), spec3);
-  l.col_batch(g.nz, g.bcz, COL_FWD, z_args(g, t, b.A, b.A, nullptr, StepCoef{0, 0, 0}, remap),
+  l.col_batch(g.fy, g.bcy, COL_FWD, y_args(g, t, b.A, b.A, remap), spec3);
+  l.col_batch(g.fz, g.bcz, COL_FWD, z_args(g, t, b.A, b.A, nullptr, StepCoef{0, 0, 0}, remap),
               spec3);
   l.spec(spec_args(g, t, b, co, 0));
   const double norm = (g.bc == BC_PERIODIC || g.xcplx) ? 1.0 / double(g.V) : 1.0;
   l.final(FinalArgs{b.partial, AUX_BLOCKS, dk, dM, norm, norm, 1, 1});
   // inverse transforms: Lm -> lam, B -> v
   const PassBatch spec2{{b.Lm, b.B, nullptr}, {b.Lm, b.B, nullptr}, 2};
-  l.col_batch(g.nz, g.bcz, COL_INV, z_args(g, t, b.Lm, b.Lm, nullptr, StepCoef{0, 0, 0}, remap),
+  l.col_batch(g.fz, g.bcz, COL_INV, z_args(g, t, b.Lm, b.Lm, nullptr, StepCoef{0, 0, 0}, remap),
               spec2);
-  l.col_batch(g.ny, g.bcy, COL_INV, y_args(g, t, b.Lm, b.Lm, remap), spec2);
+  l.col_batch(g.fy, g.bcy, COL_INV, y_args(g, t, b.Lm, b.Lm, remap), spec2);
   const PassBatch rows_inv{{b.Lm, b.B, nullptr}, {lam, b.v, nullptr}, 2};
   l.row_batch(g.row_len, g.bc, ROW_INV, x_args(g, t, b.Lm, nullptr, nullptr, lam), rows_inv);
   l.combine(CombineArgs{lam, c, b.v, g.V});
@@ -139,8 +139,8 @@ void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* 
     const PassBatch rows{{u, v, b.v, b.v2}, {U, V, RU, RV}, 4};
     l.row_batch(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, u, U, nullptr), rows);
     const PassBatch all{{U, V, RU, RV}, {U, V, RU, RV}, 4};
-    l.col_batch(g.ny, g.bcy, COL_FWD, y_args(g, t, U, U, remap), all);
-    l.col_batch(g.nz, g.bcz, COL_FWD, z_args(g, t, U, U, nullptr, StepCoef{0, 0, 0}, remap), all);
+    l.col_batch(g.fy, g.bcy, COL_FWD, y_args(g, t, U, U, remap), all);
+    l.col_batch(g.fz, g.bcz, COL_FWD, z_args(g, t, U, U, nullptr, StepCoef{0, 0, 0}, remap), all);
     GsUpdateArgs ua{};
     ua.U = U;
     ua.V = V;
@@ -161,8 +161,8 @@ void sched_gray_scott(L& l, const Geom& g, const TablePtrs& t, float* u, float* 
     ua.dt_dv = co.dt_dv;
     l.gs_update(ua);
     const PassBatch two{{U, V}, {U, V}, 2};
-    l.col_batch(g.nz, g.bcz, COL_INV, z_args(g, t, U, U, nullptr, StepCoef{0, 0, 0}, remap), two);
-    l.col_batch(g.ny, g.bcy, COL_INV, y_args(g, t, U, U, remap), two);
+    l.col_batch(g.fz, g.bcz, COL_INV, z_args(g, t, U, U, nullptr, StepCoef{0, 0, 0}, remap), two);
+    l.col_batch(g.fy, g.bcy, COL_INV, y_args(g, t, U, U, remap), two);
     const PassBatch back{{U, V}, {u, v}, 2};
     l.row_batch(g.row_len, g.bc, ROW_INV, x_args(g, t, U, nullptr, nullptr, u), back);
   }
@@ -189,9 +189,9 @@ void sched_varmob(L& l, const Geom& g, const TablePtrs& t, float* phi, const Adj
     l.vm_mu(mu);
     l.vm_rhs(rhs);
     l.row(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, b.v2, b.A, nullptr));
-    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, b.A, b.A, remap));
-    l.col(g.nz, g.bcz, COL_Z_VM, z_args(g, t, b.A, b.A, nullptr, zc, remap));
-    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, b.A, b.A, remap));
+    l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, b.A, b.A, remap));
+    l.col(g.fz, g.bcz, COL_Z_VM, z_args(g, t, b.A, b.A, nullptr, zc, remap));
+    l.col(g.fy, g.bcy, COL_INV, y_args(g, t, b.A, b.A, remap));
     l.row(g.row_len, g.bc, ROW_INV_ADD, x_args(g, t, b.A, nullptr, nullptr, phi));
   }
 }

@@ -246,17 +246,26 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
                                 evx_bc bc_z, evx_scheme scheme, double dx) {
   if (!out) return fail(EVX_ERR_ARG, "out is NULL");
   for (evx_bc b : {bc_x, bc_y, bc_z})
-    if (b != EVX_BC_PERIODIC && b != EVX_BC_ZERO_FLUX && b != EVX_BC_DIRICHLET)
+    if (b != EVX_BC_PERIODIC && b != EVX_BC_ZERO_FLUX && b != EVX_BC_DIRICHLET &&
+        b != EVX_BC_ZERO_FLUX_VERTEX)
       return fail(EVX_ERR_ARG, "bad bc %d", b);
   const evx_bc bc = bc_x;
   if (scheme != EVX_SCHEME_SPECTRAL && scheme != EVX_SCHEME_STENCIL7)
     return fail(EVX_ERR_ARG, "bad scheme %d", scheme);
   if (!(dx > 0)) return fail(EVX_ERR_ARG, "dx must be > 0");
   if (nx <= 0 || ny <= 0 || nz <= 0) return fail(EVX_ERR_ARG, "sizes must be positive");
-  if (!axis_ok(ny) || !axis_ok(nz)) return fail(EVX_ERR_SIZE, "ny=%d / nz=%d not supported", ny, nz);
+  // a vertex-centred axis of n points transforms its even extension of 2 (n - 1) points
+  auto col_ok = [](int n, evx_bc b) {
+    return b == EVX_BC_ZERO_FLUX_VERTEX ? (n >= 3 && axis_ok(2 * (n - 1))) : axis_ok(n);
+  };
+  if (!col_ok(ny, bc_y) || !col_ok(nz, bc_z))
+    return fail(EVX_ERR_SIZE, "ny=%d / nz=%d not supported", ny, nz);
   if (bc == EVX_BC_PERIODIC) {
     if (nx % 2 != 0 || !axis_ok(nx / 2))
       return fail(EVX_ERR_SIZE, "periodic nx=%d needs nx/2 in the supported list", nx);
+  } else if (bc == EVX_BC_ZERO_FLUX_VERTEX) {
+    if (nx < 3 || !axis_ok(nx - 1))
+      return fail(EVX_ERR_SIZE, "vertex-centred nx=%d needs nx - 1 in the supported list", nx);
   } else if (!axis_ok(nx)) {
     return fail(EVX_ERR_SIZE, "nx=%d not supported", nx);
   }
@@ -503,6 +512,8 @@ evx_status evx_ch_adjoint_step(evx_plan* p, const float* c_n, float* lam,
   if (!c_n || !lam || !dkappa || !dM) return fail(EVX_ERR_ARG, "NULL argument");
   if (q->integrator != EVX_INTEGRATOR_SEMI_IMPLICIT || q->model != EVX_MODEL_CAHN_HILLIARD)
     return fail(EVX_ERR_UNSUPPORTED, "the adjoint step is the semi-implicit Cahn-Hilliard step's");
+  if (p->g.vert)
+    return fail(EVX_ERR_UNSUPPORTED, "adjoint step: no vertex-centred axes");
   if (!p->has_adj)
     return fail(EVX_ERR_NOMEM, "workspace too small for the adjoint (EVX_OP_ADJOINT)");
   AdjointCoef co{coef_of(q), float(q->dt), float(q->dt * q->kappa)};
@@ -559,8 +570,9 @@ evx_status evx_vm_step(evx_plan* p, float* phi, int nsteps, const evx_vm_params*
   if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
   if (!(q->dt > 0) || !(q->D0 >= 0) || !(q->gamma0 >= 0) || !(q->eps > 0) || !(q->M0 >= 0))
     return fail(EVX_ERR_ARG, "params need dt > 0, eps > 0 and D0, gamma0, M0 >= 0");
-  if (p->g.flip != 0)
-    return fail(EVX_ERR_UNSUPPORTED, "variable-mobility step: periodic or zero-flux axes only");
+  if (p->g.flip != 0 || p->g.vert != 0)
+    return fail(EVX_ERR_UNSUPPORTED,
+                "variable-mobility step: periodic or cell-centred zero-flux axes only");
   if (!p->has_gs)
     return fail(EVX_ERR_NOMEM,
                 "workspace too small for the variable-mobility step (EVX_OP_VAR_MOBILITY)");
@@ -581,6 +593,8 @@ evx_status evx_ch_diagnostics(evx_plan* p, const float* c, const evx_ch_params* 
   if (!c || !out) return fail(EVX_ERR_ARG, "NULL argument");
   if (!p->has_diag)
     return fail(EVX_ERR_NOMEM, "workspace too small for diagnostics (EVX_OP_DIAG)");
+  if (p->g.vert)
+    return fail(EVX_ERR_UNSUPPORTED, "diagnostics: no vertex-centred axes");
   TimedLauncher l = launcher(p, s);
   sched_diagnostics(l, p->g, p->t, c, q->kappa, p->aux, out, p->remap);
   return finish(l, "diagnostics");

@@ -29,7 +29,7 @@
 
 namespace evx {
 
-enum : int { BC_PERIODIC = 0, BC_ZERO_FLUX = 1, BC_DIRICHLET = 2 };
+enum : int { BC_PERIODIC = 0, BC_ZERO_FLUX = 1, BC_DIRICHLET = 2, BC_VERTEX = 3 };
 
 // Pad rows per (group, z) slab of a spectral buffer.
 constexpr int kSpecYPad = 2;
@@ -113,6 +113,9 @@ struct ColArgs {
   long long stride_lo;     // float2 stride of o_lo
   long long stride_hi;     // float2 stride of o_hi (>= (n_lo - 1) stride_lo: offsets increase)
   int x_lo;                // 1: o_lo is the x group, 0: o_hi is
+  int vlen;                // vertex-centred axis: its data length n (the transform length is
+                           // 2(n - 1)): loads mirror point k > n - 1 to row 2(n - 1) - k, stores
+                           // keep points below n; 0 otherwise
   long long row_stride;    // float2 stride between consecutive points of the transform axis
   const float2* tw;        // exp(-2 pi i j / N), j < N
   const float2* mk;        // zero flux: exp(-i pi k / (2N)), k < N
@@ -123,7 +126,7 @@ struct ColArgs {
   float dt_m_kappa;        // dt M kappa
   float dt_m;              // dt M
   int remap;               // XCD-aware block order
-  int xcomplex;            // zero-flux z pass under a periodic x: a column is one complex x bin
+  int xcomplex;            // z pass: a column is one complex x bin (else two real x bins)
   unsigned lane_bytes;     // bytes addressable from a point's block base (col_lane_bytes)
 };
 
@@ -141,6 +144,7 @@ struct RowArgs {
   int ny;              // rows r = j + ny l (for the sign)
   int remap;           // XCD-aware block order (consecutive row blocks on one XCD)
   int xcplx;           // cosine x: spectral columns are complex, one per bin (real data)
+  int vx;              // vertex-centred x: real rows of vx = NH + 1 points, extended evenly
   float poly[4];       // ROW_FUSED_POLY: poly(c) = poly[0] + poly[1] c + poly[2] c^2 + poly[3] c^3
 };
 
@@ -306,7 +310,9 @@ inline long long col_lane_bytes(const ColArgs& a) {
   // steps of o_lo (offsets increase with o, see ColArgs)
   const long long qmax = B / 8 - 1;
   const long long cmax = qmax == 0 ? 7 : (qmax / a.n_lo + 1) * a.stride_hi + qmax * a.stride_lo + 7;
-  return (cmax + 2LL * TPS * a.row_stride + 2) * 8;
+  // a point base plus t rows, a Makhoul row shift (< 2 TPS rows), or a vertex axis's data row
+  // (< N / 2 + 1 rows) from the point-0 base: N rows cover all of them (N >= 2 TPS)
+  return (cmax + (long long)N * a.row_stride + 2) * 8;
 }
 
 template <int N>
@@ -356,6 +362,10 @@ struct ColTile {
   EVX_DEV evx_buf sres(const float2* state, int e) const {
     return evx_make_buf(state + tile * ((long long)N * B) + (long long)(TPS * e) * B,
                         unsigned(TPS * B * 8));
+  }
+  // vertex-centred axis: lane offset of data row `row` from the point-0 base
+  EVX_DEV unsigned voff(long long row_stride, int row) const {
+    return live ? lc + unsigned((long long)row * row_stride * 8) : kDeadLane;
   }
   // point t + TPS e (natural order)
   EVX_DEV evx_buf res(const float2* base, long long row_stride, int e, unsigned nbytes) const {
@@ -410,24 +420,43 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
       x[e] = evx_buf_load2(ct.template res_m<ev>(a.in, a.row_stride, nb),
                            ct.template off_m<ev>(a.row_stride));
     });
+  } else if (!zf && a.vlen) {
+    // vertex-centred axis: the even extension about both end points, point n > vlen - 1 read
+    // from data row N - n (N = 2 (vlen - 1))
+    const evx_buf r0 = ct.res(a.in, a.row_stride, 0, nb);
+    static_for<E>([&](auto e) {
+      const int n = t + TPS * decltype(e)::value;
+      x[e] = evx_buf_load2(r0, ct.voff(a.row_stride, n < a.vlen ? n : N - n));
+    });
   } else {
     static_for<E>([&](auto e) { x[e] = evx_buf_load2(ct.res(a.in, a.row_stride, e, nb), ct.lo); });
   }
+  // vertex-centred axis: keep points k < vlen (the rest of the extension mirrors them)
+  auto store_points = [&](float2* out) {
+    if (a.vlen) {
+      const evx_buf r0 = ct.res(out, a.row_stride, 0, nb);
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        evx_buf_store2(r0, k < a.vlen ? ct.voff(a.row_stride, k) : kDeadLane, x[e]);
+      });
+    } else {
+      static_for<E>([&](auto e) {
+        evx_buf_store2(ct.res(out, a.row_stride, e, nb), ct.lo, x[e]);
+      });
+    }
+  };
   float kca = 0.f, kcb = 0.f;
   if constexpr (kt) {
     const int o = ct.live ? ct.olo : 0, cc = ct.live ? ct.x : 0;
     const float ko = a.k2o[o];
-    if constexpr (zf) {
-      if (a.xcomplex) {  // both components belong to x bin cc
-        kca = a.k2c[cc] + ko;
-        kcb = kca;
-      } else {           // two real x bins per column
-        kca = a.k2c[2 * cc] + ko;
-        kcb = a.k2c[2 * cc + 1] + ko;
-      }
-    } else {
+    // Pair columns (two real x bins) occur under a cosine x whose y and z spectra stay real: a
+    // cosine z, or a vertex-centred z (periodic transform of an even extension).
+    if (a.xcomplex) {  // both components belong to x bin cc
       kca = a.k2c[cc] + ko;
       kcb = kca;
+    } else {           // two real x bins per column
+      kca = a.k2c[2 * cc] + ko;
+      kcb = a.k2c[2 * cc + 1] + ko;
     }
   }
   tws.store(twl, tid);
@@ -439,7 +468,13 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
   }
 
   if constexpr (MODE == COL_FWD) {
-    static_for<E>([&](auto e) { evx_buf_store2(ct.res(a.out, a.row_stride, e, nb), ct.lo, x[e]); });
+    if constexpr (zf) {
+      static_for<E>([&](auto e) {
+        evx_buf_store2(ct.res(a.out, a.row_stride, e, nb), ct.lo, x[e]);
+      });
+    } else {
+      store_points(a.out);
+    }
     return;
   }
 
@@ -522,9 +557,7 @@ EVX_DEV void colpass_body(const ColArgs& a, int tid, int bid, int nblk, float2* 
                        ct.template off_m<ev>(a.row_stride), x[e]);
       });
     } else {
-      static_for<E>([&](auto e) {
-        evx_buf_store2(ct.res(a.out, a.row_stride, e, nb), ct.lo, x[e]);
-      });
+      store_points(a.out);
     }
   }
 }
@@ -558,6 +591,42 @@ EVX_DEV void copy_out(float2* EVX_RESTRICT dst, long long valid, const float2* l
         dst[i] = make_float2(o.x + v.x, o.y + v.y);
       } else {
         dst[i] = lds[i];
+      }
+    }
+  });
+}
+
+// Vertex-centred x: ROWS real rows of NR = NH + 1 floats, contiguous in the field (the block's
+// slice starts at src), copied into LDS as floats; `valid` floats are in range.
+template <int COUNT, int T>
+EVX_DEV void copy_in_floats(const float* EVX_RESTRICT src, long long valid, float* lds, int tid) {
+  constexpr int IT = (COUNT + T - 1) / T;
+  float r[IT];
+  static_for<IT>([&](auto I) {
+    const int i = tid + T * decltype(I)::value;
+    r[I] = (i < COUNT && i < valid) ? src[i] : 0.f;
+  });
+  static_for<IT>([&](auto I) {
+    const int i = tid + T * decltype(I)::value;
+    if (i < COUNT) lds[i] = r[I];
+  });
+}
+
+// ... and back: row b of the block holds the 2 NH points of the extension at lds[b 2 NH + j]; the
+// first NR = NH + 1 of them are the field's row (stored, or added with ADD).
+template <int ROWS, int NH, int T, bool ADD>
+EVX_DEV void copy_out_vertex(float* EVX_RESTRICT dst, long long valid_rows, const float* lds,
+                             int tid) {
+  constexpr int NR = NH + 1, COUNT = ROWS * NR, IT = (COUNT + T - 1) / T;
+  static_for<IT>([&](auto I) {
+    const int i = tid + T * decltype(I)::value;
+    const int row = i / NR, j = i - row * NR;
+    if (i < COUNT && row < valid_rows) {
+      const float v = lds[row * 2 * NH + j];
+      if constexpr (ADD) {
+        dst[i] = dst[i] + v;
+      } else {
+        dst[i] = v;
       }
     }
   });
@@ -801,13 +870,29 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, int nblk, float2* 
     constexpr int NX = 2 * NH, W = C::SROW;
     // ---------------------------------------------------------------- input
     if constexpr (MODE == ROW_FWD || MODE == ROW_FWD_FP) {
-      // real rows, read as pairs (c[2n], c[2n+1]) into stage[b*NH + n]
-      copy_in<B * NH, T>(reinterpret_cast<const float2*>(a.in_r) + r0 * NH, (a.nrows - r0) * NH,
-                         lds, tid);
-      tws.store(twl, tid);
-      pos.store(pol, tid);
-      evx_sync();
-      static_for<E>([&](auto e) { x[e] = lds[b * NH + t + TPS * decltype(e)::value]; });
+      if (a.vx) {
+        // vertex-centred x: rows of NH + 1 points, extended evenly about both end points to the
+        // 2 NH points the real transform takes: point j > NH is point 2 NH - j
+        float* st = reinterpret_cast<float*>(lds);
+        copy_in_floats<B * (NH + 1), T>(a.in_r + r0 * (NH + 1), (a.nrows - r0) * (NH + 1), st,
+                                        tid);
+        tws.store(twl, tid);
+        pos.store(pol, tid);
+        evx_sync();
+        const float* row = st + b * (NH + 1);
+        static_for<E>([&](auto e) {
+          const int j = 2 * (t + TPS * decltype(e)::value);
+          x[e] = make_float2(row[j <= NH ? j : 2 * NH - j], row[j + 1 <= NH ? j + 1 : 2 * NH - j - 1]);
+        });
+      } else {
+        // real rows, read as pairs (c[2n], c[2n+1]) into stage[b*NH + n]
+        copy_in<B * NH, T>(reinterpret_cast<const float2*>(a.in_r) + r0 * NH,
+                           (a.nrows - r0) * NH, lds, tid);
+        tws.store(twl, tid);
+        pos.store(pol, tid);
+        evx_sync();
+        static_for<E>([&](auto e) { x[e] = lds[b * NH + t + TPS * decltype(e)::value]; });
+      }
       if (a.flip) {  // Dirichlet y / z: one sign per row
         const float sg = dirichlet_sign(r0 + b, 0, a.ny, a.flip);
         static_for<E>([&](auto e) { x[e] = cscale(x[e], sg); });
@@ -838,8 +923,12 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, int nblk, float2* 
           lds[b * NH + t + TPS * decltype(e)::value] = a.flip ? cscale(x[e], sg) : x[e];
         });
         evx_sync();
-        copy_out<B * NH, T, MODE == ROW_INV_ADD>(reinterpret_cast<float2*>(a.out_r) + r0 * NH,
-                                                 (a.nrows - r0) * NH, lds, tid);
+        if (a.vx)
+          copy_out_vertex<B, NH, T, MODE == ROW_INV_ADD>(a.out_r + r0 * (NH + 1), a.nrows - r0,
+                                                         reinterpret_cast<const float*>(lds), tid);
+        else
+          copy_out<B * NH, T, MODE == ROW_INV_ADD>(reinterpret_cast<float2*>(a.out_r) + r0 * NH,
+                                                   (a.nrows - r0) * NH, lds, tid);
         if constexpr (MODE == ROW_INV || MODE == ROW_INV_ADD) return;
         evx_sync();  // the forward transform reuses the staging area
       }

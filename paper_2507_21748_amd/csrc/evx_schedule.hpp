@@ -44,7 +44,11 @@ inline int col_block_seqs(int n) {
 }
 
 struct Geom {
-  int nx = 0, ny = 0, nz = 0;
+  int nx = 0, ny = 0, nz = 0;   // points per axis (the data)
+  int vert = 0;          // vertex-centred zero-flux axes (bit 0 x, 1 y, 2 z): the transform is the
+                         // periodic one of the even extension about the end points, length 2(n-1)
+  int nxe = 0;           // x length of the periodic transform family: nx, or 2(nx - 1) (vertex x)
+  int fy = 0, fz = 0;    // y and z transform lengths: ny, nz, or 2(n - 1) for a vertex axis
   int bc = BC_PERIODIC;  // x transform family: Dirichlet axes run the zero-flux kernels
   int bcy = BC_PERIODIC, bcz = BC_PERIODIC;  // y and z transform families
   int flip = 0;          // Dirichlet (DST-II) axes, bit 0 x, 1 y, 2 z: sign and reversed K2
@@ -61,8 +65,10 @@ struct Geom {
   long long nrows = 0;   // ny * nz
 };
 
-// Per-axis boundaries: x periodic with any y and z, or any mix of zero flux and Dirichlet (a
-// non-periodic x makes the spectral data real, which a periodic y or z transform cannot keep).
+// Per-axis boundaries: any mix of periodic, zero flux (cell- or vertex-centred) and Dirichlet.
+// A vertex-centred axis runs the periodic transform of the field's even extension about its end
+// points (length 2(n - 1): the DCT-I), so it joins the periodic transform family; its spectrum is
+// real, and the extension is formed and cut in the passes that touch real data.
 inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int scheme, double dx) {
   Geom g;
   g.nx = nx;
@@ -70,23 +76,29 @@ inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int sc
   g.nz = nz;
   g.flip = (bcx == BC_DIRICHLET ? 1 : 0) | (bcy == BC_DIRICHLET ? 2 : 0) |
            (bcz == BC_DIRICHLET ? 4 : 0);
-  const int bc = bcx == BC_PERIODIC ? BC_PERIODIC : BC_ZERO_FLUX;
+  g.vert = (bcx == BC_VERTEX ? 1 : 0) | (bcy == BC_VERTEX ? 2 : 0) | (bcz == BC_VERTEX ? 4 : 0);
+  auto family = [](int b) { return (b == BC_PERIODIC || b == BC_VERTEX) ? BC_PERIODIC : BC_ZERO_FLUX; };
+  const int bc = family(bcx);
   g.bc = bc;
-  g.bcy = bcy == BC_PERIODIC ? BC_PERIODIC : BC_ZERO_FLUX;
-  g.bcz = bcz == BC_PERIODIC ? BC_PERIODIC : BC_ZERO_FLUX;
+  g.bcy = family(bcy);
+  g.bcz = family(bcz);
+  g.nxe = (g.vert & 1) ? 2 * (nx - 1) : nx;
+  g.fy = (g.vert & 2) ? 2 * (ny - 1) : ny;
+  g.fz = (g.vert & 4) ? 2 * (nz - 1) : nz;
   g.scheme = scheme;
   g.dx = dx;
   g.V = (long long)nx * ny * nz;
-  // a cosine x keeps two real bins per float2 column, unless a periodic y or z transform follows,
-  // whose complex output needs one complex column per bin
-  g.xcplx = (bc != BC_PERIODIC && (g.bcy == BC_PERIODIC || g.bcz == BC_PERIODIC)) ? 1 : 0;
-  g.ncols = (bc == BC_PERIODIC) ? nx / 2 + 1 : (g.xcplx ? nx : nx / 2);
-  g.row_len = (bc == BC_PERIODIC) ? nx / 2 : nx;
+  // a cosine x keeps two real bins per float2 column, unless a (truly) periodic y or z transform
+  // follows, whose complex output needs one complex column per bin; a vertex y or z keeps the
+  // spectrum real, like a cosine one
+  g.xcplx = (bc != BC_PERIODIC && (bcy == BC_PERIODIC || bcz == BC_PERIODIC)) ? 1 : 0;
+  g.ncols = (bc == BC_PERIODIC) ? g.nxe / 2 + 1 : (g.xcplx ? nx : nx / 2);
+  g.row_len = (bc == BC_PERIODIC) ? g.nxe / 2 : nx;
   g.ngx = (g.ncols + 7) / 8;
   g.ypitch = ny + kSpecYPad;
   g.spec = (long long)g.ngx * nz * g.ypitch * 8;
-  const long long bz = col_block_seqs(nz), nseq_z = (long long)g.ngx * ny * 8;
-  g.state = bz > 0 ? (nseq_z + bz - 1) / bz * bz * nz : g.spec;
+  const long long bz = col_block_seqs(g.fz), nseq_z = (long long)g.ngx * ny * 8;
+  g.state = bz > 0 ? (nseq_z + bz - 1) / bz * bz * g.fz : g.spec;
   g.nrows = (long long)ny * nz;
   return g;
 }
@@ -148,23 +160,25 @@ inline std::vector<float> k2_table(int count, int n, int bc, int scheme, double 
 inline HostTables make_tables(const Geom& g) {
   HostTables h;
   h.tw_x = twiddles(g.row_len);
-  h.tw_y = twiddles(g.ny);
-  h.tw_z = twiddles(g.nz);
+  h.tw_y = twiddles(g.fy);
+  h.tw_z = twiddles(g.fz);
   if (g.bc == BC_PERIODIC) {
-    h.post_x.resize(g.nx / 2 + 1);
-    for (int k = 0; k <= g.nx / 2; ++k) {
-      const double a = -2.0 * M_PI * double(k) / double(g.nx);
+    // a vertex x: the periodic tables of its extension (length nxe), whose wavenumbers
+    // 2 pi m / (nxe dx) are the cosine modes pi m / ((nx - 1) dx)
+    h.post_x.resize(g.nxe / 2 + 1);
+    for (int k = 0; k <= g.nxe / 2; ++k) {
+      const double a = -2.0 * M_PI * double(k) / double(g.nxe);
       h.post_x[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
     }
-    h.k2_x = k2_table(g.nx / 2 + 1, g.nx, g.bc, g.scheme, g.dx);
+    h.k2_x = k2_table(g.nxe / 2 + 1, g.nxe, g.bc, g.scheme, g.dx);
   } else {
     h.post_x = makhoul_twiddles(g.nx);
     h.k2_x = k2_table(g.nx, g.nx, g.bc, g.scheme, g.dx, (g.flip & 1) != 0);
   }
   if (g.bcy != BC_PERIODIC) h.mk_y = makhoul_twiddles(g.ny);
   if (g.bcz != BC_PERIODIC) h.mk_z = makhoul_twiddles(g.nz);
-  h.k2_y = k2_table(g.ny, g.ny, g.bcy, g.scheme, g.dx, (g.flip & 2) != 0);
-  h.k2_z = k2_table(g.nz, g.nz, g.bcz, g.scheme, g.dx, (g.flip & 4) != 0);
+  h.k2_y = k2_table(g.fy, g.fy, g.bcy, g.scheme, g.dx, (g.flip & 2) != 0);
+  h.k2_z = k2_table(g.fz, g.fz, g.bcz, g.scheme, g.dx, (g.flip & 4) != 0);
   return h;
 }
 
@@ -196,6 +210,7 @@ inline ColArgs y_args(const Geom& g, const TablePtrs& t, const float2* in, float
   a.stride_hi = (long long)g.nz * g.ypitch * 8;
   a.x_lo = 0;
   a.row_stride = 8;
+  a.vlen = (g.vert & 2) ? g.ny : 0;
   a.tw = t.tw_y;
   a.mk = t.mk_y;
   a.remap = remap;
@@ -216,6 +231,7 @@ inline ColArgs z_args(const Geom& g, const TablePtrs& t, const float2* in, float
   a.stride_hi = (long long)g.nz * g.ypitch * 8;
   a.x_lo = 0;
   a.row_stride = (long long)g.ypitch * 8;
+  a.vlen = (g.vert & 4) ? g.nz : 0;
   a.tw = t.tw_z;
   a.mk = t.mk_z;
   a.k2c = t.k2_x;
@@ -241,12 +257,17 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   a.nrows = g.nrows;
   a.tw = t.tw_x;
   a.post = t.post_x;
-  // inverse normalisation: 1/n per periodic axis, 1/(2n) per cosine (DCT-III of DCT-II) axis
-  const int ncos = (g.bc != BC_PERIODIC) + (g.bcy != BC_PERIODIC) + (g.bcz != BC_PERIODIC);
-  a.scale = float(1.0 / (double(1 << ncos) * double(g.V)));
+  // inverse normalisation: 1/n per periodic axis, 1/(2n) per cosine (DCT-III of DCT-II) axis,
+  // 1/(2(n - 1)) per vertex axis (the periodic length of its extension)
+  auto len = [](int n, int family, bool vertex) {
+    return vertex ? 2.0 * (n - 1) : (family == BC_PERIODIC ? double(n) : 2.0 * n);
+  };
+  a.scale = float(1.0 / (len(g.nx, g.bc, g.vert & 1) * len(g.ny, g.bcy, g.vert & 2) *
+                         len(g.nz, g.bcz, g.vert & 4)));
   a.flip = g.flip;
   a.ny = g.ny;
   a.remap = 1;
+  a.vx = (g.vert & 1) ? g.nx : 0;
   return a;
 }
 
@@ -257,8 +278,8 @@ template <class L>
 void sched_begin(L& l, const Geom& g, const TablePtrs& t, const float* c, float2* S, float2* W,
                  int remap) {
   l.row(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, c, W, nullptr));
-  l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
-  l.col(g.nz, g.bcz, COL_Z_INIT, z_args(g, t, W, W, S, StepCoef{0, 0, 0}, remap));
+  l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+  l.col(g.fz, g.bcz, COL_Z_INIT, z_args(g, t, W, W, S, StepCoef{0, 0, 0}, remap));
 }
 
 // nsteps steps; W must hold F_z^{-1} S on entry and holds it again on exit.
@@ -266,10 +287,10 @@ template <class L>
 void sched_advance(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, StepCoef c,
                    int nsteps, int remap, int zmode = COL_Z_UPDATE) {
   for (int n = 0; n < nsteps; ++n) {
-    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
+    l.col(g.fy, g.bcy, COL_INV, y_args(g, t, W, W, remap));
     l.row(g.row_len, g.bc, ROW_FUSED, x_args(g, t, W, nullptr, W, nullptr));
-    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
-    l.col(g.nz, g.bcz, zmode, z_args(g, t, W, W, S, c, remap));
+    l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.fz, g.bcz, zmode, z_args(g, t, W, W, S, c, remap));
   }
 }
 
@@ -282,10 +303,10 @@ void sched_advance_rd(L& l, const Geom& g, const TablePtrs& t, float2* S, float2
   RowArgs xa = x_args(g, t, W, nullptr, W, nullptr);
   for (int k = 0; k < 4; ++k) xa.poly[k] = poly[k];
   for (int n = 0; n < nsteps; ++n) {
-    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
+    l.col(g.fy, g.bcy, COL_INV, y_args(g, t, W, W, remap));
     l.row(g.row_len, g.bc, ROW_FUSED_POLY, xa);
-    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
-    l.col(g.nz, g.bcz, COL_Z_AC, z_args(g, t, W, W, S, c, remap));
+    l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.fz, g.bcz, COL_Z_AC, z_args(g, t, W, W, S, c, remap));
   }
 }
 
@@ -295,24 +316,24 @@ template <class L>
 void sched_advance_record(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W,
                           StepCoef c, int nsteps, int remap, int zmode, float* traj) {
   for (int n = 0; n < nsteps; ++n) {
-    l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
+    l.col(g.fy, g.bcy, COL_INV, y_args(g, t, W, W, remap));
     l.row(g.row_len, g.bc, ROW_FUSED_REC, x_args(g, t, W, nullptr, W, traj + (long long)n * g.V));
-    l.col(g.ny, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
-    l.col(g.nz, g.bcz, zmode, z_args(g, t, W, W, S, c, remap));
+    l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    l.col(g.fz, g.bcz, zmode, z_args(g, t, W, W, S, c, remap));
   }
 }
 
 // Real field from W = F_z^{-1} S (consumes W).
 template <class L>
 void sched_end(L& l, const Geom& g, const TablePtrs& t, float* c, float2* W, int remap) {
-  l.col(g.ny, g.bcy, COL_INV, y_args(g, t, W, W, remap));
+  l.col(g.fy, g.bcy, COL_INV, y_args(g, t, W, W, remap));
   l.row(g.row_len, g.bc, ROW_INV, x_args(g, t, W, nullptr, nullptr, c));
 }
 
 // W <- F_z^{-1} S (restores the loop-entry buffer from the state).
 template <class L>
 void sched_restore(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, int remap) {
-  l.col(g.nz, g.bcz, COL_Z_INV_STATE, z_args(g, t, nullptr, W, S, StepCoef{0, 0, 0}, remap));
+  l.col(g.fz, g.bcz, COL_Z_INV_STATE, z_args(g, t, nullptr, W, S, StepCoef{0, 0, 0}, remap));
 }
 
 }  // namespace evx

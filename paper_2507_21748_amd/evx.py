@@ -18,7 +18,7 @@ __all__ = ["EvxError", "load", "lib_path", "CHParams", "Plan", "BC", "SCHEME", "
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-BC = {"periodic": 0, "zero_flux": 1, "dirichlet": 2}
+BC = {"periodic": 0, "zero_flux": 1, "dirichlet": 2, "zero_flux_vertex": 3}
 SCHEME = {"spectral": 0, "stencil7": 1}
 
 OP_STEP, OP_DIAG, OP_ADJOINT, OP_GRAY_SCOTT, OP_VAR_MOBILITY = 1, 2, 4, 8, 16
