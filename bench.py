@@ -217,9 +217,11 @@ def pass_bytes(shape, bc):
     return [2 * spec, 2 * spec, 2 * spec, 4 * spec]
 
 
-def run_workload(evx, torch, w, steps, warmup, timing=True, integrator=0, model=0):
+def run_workload(evx, torch, w, steps, warmup, timing=True, integrator=0, model=0, graph=None):
     from paper_2507_21748_amd.inputs import quench_field
     plan = evx.Plan(w.shape, w.bc, w.scheme, dx=w.dx)
+    if graph is not None:
+        plan.set_step_graph(graph)
     prm = evx.CHParams(dt=w.dt, M=w.M, kappa=w.kappa, A=w.A, integrator=integrator, model=model)
     c = torch.from_numpy(quench_field(w.shape, w.mean, w.amp, w.seed)).cuda()
     plan.begin(c)
@@ -525,8 +527,12 @@ def main():
             r = run_workload(evx, torch, WORKLOADS[name], 200, 10, timing=False)
             rp = run_workload(evx, torch, WORKLOADS[name], 50, 5, timing=True)
             wb = sum(pass_bytes(WORKLOADS[name].shape, WORKLOADS[name].bc))
+            # the same loop with every kernel launched individually (the default replays
+            # captured chunks of 8 steps on grids of at most 2^22 voxels)
+            re = run_workload(evx, torch, WORKLOADS[name], 200, 10, timing=False, graph=0)
             extra[name] = {"voxel_steps_per_s": r["voxel_steps_per_s"],
                            "ms_per_step": r["ms_per_step"],
+                           "ms_per_step_individual_launches": re["ms_per_step"],
                            "step_effective_gbs": wb * r["voxel_steps_per_s"]
                            / WORKLOADS[name].voxels / 1e9,
                            "passes": {k: v["avg_ms"] for k, v in rp["passes"].items()}}

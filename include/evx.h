@@ -307,6 +307,22 @@ evx_status evx_ch_distance(evx_plan* plan, const float* a, const float* b, doubl
 evx_status evx_plan_enable_pass_timing(evx_plan* plan, int on);
 evx_status evx_plan_read_pass_times(evx_plan* plan, double ms[4], long long counts[4]);
 
+/* Launch mode of the time loop of evx_ch_advance (and evx_ch_step, which calls it): the
+ * semi-implicit step of the Appendix, "Semi-implicit timestepping", repeated.  It changes how the
+ * kernels are issued, not what they compute.
+ *   steps > 0: whole chunks of `steps` time steps run as one HIP graph, captured once per plan,
+ *     parameter set and workspace and replayed on the caller's stream; leftover steps are
+ *     launched kernel by kernel.
+ *   steps = 0: every kernel is launched individually.
+ *   steps = -1 (default): chunks of 8 steps on grids of at most 2^22 voxels, where the four
+ *     launches of a step are a sizeable part of its time; individual launches above.
+ * The kernels and their arguments are the same in every mode, so results are bitwise identical.
+ * Pass timing, and a caller's stream that is itself being captured, use individual launches.
+ * The graph holds the plan's workspace addresses: evx_plan_set_workspace discards it.  The first
+ * call with new parameters captures and instantiates a graph (host time, no device work).
+ * EVX_ERR_ARG for steps < -1. */
+evx_status evx_plan_set_step_graph(evx_plan* plan, int steps);
+
 /* Block-order option: 1 (default) places consecutive column tiles on the same XCD. */
 evx_status evx_plan_set_xcd_remap(evx_plan* plan, int on);
 

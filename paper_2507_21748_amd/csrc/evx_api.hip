@@ -82,6 +82,14 @@ struct evx_plan {
   bool begun = false;     // S holds a state
   bool w_valid = false;   // W holds F_z^{-1} S
   int remap = 1;
+  // Step loop as captured chunks (evx_plan_set_step_graph): -1 automatic, 0 off, k > 0 chunks of
+  // k steps.  gexec replays sched_advance over k steps for the key (coefficients, z mode, remap)
+  // it was captured with, on this plan's S and W.
+  int graph_mode = -1;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int gexec_chunk = 0, gexec_zmode = -1, gexec_remap = -1;
+  StepCoef gexec_coef{};
   // pass timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -196,6 +204,88 @@ TimedLauncher launcher(evx_plan* p, void* s) {
 }
 
 bool axis_ok(int n) { return fft_len_supported(n); }
+
+// Automatic step-loop capture: grids of at most this many voxels (where the four launches of a
+// step cost a sizeable part of its time), in chunks of kAutoGraphSteps steps.
+constexpr long long kAutoGraphVoxels = 1LL << 22;
+constexpr int kAutoGraphSteps = 8;
+
+int graph_chunk(const evx_plan* p) {
+  if (p->graph_mode >= 0) return p->graph_mode;
+  return p->g.V <= kAutoGraphVoxels ? kAutoGraphSteps : 0;
+}
+
+void drop_graph(evx_plan* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  p->gexec = nullptr;
+  p->gexec_chunk = 0;
+}
+
+// The captured chunk of k steps for these coefficients and z mode (captured now if the cached one
+// has another key).  The capture runs on the plan's own stream; nothing executes during it.
+evx_status step_graph(evx_plan* p, const StepCoef& c, int zmode, int k) {
+  if (p->gexec && p->gexec_chunk == k && p->gexec_zmode == zmode && p->gexec_remap == p->remap &&
+      std::memcmp(&p->gexec_coef, &c, sizeof(StepCoef)) == 0)
+    return EVX_OK;
+  drop_graph(p);
+  hipError_t e;
+  if (!p->cap_stream) {
+    e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      p->cap_stream = nullptr;
+      return hip_fail(e, "capture stream");
+    }
+  }
+  e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  HipLauncher l;
+  l.stream = p->cap_stream;
+  sched_advance(l, p->g, p->t, p->S, p->W, c, k, p->remap, zmode);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->cap_stream, &graph);  // ends the capture whatever happened inside
+  if (l.bad_len || l.err != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (l.bad_len) return fail(EVX_ERR_SIZE, "step graph: transform length has no kernel");
+    return hip_fail(l.err != hipSuccess ? l.err : e, "step graph capture");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  p->gexec = exec;
+  p->gexec_chunk = k;
+  p->gexec_zmode = zmode;
+  p->gexec_remap = p->remap;
+  p->gexec_coef = c;
+  return EVX_OK;
+}
+
+// nsteps steps of the stepper on the plan's S and W: whole chunks as graph replays where the
+// plan's mode asks for them, the rest (and everything under pass timing or inside a caller's own
+// capture) as individual launches.  Either way the same kernels run with the same arguments.
+evx_status run_steps(evx_plan* p, int nsteps, const StepCoef& c, int zmode, void* s,
+                     const char* what) {
+  hipStream_t st = static_cast<hipStream_t>(s);
+  int k = p->timing ? 0 : graph_chunk(p);
+  if (k > 0 && nsteps >= k) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) k = 0;
+  }
+  int rest = nsteps;
+  if (k > 0 && nsteps >= k) {
+    const evx_status r = step_graph(p, c, zmode, k);
+    if (r != EVX_OK) return r;
+    for (; rest >= k; rest -= k) {
+      const hipError_t e = hipGraphLaunch(p->gexec, st);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+  }
+  TimedLauncher l = launcher(p, s);
+  sched_advance(l, p->g, p->t, p->S, p->W, c, rest, p->remap, zmode);
+  return finish(l, what);
+}
 
 // The optional failure check after a batch of steps: scan the work buffer W (live columns) for
 // NaN / Inf, then synchronise and OR the per-block flags on the host.
@@ -334,6 +424,8 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
 evx_status evx_plan_destroy(evx_plan* p) {
   if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
   for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
+  drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->tables) (void)hipFree(p->tables);
   delete p;
   return EVX_OK;
@@ -357,6 +449,7 @@ evx_status evx_plan_set_workspace(evx_plan* p, void* dev, size_t bytes) {
     return fail(EVX_ERR_ARG, "workspace must be 256-byte aligned");
   if (bytes < ws_step(p->g))
     return fail(EVX_ERR_NOMEM, "workspace of %zu bytes, need %zu", bytes, ws_step(p->g));
+  drop_graph(p);  // captured on the previous workspace's buffers
   p->ws = static_cast<float2*>(dev);
   p->ws_bytes = bytes;
   unsigned char* base = static_cast<unsigned char*>(dev);
@@ -425,9 +518,7 @@ evx_status evx_ch_advance(evx_plan* p, int nsteps, const evx_ch_params* q, void*
   if (!p->w_valid) {
     if ((st = evx_ch_restore(p, s)) != EVX_OK) return st;
   }
-  TimedLauncher l = launcher(p, s);
-  sched_advance(l, p->g, p->t, p->S, p->W, coef_of(q), nsteps, p->remap, zmode_of(q));
-  st = finish(l, "advance");
+  st = run_steps(p, nsteps, coef_of(q), zmode_of(q), s, "advance");
   if (st == EVX_OK && q->check_finite) st = check_state_finite(p, p->W, s);
   return st;
 }
@@ -634,6 +725,13 @@ evx_status evx_plan_read_pass_times(evx_plan* p, double ms[4], long long counts[
   }
   p->ev_used.clear();
   p->ev_next = 0;
+  return EVX_OK;
+}
+
+evx_status evx_plan_set_step_graph(evx_plan* p, int steps) {
+  if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
+  if (steps < -1) return fail(EVX_ERR_ARG, "step graph chunk %d (need -1, 0 or > 0)", steps);
+  p->graph_mode = steps;
   return EVX_OK;
 }
 

@@ -65,15 +65,13 @@ EVX_HD long long spec_row_offset(const SpecGeom& s, long long r) {
   return z * s.zstride + (r - z * s.ny) * 8;
 }
 
-// The same for row (z0, y0) + j, j small: no division.
+// The same for row (z0, y0) + j (0 <= y0 < ny, j >= 0, y0 + j < 2^31), without a branch: an
+// unsigned division.  (A carry loop would be a divergent region, into which the compiler sinks the
+// loads that use the offset, each then waited for before the region ends.)
 EVX_HD long long spec_row_offset_from(const SpecGeom& s, long long z0, int y0, int j) {
-  int y = y0 + j;
-  long long z = z0;
-  while (y >= s.ny) {
-    y -= s.ny;
-    ++z;
-  }
-  return z * s.zstride + (long long)y * 8;
+  const unsigned y = unsigned(y0 + j), ny = unsigned(s.ny);
+  const unsigned dz = y / ny;
+  return (z0 + dz) * s.zstride + (long long)(y - dz * ny) * 8;
 }
 
 // column (y or z) pass modes
@@ -225,6 +223,23 @@ struct ColCfg {
   static constexpr int LDS = K2 + (N + 1) / 2;  // float2 slots
 };
 
+// src[i] if ok, else zero, with the load outside any branch: a load inside a divergent branch is
+// waited for before the branch joins, which would make a lane's loads one round trip each.  The
+// address is clamped to element 0 (which every caller guarantees valid) when ok is false, and the
+// value is cleared with a bit mask rather than a select (the compiler turns a select of a loaded
+// value into a branch around the load).
+EVX_DEV float evx_keep(float v, unsigned mask) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, v) & mask);
+}
+EVX_DEV float2 load_or_zero(const float2* EVX_RESTRICT src, long long i, bool ok) {
+  const float2 v = src[ok ? i : 0];
+  const unsigned m = ok ? ~0u : 0u;
+  return make_float2(evx_keep(v.x, m), evx_keep(v.y, m));
+}
+EVX_DEV float load_or_zero(const float* EVX_RESTRICT src, long long i, bool ok) {
+  return evx_keep(src[ok ? i : 0], ok ? ~0u : 0u);
+}
+
 // A block's copy of a small constant table (COUNT entries) staged in LDS: every lane issues its
 // table loads before the data loads (load) and writes them to LDS after (store), so the table
 // latency overlaps the data latency.  Readers come after a barrier.
@@ -235,7 +250,7 @@ struct TableStage {
   EVX_DEV void load(const V* EVX_RESTRICT src, int tid) {
     static_for<IT>([&](auto I) {
       const int i = tid + T * decltype(I)::value;
-      if (i < COUNT) r[I] = src[i];
+      r[I] = src[i < COUNT ? i : 0];
     });
   }
   EVX_DEV void store(V* dst, int tid) const {
@@ -572,7 +587,7 @@ EVX_DEV void copy_in(const float2* EVX_RESTRICT src, long long valid, float2* ld
   float2 r[IT];
   static_for<IT>([&](auto I) {
     const int i = tid + T * decltype(I)::value;
-    r[I] = (i < COUNT && i < valid) ? src[i] : make_float2(0.f, 0.f);
+    r[I] = load_or_zero(src, i, i < COUNT && i < valid);
   });
   static_for<IT>([&](auto I) {
     const int i = tid + T * decltype(I)::value;
@@ -604,7 +619,7 @@ EVX_DEV void copy_in_floats(const float* EVX_RESTRICT src, long long valid, floa
   float r[IT];
   static_for<IT>([&](auto I) {
     const int i = tid + T * decltype(I)::value;
-    r[I] = (i < COUNT && i < valid) ? src[i] : 0.f;
+    r[I] = load_or_zero(src, i, i < COUNT && i < valid);
   });
   static_for<IT>([&](auto I) {
     const int i = tid + T * decltype(I)::value;
@@ -644,7 +659,7 @@ EVX_DEV void rows_in(const float2* EVX_RESTRICT src, long long valid_rows, float
   float2 r[IT];
   static_for<IT>([&](auto I) {
     const int c = c0 + TR * decltype(I)::value;
-    r[I] = (ok && c < NLIVE) ? src[row * P + c] : make_float2(0.f, 0.f);
+    r[I] = load_or_zero(src, (long long)row * P + c, ok && c < NLIVE);
   });
   static_for<IT>([&](auto I) {
     const int c = c0 + TR * decltype(I)::value;
@@ -757,8 +772,7 @@ EVX_DEV void spec_rows_in(const float2* EVX_RESTRICT src, const SpecGeom& sg, lo
     const int g = f / RC::PER;
     const int row = (f >> 3) % ROWS;
     const bool ok = f < RC::TOT && row < valid_rows && g * 8 + c < NL;
-    r[I] = ok ? src[g * sg.xstride + spec_row_offset_from(sg, z0, y0, row) + c]
-              : make_float2(0.f, 0.f);
+    r[I] = load_or_zero(src, g * sg.xstride + spec_row_offset_from(sg, z0, y0, row) + c, ok);
   });
   static_for<IT>([&](auto I) {
     const int f = tid + T * decltype(I)::value;

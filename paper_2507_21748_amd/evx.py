@@ -151,6 +151,7 @@ _PROTOS = {
     "evx_plan_read_pass_times": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_longlong)],
     "evx_plan_set_xcd_remap": [ctypes.c_void_p, ctypes.c_int],
+    "evx_plan_set_step_graph": [ctypes.c_void_p, ctypes.c_int],
     "evx_ch_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_void_p],
@@ -237,6 +238,18 @@ class Plan:
         _check(lib.evx_plan_set_workspace(h, ctypes.c_void_p(base + self._ws_off), nb.value),
                "evx_plan_set_workspace")
         self.workspace_bytes = nb.value
+
+    def set_workspace(self, buf: torch.Tensor):
+        """Use the uint8 device tensor buf (at least workspace_bytes + 255 bytes) as the plan's
+        workspace; the plan keeps a reference.  Begin or restore a state afterwards."""
+        if buf.dtype != torch.uint8 or buf.device != self.device or not buf.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor on the plan's device")
+        off = (-buf.data_ptr()) % 256
+        if buf.numel() < off + self.workspace_bytes:
+            raise ValueError(f"workspace needs {self.workspace_bytes} bytes after alignment")
+        _check(_LIB.evx_plan_set_workspace(self._h, ctypes.c_void_p(buf.data_ptr() + off),
+                                           self.workspace_bytes), "evx_plan_set_workspace")
+        self.workspace, self._ws_off = buf, off
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -362,3 +375,8 @@ class Plan:
 
     def set_xcd_remap(self, on: bool):
         _check(_LIB.evx_plan_set_xcd_remap(self._h, int(bool(on))), "evx_plan_set_xcd_remap")
+
+    def set_step_graph(self, steps: int):
+        """Step-loop launch mode: chunks of `steps` steps replayed as one HIP graph (> 0), every
+        kernel launched individually (0), or automatic (-1, the default)."""
+        _check(_LIB.evx_plan_set_step_graph(self._h, int(steps)), "evx_plan_set_step_graph")

@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2507_21748_amd", "csrc")
 MAIN = os.path.join(ROOT, "tests", "emu", "emu_main.cpp")
 OUT = os.path.join(ROOT, "_build", "emu")
-SIZES = "X(8) X(12) X(16) X(20) X(24) X(48) X(96)"
+SIZES = "X(8) X(12) X(16) X(20) X(24) X(48) X(64) X(96)"
 SAN = {"asan": "-fsanitize=address", "tsan": "-fsanitize=thread"}
 
 
@@ -92,6 +92,9 @@ CASES = [
     ((96, 8, 16), "periodic", "spectral", 1),     # three-stage 96-point plan along z
     ((8, 48, 96), "zero_flux", "stencil7", 1),
     ((8, 8, 192), "periodic", "stencil7", 1),     # 96-point packed real rows
+    ((64, 12, 16), "periodic", "spectral", 2),    # 64-point plan (4 points per lane) along z
+    ((8, 12, 64), "zero_flux", "stencil7", 2),    # ... as the zero-flux row
+    ((8, 12, 128), "periodic", "spectral", -2),   # ... as the periodic row (nx/2 = 64), resume
 ]
 
 
