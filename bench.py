@@ -262,8 +262,9 @@ def run_workload(evx, torch, w, steps, warmup, timing=True, integrator=0, model=
 
 def adjoint_workload(evx, torch, w, steps: int = 200, every: int = 20):
     """The inverse-problem gradient: an nsteps rollout with spectral checkpoints every `every`
-    steps, then the backward sweep of hand-written adjoint steps (gradients for c0, kappa, M).
-    Returns wall times of the forward and backward halves."""
+    steps (every = 0: every state recorded in the forward pass), then the backward sweep of
+    hand-written adjoint steps (gradients for c0, kappa, M).  Returns wall times of the forward
+    and backward halves."""
     from paper_2507_21748_amd.autograd import ch_rollout
     from paper_2507_21748_amd.inputs import quench_field
     plan = evx.Plan(w.shape, w.bc, w.scheme, dx=w.dx, ops=evx.OP_STEP | evx.OP_ADJOINT)
@@ -482,7 +483,9 @@ def main():
         return
     if args.extra_only == "inverse128":
         print(json.dumps({"inverse128_gradient":
-                          adjoint_workload(evx, torch, WORKLOADS["inverse128"])}))
+                          adjoint_workload(evx, torch, WORKLOADS["inverse128"]),
+                          "inverse128_gradient_stored":
+                          adjoint_workload(evx, torch, WORKLOADS["inverse128"], every=0)}))
         return
     w = WORKLOADS[args.workload]
     probe = copy_probe(torch, args.copy_probe_gib) if args.copy_probe_gib > 0 else None
@@ -564,6 +567,9 @@ def main():
         extra["varmob256"] = varmob_workload(evx, torch)
         extra["reaction_diffusion256"] = rd_workload(evx, torch)
         extra["inverse128_gradient"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"])
+        # the same with every state kept from the forward pass (1.7 GB): no recomputation
+        extra["inverse128_gradient_stored"] = adjoint_workload(evx, torch, WORKLOADS["inverse128"],
+                                                               every=0)
         extra["surrogate512_application"] = surrogate_workload(torch, WORKLOADS["surrogate512"])
         extra["surrogate_vs_plain"] = surrogate_experiment(torch)
         line["extra"] = extra

@@ -218,6 +218,17 @@ evx_status evx_ch_adjoint_step(evx_plan* plan, const float* c_n, float* lam,
                                const evx_ch_params* params, double* dkappa, double* dM,
                                void* hip_stream);
 
+/* nsteps adjoint steps in one call, backwards through a stored trajectory: for n = nsteps - 1
+ * down to 0, evx_ch_adjoint_step with c_n = states + n V.  states: device, nsteps x V floats
+ * (c^0 .. c^{nsteps-1} of the forward steps, e.g. from evx_ch_advance_record plus evx_ch_end),
+ * read.  lam, dkappa, dM as in evx_ch_adjoint_step: lam goes from dL/dc^{nsteps} to dL/dc^0.
+ * The launches are those of nsteps single calls, so the results are bitwise equal to them.
+ * nsteps = 0 does nothing; EVX_ERR_ARG for nsteps < 0 or a NULL pointer; otherwise errors as
+ * evx_ch_adjoint_step. */
+evx_status evx_ch_adjoint_sweep(evx_plan* plan, const float* states, int nsteps, float* lam,
+                                const evx_ch_params* params, double* dkappa, double* dM,
+                                void* hip_stream);
+
 /* Mass and discrete free energy of a real field (paper: the interfacial free energy functional
  * of the Appendix, here with the double well f):  out[0] = dx^3 sum c,
  * out[1] = dx^3 [sum f(c) + (kappa/2) sum c (-L c)], L the plan's discrete Laplacian.

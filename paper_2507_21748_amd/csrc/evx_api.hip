@@ -613,6 +613,27 @@ evx_status evx_ch_adjoint_step(evx_plan* p, const float* c_n, float* lam,
   return finish(l, "adjoint step");
 }
 
+evx_status evx_ch_adjoint_sweep(evx_plan* p, const float* states, int nsteps, float* lam,
+                                const evx_ch_params* q, double* dkappa, double* dM, void* s) {
+  evx_status st = check_plan(p);
+  if (st != EVX_OK) return st;
+  if ((st = check_params(q)) != EVX_OK) return st;
+  if (nsteps < 0) return fail(EVX_ERR_ARG, "nsteps < 0");
+  if (!states || !lam || !dkappa || !dM) return fail(EVX_ERR_ARG, "NULL argument");
+  if (q->integrator != EVX_INTEGRATOR_SEMI_IMPLICIT || q->model != EVX_MODEL_CAHN_HILLIARD)
+    return fail(EVX_ERR_UNSUPPORTED, "the adjoint step is the semi-implicit Cahn-Hilliard step's");
+  if (p->g.vert)
+    return fail(EVX_ERR_UNSUPPORTED, "adjoint sweep: no vertex-centred axes");
+  if (!p->has_adj)
+    return fail(EVX_ERR_NOMEM, "workspace too small for the adjoint (EVX_OP_ADJOINT)");
+  const AdjointCoef co{coef_of(q), float(q->dt), float(q->dt * q->kappa)};
+  TimedLauncher l = launcher(p, s);
+  for (int n = nsteps - 1; n >= 0; --n)
+    sched_adjoint(l, p->g, p->t, states + size_t(n) * size_t(p->g.V), lam, p->aux, co, dkappa,
+                  dM, p->remap);
+  return finish(l, "adjoint sweep");
+}
+
 evx_status evx_gs_step(evx_plan* p, float* u, float* v, int nsteps, const evx_gs_params* q,
                        void* s) {
   evx_status st = check_plan(p);

@@ -155,6 +155,9 @@ _PROTOS = {
     "evx_ch_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_void_p],
+    "evx_ch_adjoint_sweep": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                             ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_void_p],
     "evx_ch_diagnostics": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Params),
                            ctypes.c_void_p, ctypes.c_void_p],
     "evx_ch_distance": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -338,6 +341,20 @@ class Plan:
             self._h, _dev_ptr(c_n, numel=self.voxels), _dev_ptr(lam, numel=self.voxels),
             ctypes.byref(p), _dev_ptr(dkappa, torch.float64, 1), _dev_ptr(dM, torch.float64, 1),
             _stream_handle(stream)), "evx_ch_adjoint_step")
+        return lam
+
+    def adjoint_sweep(self, states: torch.Tensor, nsteps: int, lam: torch.Tensor,
+                      params: CHParams, dkappa: torch.Tensor, dM: torch.Tensor, stream=None):
+        """nsteps adjoint steps backwards through states[0 .. nsteps-1] (c^0 .. c^{nsteps-1},
+        the leading nsteps fields of a contiguous float32 tensor): lam <- dL/dc^0 from
+        dL/dc^{nsteps}; dkappa, dM accumulate.  Bitwise equal to nsteps adjoint_step calls."""
+        p = params.c()
+        if states.numel() < nsteps * self.voxels:
+            raise ValueError(f"states holds fewer than {nsteps} fields")
+        _check(_LIB.evx_ch_adjoint_sweep(
+            self._h, _dev_ptr(states), int(nsteps), _dev_ptr(lam, numel=self.voxels),
+            ctypes.byref(p), _dev_ptr(dkappa, torch.float64, 1), _dev_ptr(dM, torch.float64, 1),
+            _stream_handle(stream)), "evx_ch_adjoint_sweep")
         return lam
 
     def diagnostics(self, c: torch.Tensor, params: CHParams, out: torch.Tensor = None,

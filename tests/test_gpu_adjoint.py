@@ -113,9 +113,37 @@ def test_checkpointing_is_bitwise(evx_gpu):
     a = _rollout_grads(evx_gpu, c0, target, shape, "periodic", "spectral", p, n, 1)
     b = _rollout_grads(evx_gpu, c0, target, shape, "periodic", "spectral", p, n, 7)
     c = _rollout_grads(evx_gpu, c0, target, shape, "periodic", "spectral", p, n, 30)
-    assert a[0] == b[0] == c[0]
-    assert np.array_equal(a[1], b[1]) and np.array_equal(a[1], c[1])
-    assert a[2] == b[2] == c[2] and a[3] == b[3] == c[3]
+    d = _rollout_grads(evx_gpu, c0, target, shape, "periodic", "spectral", p, n, 0)  # stored
+    assert a[0] == b[0] == c[0] == d[0]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[1], c[1]) and np.array_equal(a[1], d[1])
+    assert a[2] == b[2] == c[2] == d[2] and a[3] == b[3] == c[3] == d[3]
+
+
+@pytest.mark.parametrize("bc,scheme", [("periodic", "spectral"), ("zero_flux", "stencil7")])
+def test_adjoint_sweep_equals_single_steps(evx_gpu, bc, scheme):
+    """evx_ch_adjoint_sweep over a recorded trajectory is bitwise the loop of single adjoint
+    steps (lam and both parameter gradients); nsteps = 0 leaves everything untouched."""
+    shape, n = (16, 24, 32), 5
+    prm = evx_gpu.CHParams(dt=0.5, M=0.9, kappa=1.1)
+    plan = evx_gpu.Plan(shape, bc, scheme, ops=evx_gpu.OP_STEP | evx_gpu.OP_ADJOINT)
+    plan.begin(torch.from_numpy(quench_field(shape, 0.1, 0.3, seed=12)).cuda())
+    traj = torch.empty((n,) + shape, dtype=torch.float32, device="cuda")
+    plan.advance_record(n, prm, traj)
+    lam0 = torch.from_numpy(quench_field(shape, 0.0, 1.0, seed=13)).cuda()
+    a, b = lam0.clone(), lam0.clone()
+    ga = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2)]
+    gb = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2)]
+    for i in range(n - 1, -1, -1):
+        plan.adjoint_step(traj[i], a, prm, ga[0], ga[1])
+    plan.adjoint_sweep(traj, n, b, prm, gb[0], gb[1])
+    plan.adjoint_sweep(traj, 0, b, prm, gb[0], gb[1])
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(ga[0], gb[0]) and torch.equal(ga[1], gb[1])
+    assert not torch.equal(a, lam0)
+    with pytest.raises(evx_gpu.EvxError) as ei:
+        plan.adjoint_sweep(traj, -1, b, prm, gb[0], gb[1])
+    assert ei.value.status == 1
 
 
 def test_inverse_problem_128(evx_gpu):
