@@ -59,11 +59,12 @@ static_assert(NPARAM == 57121, "parameter count");
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ bf16_t f2bf(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
-  return bf16_t(u >> 16);
+// FP32 -> BF16, round to nearest even: gfx950's conversion instruction (two values at once)
+__device__ __forceinline__ unsigned f2bf2(float lo, float hi) {
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(unsigned, v);
 }
+__device__ __forceinline__ bf16_t f2bf(float f) { return bf16_t(f2bf2(f, 0.f)); }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
 // GELU(z) = z Phi(z) with Phi(z) = erfc(-z / sqrt 2) / 2, evaluated through erfc so that the
@@ -108,26 +109,59 @@ __device__ __forceinline__ float gelu_prime(float z) {
   return p + z * 0.39894228040143268f * g;
 }
 
-// GELU of a BF16 pre-activation, rounded to BF16, by table.  For |z| in [2^-8, 8) (11 binades x
-// 128 mantissas x 2 signs = 2816 values) the table holds bf16(gelu(z)) computed once by gelu()
-// above, so those results are identical to evaluating it.  Below 2^-8, Phi(z) = 1/2 + z/sqrt(2 pi)
-// to a relative 1e-8; from 8 up, gelu(z) rounds to z; from -8 down the full evaluation runs.
-constexpr int GT_EMIN = 127 - 8, GT_NEXP = 11, GT_HALF = GT_NEXP * 128, GT_N = 2 * GT_HALF;
-static_assert(GT_N % 8 == 0, "table staged in 16-byte chunks");
-__device__ __forceinline__ bf16_t gelu_table_arg(int idx) {
-  const int sign = idx / GT_HALF, rem = idx % GT_HALF;
-  return bf16_t((sign << 15) | ((GT_EMIN + rem / 128) << 7) | (rem % 128));
+// GELU of a BF16 pre-activation, rounded to BF16, by table.  For |z| in [2^-16, 8) (19 binades x
+// 128 mantissas) the table holds bf16(gelu(z)) computed once by gelu() above, so those results
+// are identical to evaluating it.  It has one row per sign of GT_ROW entries: entry r < GT_HALF is
+// the binade-major position of |z| above 2^-16 (|z|'s bits minus those of 2^-16), and entry GT_HALF
+// is a sentinel (0xFFFF, which no finite result has) that lookups of out-of-range values land on.
+// Below 2^-16, gelu(z) = z (1/2 + z / sqrt(2 pi)) to a relative 1e-5, far below half a BF16 ulp;
+// from 8 up, gelu(z) rounds to z; from -8 down the full evaluation runs.
+constexpr int GT_EMIN = 127 - 16, GT_NEXP = 19, GT_HALF = GT_NEXP * 128, GT_ROW = GT_HALF + 1;
+constexpr int GT_N = (2 * GT_ROW + 7) / 8 * 8;  // staged in 16-byte chunks
+constexpr unsigned GT_SENTINEL = 0xFFFFu;
+__device__ __forceinline__ unsigned gelu_table_entry(int idx) {
+  const int sign = idx / GT_ROW, rel = idx % GT_ROW;
+  if (sign > 1) return 0u;  // padding
+  if (rel == GT_HALF) return GT_SENTINEL;
+  return bf16_t((sign << 15) | ((GT_EMIN << 7) + rel));
+}
+// The slow path of an out-of-table pre-activation.
+__device__ __forceinline__ bf16_t gelu_bf16_outside(bf16_t zb) {
+  const unsigned mag = zb & 0x7FFFu;
+  const float z = bf2f(zb);
+  if (mag < unsigned(GT_EMIN << 7)) return f2bf(z * __builtin_fmaf(0.39894228040143268f, z, 0.5f));
+  return (zb >> 15) ? f2bf(gelu(z)) : zb;  // |z| >= 8, inf, NaN
 }
 __device__ __forceinline__ bf16_t gelu_bf16(bf16_t zb, const bf16_t* tab) {
-  const int ex = (zb >> 7) & 0xFF;
-  const int idx = (zb >> 15) * GT_HALF + (ex - GT_EMIN) * 128 + (zb & 127);
-  const bool in_tab = ex >= GT_EMIN && ex < GT_EMIN + GT_NEXP;
-  const bf16_t tv = tab[in_tab ? idx : 0];
-  const float z = bf2f(zb);
-  bf16_t r = in_tab ? tv : f2bf(z * __builtin_fmaf(0.39894228040143268f, z, 0.5f));
-  if (ex >= GT_EMIN + GT_NEXP) {  // |z| >= 8 (and inf / NaN)
-    if (zb >> 15) r = f2bf(gelu(z));
-    else r = zb;
+  const unsigned rel = (zb & 0x7FFFu) - unsigned(GT_EMIN << 7);  // wraps below 2^-16
+  if (rel < unsigned(GT_HALF)) return tab[(zb >> 15) * GT_ROW + rel];
+  return gelu_bf16_outside(zb);
+}
+
+// Two pre-activations packed in a dword (low half first) at once, on packed 16-bit integer
+// operations: both table positions are formed together, out-of-range ones clamped to the
+// sentinel, and no branch separates the reads, so an epilogue issues all of them before waiting
+// for any.  *worst collects the largest clamped position seen; if it reached GT_HALF in either
+// half, gelu2_fix redoes the sentinel results (rare: |z| < 2^-16 or |z| >= 8).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned gelu2_lookup(unsigned zz, const bf16_t* tab, u16x2* worst) {
+  const u16x2 z = __builtin_bit_cast(u16x2, zz);
+  const u16x2 rel = __builtin_elementwise_min(
+      (u16x2)(z & (u16x2)0x7FFF) - (u16x2)(GT_EMIN << 7), (u16x2)GT_HALF);
+  *worst = __builtin_elementwise_max(*worst, rel);
+  const u16x2 idx = (u16x2)(z >> (u16x2)15) * (u16x2)GT_ROW + rel;
+  return unsigned(tab[idx.x]) | (unsigned(tab[idx.y]) << 16);
+}
+__device__ __forceinline__ bool gelu2_any_outside(u16x2 worst) {
+  return worst.x == GT_HALF || worst.y == GT_HALF;
+}
+__device__ __forceinline__ unsigned gelu2_fix(unsigned zz, unsigned r) {
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    if (((r >> (16 * e)) & 0xFFFFu) == GT_SENTINEL) {
+      const unsigned v = gelu_bf16_outside(bf16_t(zz >> (16 * e)));
+      r = (r & ~(0xFFFFu << (16 * e))) | (v << (16 * e));
+    }
   }
   return r;
 }
@@ -170,13 +204,27 @@ constexpr int MFMA_THREADS = 512;                // 8 waves
 constexpr int HALO_CHUNKS = HALO_VOX * 4;        // 16-byte chunks (64 B per voxel)
 constexpr int W_CHUNKS = 27 * CH * CH * 2 / 16;  // 3456
 
-constexpr int HALO_IT = (HALO_CHUNKS + MFMA_THREADS - 1) / MFMA_THREADS;  // 9
+// Halo staging by rows: lane t < ROWS_PER_IT * ROW_CHUNKS moves chunk t % ROW_CHUNKS (voxel hx =
+// its index / 4, 16-byte part its index % 4) of halo rows t / ROW_CHUNKS + ROWS_PER_IT k (row =
+// hz HY + hy), so the x coordinate is wrapped once per tile and each chunk costs one row's
+// arithmetic.
+constexpr int ROW_CHUNKS = HX * 4;                        // 72
+constexpr int ROWS_PER_IT = MFMA_THREADS / ROW_CHUNKS;    // 7
+constexpr int HALO_ROWS = HY * HZ;                        // 60
+constexpr int HALO_IT = (HALO_ROWS + ROWS_PER_IT - 1) / ROWS_PER_IT;  // 9
+// LDS layouts are chunk-major (a chunk = 8 channels, 16 bytes): halo chunk c of voxel v at
+// c * HALO_CS + v, weight chunk c of output row o (= 16 h + li) for offset d at
+// ((2 d + h) * 4 + c) * 16 + li.  The 8 lanes a 16-byte LDS read serves together (consecutive
+// voxels or rows, one chunk) then read 128 contiguous bytes; with voxels 64 bytes apart they fell
+// in two bank groups (a 4-way conflict on every fragment read).  The 2-voxel pad spreads the four
+// chunks of one voxel over distinct banks when the halo is stored.
+constexpr int HALO_CS = HALO_VOX + 2;
 
 // Persistent: each block stages the weights once and walks tiles blockIdx.x, +gridDim.x, ...;
 // the next tile's halo is loaded into registers while the current one is computed.
 template <int EPI>
 __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntiles) {
-  __shared__ __attribute__((aligned(16))) bf16_t s_in[HALO_VOX * CH];
+  __shared__ __attribute__((aligned(16))) bf16_t s_in[HALO_CS * CH];
   __shared__ __attribute__((aligned(16))) bf16_t s_w[27 * CH * CH];
   __shared__ __attribute__((aligned(16))) bf16_t s_gt[GT_N];
   const int tid = threadIdx.x;
@@ -199,27 +247,40 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int i = i0 + k * MFMA_THREADS;
-        if (i < W_CHUNKS) sw4[i] = r[k];
+        const int row = i >> 2, d = row >> 5, o = row & 31;
+        if (i < W_CHUNKS) sw4[((2 * d + (o >> 4)) * 4 + (i & 3)) * 16 + (o & 15)] = r[k];
       }
     }
   }
   u32x4 pre[HALO_IT];
+  const bool narrow = a.nx < HX || a.ny < HY || a.nz < HZ;  // uniform
+  const int f_col = tid % ROW_CHUNKS, f_row0 = tid / ROW_CHUNKS;
+  const int f_hx = f_col >> 2, f_part = f_col & 3;
+  auto row_ok = [&](int k) {
+    return f_row0 < ROWS_PER_IT && f_row0 + ROWS_PER_IT * k < HALO_ROWS;
+  };
   auto fetch = [&](int tl) {
     const int fx0 = (tl % ntx) * TX;
     const int rest = tl / ntx;
     const int fy0 = (rest % nty) * TY, fz0 = (rest / nty) * TZ;
+    // a partial tile reaches up to TX (TY, TZ) points past the grid edge: on grids at least a
+    // tile plus its halo wide one conditional add or subtract wraps it, else a true modulo
+    const int gx0 = fx0 + f_hx - 1;
+    const int gx = narrow ? pmod(gx0, a.nx) : wrap(gx0, a.nx);
 #pragma unroll
     for (int k = 0; k < HALO_IT; ++k) {
-      const int i = tid + k * MFMA_THREADS;
-      if (i < HALO_CHUNKS) {
-        const int vox = i >> 2, part = i & 3;
-        const int hx = vox % HX, hy = (vox / HX) % HY, hz = vox / (HX * HY);
-        // true modulo: a partial tile may reach up to TX (TY, TZ) points past the grid edge
-        const long long gx = ((fx0 + hx - 1) % a.nx + a.nx) % a.nx,
-                        gy = ((fy0 + hy - 1) % a.ny + a.ny) % a.ny,
-                        gz = ((fz0 + hz - 1) % a.nz + a.nz) % a.nz;
-        pre[k] = gin[((gz * a.ny + gy) * a.nx + gx) * 4 + part];
+      // lanes without a row of their own load row 0 (always valid) and store nothing
+      const int r = row_ok(k) ? f_row0 + ROWS_PER_IT * k : 0;
+      const int hy = r % HY, hz = r / HY;
+      int gy = fy0 + hy - 1, gz = fz0 + hz - 1;
+      if (narrow) {
+        gy = pmod(gy, a.ny);
+        gz = pmod(gz, a.nz);
+      } else {
+        gy = wrap(gy, a.ny);
+        gz = wrap(gz, a.nz);
       }
+      pre[k] = gin[(((long long)gz * a.ny + gy) * a.nx + gx) * 4 + f_part];
     }
   };
   int tile = blockIdx.x;
@@ -241,10 +302,8 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
     const int y0 = (rest % nty) * TY, z0 = (rest / nty) * TZ;
     __syncthreads();  // the previous tile's epilogue is done with the LDS tile
 #pragma unroll
-    for (int k = 0; k < HALO_IT; ++k) {
-      const int i = tid + k * MFMA_THREADS;
-      if (i < HALO_CHUNKS) sin4[i] = pre[k];
-    }
+    for (int k = 0; k < HALO_IT; ++k)
+      if (row_ok(k)) sin4[f_part * HALO_CS + (f_row0 + ROWS_PER_IT * k) * HX + f_hx] = pre[k];
     __syncthreads();
     if (tile + int(gridDim.x) < ntiles) fetch(tile + gridDim.x);
 
@@ -264,13 +323,14 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int d = (dz + 1) * 9 + dyi * 3 + dxi;
-            bw[dyi][h] =
-                *reinterpret_cast<const bf16x8*>(&s_w[((d * CH) + 16 * h + li) * CH + 8 * lg]);
+            bw[dyi][h] = *reinterpret_cast<const bf16x8*>(
+                &reinterpret_cast<const u32x4*>(s_w)[((2 * d + h) * 4 + lg) * 16 + li]);
           }
 #pragma unroll
         for (int yr = 0; yr < 6; ++yr) {
           const int hidx = ((zl + 1 + dz) * HY + (yb + yr)) * HX + (li + dxi);
-          const bf16x8 av = *reinterpret_cast<const bf16x8*>(&s_in[hidx * CH + 8 * lg]);
+          const bf16x8 av =
+              *reinterpret_cast<const bf16x8*>(&reinterpret_cast<const u32x4*>(s_in)[lg * HALO_CS + hidx]);
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             const int dyi = yr - m;  // dy + 1
@@ -285,6 +345,48 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
     // D[o][v] of lane (li, lg), element r: channel 16 h + 4 lg + r of voxel x0 + li in output
     // row m, so each lane leaves 4 consecutive channels of one voxel as an 8-byte store
     const int y = y0 + yb, z = z0 + zl, x = x0 + li;
+    if constexpr (EPI == EPI_GELU || EPI == EPI_GELU_Z) {
+      // z = bf16(acc + b) for all 32 outputs, then every GELU table read, then the rare fix-ups:
+      // no branch separates the reads, so they are all in flight together
+      unsigned zw[4][2][2], aw[4][2][2];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int k = 0; k < 2; ++k)
+            zw[m][h][k] = f2bf2(acc[m][h][2 * k] + bias[h][2 * k],
+                                acc[m][h][2 * k + 1] + bias[h][2 * k + 1]);
+      u16x2 worst = (u16x2)0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) aw[m][h][k] = gelu2_lookup(zw[m][h][k], s_gt, &worst);
+      if (gelu2_any_outside(worst)) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) aw[m][h][k] = gelu2_fix(zw[m][h][k], aw[m][h][k]);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
+        const long long v = ((long long)z * a.ny + y + m) * a.nx + x;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int o0 = 16 * h + 4 * lg;
+          if constexpr (EPI == EPI_GELU_Z)
+            *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) =
+                make_uint2(zw[m][h][0], zw[m][h][1]);
+          *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw[m][h][0], aw[m][h][1]);
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
@@ -292,7 +394,7 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int o0 = 16 * h + 4 * lg;
-        unsigned aw[2], zw[2];
+        unsigned aw[2] = {0u, 0u};
         if constexpr (EPI == EPI_DGELU) {
           const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
           const unsigned zz[2] = {zp.x, zp.y};
@@ -303,16 +405,6 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
                 f2bf(acc[m][h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
             aw[k] = unsigned(lo) | (unsigned(hi) << 16);
           }
-        } else {
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const bf16_t zlo = f2bf(acc[m][h][2 * k] + bias[h][2 * k]);
-            const bf16_t zhi = f2bf(acc[m][h][2 * k + 1] + bias[h][2 * k + 1]);
-            zw[k] = unsigned(zlo) | (unsigned(zhi) << 16);
-            aw[k] = unsigned(gelu_bf16(zlo, s_gt)) | (unsigned(gelu_bf16(zhi, s_gt)) << 16);
-          }
-          if constexpr (EPI == EPI_GELU_Z)
-            *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw[0], zw[1]);
         }
         *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw[0], aw[1]);
       }
@@ -349,6 +441,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
   const int z0 = (t / nty) * TZ;
   {
     constexpr int IT = (HALO_VOX + SMALL_THREADS - 1) / SMALL_THREADS;
+    const bool narrow = a.nx < HX || a.ny < HY || a.nz < HZ;  // uniform
     const elem_t* gin = static_cast<const elem_t*>(a.in);
     elem_t r[IT];
 #pragma unroll
@@ -356,9 +449,17 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
       const int i = tid + k * SMALL_THREADS;
       if (i < HALO_VOX) {
         const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        const long long gx = pmod(x0 + hx - 1, a.nx), gy = pmod(y0 + hy - 1, a.ny),
-                        gz = pmod(z0 + hz - 1, a.nz);
-        r[k] = gin[(gz * a.ny + gy) * a.nx + gx];
+        int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        if (narrow) {  // grids narrower than a tile plus halo: true modulo
+          gx = pmod(gx, a.nx);
+          gy = pmod(gy, a.ny);
+          gz = pmod(gz, a.nz);
+        } else {
+          gx = wrap(gx, a.nx);
+          gy = wrap(gy, a.ny);
+          gz = wrap(gz, a.nz);
+        }
+        r[k] = gin[((long long)gz * a.ny + gy) * a.nx + gx];
       }
     }
 #pragma unroll
@@ -395,6 +496,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
     rel[j] = ok[j] ? ((d / 9 - 1) * HY + (d / 3) % 3 - 1) * HX + d % 3 - 1 : 0;
   }
   __syncthreads();
+  f32x4 accs[4][2];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int yl = yb + m;
@@ -421,21 +523,63 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
 #pragma unroll
       for (int n = 0; n < NT; ++n) part[n][k] = lo[n] | (hi[n] << 16);
     }
-    f32x4 acc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      acc[h] = f32x4{0.f, 0.f, 0.f, 0.f};
+      accs[m][h] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int n = 0; n < NT; ++n)
-        acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[h], as_bf16x8(part[n]), acc[h], 0, 0, 0);
+        accs[m][h] =
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[h], as_bf16x8(part[n]), accs[m][h], 0, 0, 0);
     }
+  }
+  if constexpr (EPI == EPI_GELU || EPI == EPI_GELU_Z) {
+    // as in conv32_mfma: every GELU table read before any is used, rare fix-ups after
+    unsigned zw[4][2][2], gw[4][2][2];
+    u16x2 worst = (u16x2)0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          zw[m][h][k] = f2bf2(accs[m][h][2 * k] + bias[h][2 * k],
+                              accs[m][h][2 * k + 1] + bias[h][2 * k + 1]);
+          gw[m][h][k] = gelu2_lookup(zw[m][h][k], s_gt, &worst);
+        }
+    if (gelu2_any_outside(worst)) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) gw[m][h][k] = gelu2_fix(zw[m][h][k], gw[m][h][k]);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int x = x0 + li, y = y0 + yb + m, z = z0 + zl;
+      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+      const long long v = ((long long)z * a.ny + y) * a.nx + x;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int o0 = 16 * h + 4 * lg;
+        if constexpr (EPI == EPI_GELU_Z)
+          *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw[m][h][0], zw[m][h][1]);
+        *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(gw[m][h][0], gw[m][h][1]);
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const f32x4 (&acc)[2] = accs[m];
+    const int yl = yb + m;
     const int x = x0 + li, y = y0 + yl, z = z0 + zl;
     if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
     const long long v = ((long long)z * a.ny + y) * a.nx + x;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int o0 = 16 * h + 4 * lg;
-      unsigned aw2[2], zw2[2];
+      unsigned aw2[2] = {0u, 0u};
       if constexpr (EPI == EPI_DGELU) {
         const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
         const unsigned zz[2] = {zp.x, zp.y};
@@ -446,16 +590,6 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
               f2bf(acc[h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
           aw2[k] = unsigned(lo) | (unsigned(hi) << 16);
         }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const bf16_t zlo = f2bf(acc[h][2 * k] + bias[h][2 * k]);
-          const bf16_t zhi = f2bf(acc[h][2 * k + 1] + bias[h][2 * k + 1]);
-          zw2[k] = unsigned(zlo) | (unsigned(zhi) << 16);
-          aw2[k] = unsigned(gelu_bf16(zlo, s_gt)) | (unsigned(gelu_bf16(zhi, s_gt)) << 16);
-        }
-        if constexpr (EPI == EPI_GELU_Z)
-          *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw2[0], zw2[1]);
       }
       *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw2[0], aw2[1]);
     }
@@ -891,7 +1025,10 @@ __global__ __launch_bounds__(RED_K * RED_G) void wgrad_reduce(const float* parti
 // ----------------------------------------------------------------------------- misc element-wise
 __global__ void fill_gelu_table(bf16_t* tab) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < GT_N) tab[i] = f2bf(gelu(bf2f(gelu_table_arg(i))));
+  if (i >= GT_N) return;
+  const unsigned e = gelu_table_entry(i);
+  const bool arg = i < 2 * GT_ROW && i % GT_ROW != GT_HALF;
+  tab[i] = arg ? f2bf(gelu(bf2f(bf16_t(e)))) : bf16_t(e);
 }
 
 
