@@ -10,7 +10,7 @@
 //   conv32_mfma   32 -> 32 layers as an implicit GEMM on v_mfma_f32_16x16x32_bf16: one MFMA per
 //                 (16 voxels, 16 output channels, one offset d, all 32 input channels).  A block
 //                 stages a 6x10x18-voxel halo tile (69 KB) and the layer's weights (55 KB) in LDS
-//                 and computes a 4x8x16 output tile with 8 waves.
+//                 and computes a 4x8x16 output tile with 8 waves (4 rows of 16 voxels each).
 //   conv_in_mfma  1 -> 32 layer (and the last layer's backward data) as a GEMM over the 27
 //                 offsets: D[o][v] = sum_d W[d][o] x[v + d]; GELU by a BF16 table.
 //   conv_out_mfma 32 -> 1 layer: P[u][d] = sum_i W[d][i] a[u][i] on MFMA, then
@@ -201,6 +201,11 @@ constexpr int TX = 16, TY = 8, TZ = 4;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HALO_VOX = HX * HY * HZ;           // 1080
 constexpr int MFMA_THREADS = 512;                // 8 waves
+// output rows (y within one z plane) per wave.  4 waves of 8 rows (each weight fragment read
+// from LDS feeds 8 MFMAs instead of 4) measured 30% slower: one wave per SIMD, and its
+// accumulators and prefetch no longer fit the architected registers.
+constexpr int WROWS = TY * TZ / (MFMA_THREADS / 64);
+static_assert(TY % WROWS == 0, "a wave's rows lie in one z plane");
 constexpr int HALO_CHUNKS = HALO_VOX * 4;        // 16-byte chunks (64 B per voxel)
 constexpr int W_CHUNKS = 27 * CH * CH * 2 / 16;  // 3456
 
@@ -209,9 +214,9 @@ constexpr int W_CHUNKS = 27 * CH * CH * 2 / 16;  // 3456
 // hz HY + hy), so the x coordinate is wrapped once per tile and each chunk costs one row's
 // arithmetic.
 constexpr int ROW_CHUNKS = HX * 4;                        // 72
-constexpr int ROWS_PER_IT = MFMA_THREADS / ROW_CHUNKS;    // 7
+constexpr int ROWS_PER_IT = MFMA_THREADS / ROW_CHUNKS;
 constexpr int HALO_ROWS = HY * HZ;                        // 60
-constexpr int HALO_IT = (HALO_ROWS + ROWS_PER_IT - 1) / ROWS_PER_IT;  // 9
+constexpr int HALO_IT = (HALO_ROWS + ROWS_PER_IT - 1) / ROWS_PER_IT;
 // LDS layouts are chunk-major (a chunk = 8 channels, 16 bytes): halo chunk c of voxel v at
 // c * HALO_CS + v, weight chunk c of output row o (= 16 h + li) for offset d at
 // ((2 d + h) * 4 + c) * 16 + li.  The 8 lanes a 16-byte LDS read serves together (consecutive
@@ -287,8 +292,8 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
   if (tile < ntiles) fetch(tile);
 
   const int wave = tid >> 6, lane = tid & 63;
-  const int zl = wave >> 1;          // output z within the tile
-  const int yb = (wave & 1) * 4;     // first of the wave's 4 output rows
+  const int zl = wave * WROWS / TY;  // output z within the tile
+  const int yb = wave * WROWS % TY;  // first of the wave's WROWS output rows
   const int li = lane & 15, lg = lane >> 4;
   float bias[2][4];
 #pragma unroll
@@ -307,40 +312,52 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
     __syncthreads();
     if (tile + int(gridDim.x) < ntiles) fetch(tile + gridDim.x);
 
-    f32x4 acc[4][2];
+    f32x4 acc[WROWS][2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < WROWS; ++m)
 #pragma unroll
       for (int h = 0; h < 2; ++h) acc[m][h] = f32x4{0.f, 0.f, 0.f, 0.f};
     // For fixed (dz, dx) an input row yr of the halo feeds output rows m = yr - 1 - dy of the
-    // wave (dy in {-1, 0, 1}): load its A fragment once and apply it to each of them.
-    for (int dz = -1; dz <= 1; ++dz) {
+    // wave (dy in {-1, 0, 1}): load its B fragment once and apply it to each of them.  The nine
+    // (dz, dx) steps are software-pipelined: step i + 1's fragments (6 weight, WROWS + 2 input)
+    // are read from LDS before step i's MFMAs issue, so their latency hides behind them.
+    bf16x8 fw[2][3][2], fa[2][WROWS + 2];
+    auto load_step = [&](int it, int buf) {
+      const int dz = it / 3 - 1, dxi = it % 3;
 #pragma unroll
-      for (int dxi = 0; dxi < 3; ++dxi) {
-        bf16x8 bw[3][2];
+      for (int dyi = 0; dyi < 3; ++dyi)
 #pragma unroll
-        for (int dyi = 0; dyi < 3; ++dyi)
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int d = (dz + 1) * 9 + dyi * 3 + dxi;
-            bw[dyi][h] = *reinterpret_cast<const bf16x8*>(
-                &reinterpret_cast<const u32x4*>(s_w)[((2 * d + h) * 4 + lg) * 16 + li]);
-          }
-#pragma unroll
-        for (int yr = 0; yr < 6; ++yr) {
-          const int hidx = ((zl + 1 + dz) * HY + (yb + yr)) * HX + (li + dxi);
-          const bf16x8 av =
-              *reinterpret_cast<const bf16x8*>(&reinterpret_cast<const u32x4*>(s_in)[lg * HALO_CS + hidx]);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int dyi = yr - m;  // dy + 1
-            if (dyi < 0 || dyi > 2) continue;
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-              acc[m][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[dyi][h], av, acc[m][h], 0, 0, 0);
-          }
+        for (int h = 0; h < 2; ++h) {
+          const int d = (dz + 1) * 9 + dyi * 3 + dxi;
+          fw[buf][dyi][h] = *reinterpret_cast<const bf16x8*>(
+              &reinterpret_cast<const u32x4*>(s_w)[((2 * d + h) * 4 + lg) * 16 + li]);
         }
+#pragma unroll
+      for (int yr = 0; yr < WROWS + 2; ++yr) {
+        const int hidx = ((zl + 1 + dz) * HY + (yb + yr)) * HX + (li + dxi);
+        fa[buf][yr] = *reinterpret_cast<const bf16x8*>(
+            &reinterpret_cast<const u32x4*>(s_in)[lg * HALO_CS + hidx]);
       }
+    };
+    load_step(0, 0);
+#pragma unroll
+    for (int it = 0; it < 9; ++it) {
+      const int buf = it & 1;
+      if (it + 1 < 9) load_step(it + 1, buf ^ 1);
+      // keep the scheduler from sinking those reads back down to their uses
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int yr = 0; yr < WROWS + 2; ++yr)
+#pragma unroll
+        for (int m = 0; m < WROWS; ++m) {
+          const int dyi = yr - m;  // dy + 1
+          if (dyi < 0 || dyi > 2) continue;
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[m][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[buf][dyi][h], fa[buf][yr],
+                                                                 acc[m][h], 0, 0, 0);
+        }
+      __builtin_amdgcn_sched_barrier(0);
     }
     // D[o][v] of lane (li, lg), element r: channel 16 h + 4 lg + r of voxel x0 + li in output
     // row m, so each lane leaves 4 consecutive channels of one voxel as an 8-byte store
@@ -348,9 +365,9 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
     if constexpr (EPI == EPI_GELU || EPI == EPI_GELU_Z) {
       // z = bf16(acc + b) for all 32 outputs, then every GELU table read, then the rare fix-ups:
       // no branch separates the reads, so they are all in flight together
-      unsigned zw[4][2][2], aw[4][2][2];
+      unsigned zw[WROWS][2][2], aw[WROWS][2][2];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < WROWS; ++m)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -359,21 +376,21 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
                                 acc[m][h][2 * k + 1] + bias[h][2 * k + 1]);
       u16x2 worst = (u16x2)0;
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < WROWS; ++m)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int k = 0; k < 2; ++k) aw[m][h][k] = gelu2_lookup(zw[m][h][k], s_gt, &worst);
       if (gelu2_any_outside(worst)) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < WROWS; ++m)
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int k = 0; k < 2; ++k) aw[m][h][k] = gelu2_fix(zw[m][h][k], aw[m][h][k]);
       }
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < WROWS; ++m) {
         if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
         const long long v = ((long long)z * a.ny + y + m) * a.nx + x;
 #pragma unroll
@@ -388,7 +405,7 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
       continue;
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < WROWS; ++m) {
       if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
       const long long v = ((long long)z * a.ny + y + m) * a.nx + x;
 #pragma unroll
@@ -424,7 +441,7 @@ constexpr int SMALL_THREADS = TX * TY * TZ;  // 512
 // staging.  FP32 input enters as three BF16 terms (hi + mid + lo, exact barring underflow), so
 // every product is exact and only the FP32 accumulation rounds.
 template <bool IN_F32, int EPI>
-__global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
+__global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a, int ntiles) {
   typedef typename std::conditional<IN_F32, float, bf16_t>::type elem_t;
   constexpr int NT = IN_F32 ? 3 : 1;
   __shared__ elem_t s_h[HALO_VOX];
@@ -434,40 +451,9 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
     for (int i = tid; i < GT_N / 8; i += SMALL_THREADS)
       reinterpret_cast<u32x4*>(s_gt)[i] = reinterpret_cast<const u32x4*>(a.gtab)[i];
   const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
-  int t = blockIdx.x;
-  const int x0 = (t % ntx) * TX;
-  t /= ntx;
-  const int y0 = (t % nty) * TY;
-  const int z0 = (t / nty) * TZ;
-  {
-    constexpr int IT = (HALO_VOX + SMALL_THREADS - 1) / SMALL_THREADS;
-    const bool narrow = a.nx < HX || a.ny < HY || a.nz < HZ;  // uniform
-    const elem_t* gin = static_cast<const elem_t*>(a.in);
-    elem_t r[IT];
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int i = tid + k * SMALL_THREADS;
-      if (i < HALO_VOX) {
-        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-        if (narrow) {  // grids narrower than a tile plus halo: true modulo
-          gx = pmod(gx, a.nx);
-          gy = pmod(gy, a.ny);
-          gz = pmod(gz, a.nz);
-        } else {
-          gx = wrap(gx, a.nx);
-          gy = wrap(gy, a.ny);
-          gz = wrap(gz, a.nz);
-        }
-        r[k] = gin[((long long)gz * a.ny + gy) * a.nx + gx];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int i = tid + k * SMALL_THREADS;
-      if (i < HALO_VOX) s_h[i] = r[k];
-    }
-  }
+  constexpr int IT = (HALO_VOX + SMALL_THREADS - 1) / SMALL_THREADS;
+  const bool narrow = a.nx < HX || a.ny < HY || a.nz < HZ;  // uniform
+  const elem_t* gin = static_cast<const elem_t*>(a.in);
   const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int zl = wave >> 1, yb = (wave & 1) * 4;
   // A[o][d] = W[d][o] for o = 16 h + li and this lane's reduction slots d = 8 lg + j
@@ -495,103 +481,135 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a) {
     ok[j] = d < 27;
     rel[j] = ok[j] ? ((d / 9 - 1) * HY + (d / 3) % 3 - 1) * HX + d % 3 - 1 : 0;
   }
-  __syncthreads();
-  f32x4 accs[4][2];
+  // persistent: the table and the weights are staged once, then the block walks tiles
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int x0 = (tile % ntx) * TX;
+    const int y0 = (tile / ntx % nty) * TY;
+    const int z0 = (tile / ntx / nty) * TZ;
+    __syncthreads();  // the previous tile is done with s_h
+    {
+      elem_t r[IT];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int yl = yb + m;
-    const int base = ((zl + 1) * HY + yl + 1) * HX + li + 1;
-    u32x4 part[NT];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      unsigned lo[NT], hi[NT];
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int j = 2 * k + e;
-        float v = 0.f;
-        if (ok[j]) {
-          if constexpr (IN_F32) v = s_h[base + rel[j]];
-          else v = bf2f(s_h[base + rel[j]]);
+      for (int k = 0; k < IT; ++k) {
+        // lanes past the halo load voxel 0 (always valid) and store nothing
+        const int i = tid + k * SMALL_THREADS < HALO_VOX ? tid + k * SMALL_THREADS : 0;
+        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+        int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        if (narrow) {  // grids narrower than a tile plus halo: true modulo
+          gx = pmod(gx, a.nx);
+          gy = pmod(gy, a.ny);
+          gz = pmod(gz, a.nz);
+        } else {
+          gx = wrap(gx, a.nx);
+          gy = wrap(gy, a.ny);
+          gz = wrap(gz, a.nz);
         }
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-          const bf16_t hb = f2bf(v);
-          v -= bf2f(hb);
-          (e ? hi : lo)[n] = hb;
-        }
+        r[k] = gin[((long long)gz * a.ny + gy) * a.nx + gx];
       }
 #pragma unroll
-      for (int n = 0; n < NT; ++n) part[n][k] = lo[n] | (hi[n] << 16);
+      for (int k = 0; k < IT; ++k) {
+        const int i = tid + k * SMALL_THREADS;
+        if (i < HALO_VOX) s_h[i] = r[k];
+      }
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      accs[m][h] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int n = 0; n < NT; ++n)
-        accs[m][h] =
-            __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[h], as_bf16x8(part[n]), accs[m][h], 0, 0, 0);
-    }
-  }
-  if constexpr (EPI == EPI_GELU || EPI == EPI_GELU_Z) {
-    // as in conv32_mfma: every GELU table read before any is used, rare fix-ups after
-    unsigned zw[4][2][2], gw[4][2][2];
-    u16x2 worst = (u16x2)0;
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          zw[m][h][k] = f2bf2(accs[m][h][2 * k] + bias[h][2 * k],
-                              accs[m][h][2 * k + 1] + bias[h][2 * k + 1]);
-          gw[m][h][k] = gelu2_lookup(zw[m][h][k], s_gt, &worst);
-        }
-    if (gelu2_any_outside(worst)) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int k = 0; k < 2; ++k) gw[m][h][k] = gelu2_fix(zw[m][h][k], gw[m][h][k]);
-    }
-#pragma unroll
+    __syncthreads();
+    f32x4 accs[4][2];
+  #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int x = x0 + li, y = y0 + yb + m, z = z0 + zl;
+      const int yl = yb + m;
+      const int base = ((zl + 1) * HY + yl + 1) * HX + li + 1;
+      u32x4 part[NT];
+  #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        unsigned lo[NT], hi[NT];
+  #pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int j = 2 * k + e;
+          float v = 0.f;
+          if (ok[j]) {
+            if constexpr (IN_F32) v = s_h[base + rel[j]];
+            else v = bf2f(s_h[base + rel[j]]);
+          }
+  #pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            const bf16_t hb = f2bf(v);
+            v -= bf2f(hb);
+            (e ? hi : lo)[n] = hb;
+          }
+        }
+  #pragma unroll
+        for (int n = 0; n < NT; ++n) part[n][k] = lo[n] | (hi[n] << 16);
+      }
+  #pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        accs[m][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+  #pragma unroll
+        for (int n = 0; n < NT; ++n)
+          accs[m][h] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[h], as_bf16x8(part[n]), accs[m][h], 0, 0, 0);
+      }
+    }
+    if constexpr (EPI == EPI_GELU || EPI == EPI_GELU_Z) {
+      // as in conv32_mfma: every GELU table read before any is used, rare fix-ups after
+      unsigned zw[4][2][2], gw[4][2][2];
+      u16x2 worst = (u16x2)0;
+  #pragma unroll
+      for (int m = 0; m < 4; ++m)
+  #pragma unroll
+        for (int h = 0; h < 2; ++h)
+  #pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            zw[m][h][k] = f2bf2(accs[m][h][2 * k] + bias[h][2 * k],
+                                accs[m][h][2 * k + 1] + bias[h][2 * k + 1]);
+            gw[m][h][k] = gelu2_lookup(zw[m][h][k], s_gt, &worst);
+          }
+      if (gelu2_any_outside(worst)) {
+  #pragma unroll
+        for (int m = 0; m < 4; ++m)
+  #pragma unroll
+          for (int h = 0; h < 2; ++h)
+  #pragma unroll
+            for (int k = 0; k < 2; ++k) gw[m][h][k] = gelu2_fix(zw[m][h][k], gw[m][h][k]);
+      }
+  #pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int x = x0 + li, y = y0 + yb + m, z = z0 + zl;
+        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        const long long v = ((long long)z * a.ny + y) * a.nx + x;
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int o0 = 16 * h + 4 * lg;
+          if constexpr (EPI == EPI_GELU_Z)
+            *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw[m][h][0], zw[m][h][1]);
+          *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(gw[m][h][0], gw[m][h][1]);
+        }
+      }
+      continue;
+    }
+  #pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const f32x4 (&acc)[2] = accs[m];
+      const int yl = yb + m;
+      const int x = x0 + li, y = y0 + yl, z = z0 + zl;
       if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
       const long long v = ((long long)z * a.ny + y) * a.nx + x;
-#pragma unroll
+  #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int o0 = 16 * h + 4 * lg;
-        if constexpr (EPI == EPI_GELU_Z)
-          *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw[m][h][0], zw[m][h][1]);
-        *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(gw[m][h][0], gw[m][h][1]);
-      }
-    }
-    return;
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const f32x4 (&acc)[2] = accs[m];
-    const int yl = yb + m;
-    const int x = x0 + li, y = y0 + yl, z = z0 + zl;
-    if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-    const long long v = ((long long)z * a.ny + y) * a.nx + x;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int o0 = 16 * h + 4 * lg;
-      unsigned aw2[2] = {0u, 0u};
-      if constexpr (EPI == EPI_DGELU) {
-        const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
-        const unsigned zz[2] = {zp.x, zp.y};
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const bf16_t lo = f2bf(acc[h][2 * k] * gelu_prime(__uint_as_float(zz[k] << 16)));
-          const bf16_t hi =
-              f2bf(acc[h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
-          aw2[k] = unsigned(lo) | (unsigned(hi) << 16);
+        unsigned aw2[2] = {0u, 0u};
+        if constexpr (EPI == EPI_DGELU) {
+          const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
+          const unsigned zz[2] = {zp.x, zp.y};
+  #pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const bf16_t lo = f2bf(acc[h][2 * k] * gelu_prime(__uint_as_float(zz[k] << 16)));
+            const bf16_t hi =
+                f2bf(acc[h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
+            aw2[k] = unsigned(lo) | (unsigned(hi) << 16);
+          }
         }
+        *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw2[0], aw2[1]);
       }
-      *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw2[0], aw2[1]);
     }
   }
 }
@@ -1193,10 +1211,12 @@ hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
   const long long nt = (long long)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY) *
                        ((a.nz + TZ - 1) / TZ);
   const unsigned small_grid = unsigned(nt);
+  const int ntiles = int(nt);
+  // the 1 -> 32 kernel is persistent too: four blocks per CU (its table and halo take 12 KB)
+  const unsigned in_grid = unsigned(nt < 4 * g_num_cus ? nt : 4 * g_num_cus);
   if (kind == K_MFMA) {
     // one persistent block per CU (the LDS tile and weights take 124 KB)
     const unsigned grid = unsigned(nt < g_num_cus ? nt : g_num_cus);
-    const int ntiles = int(nt);
     if (epi == EPI_GELU_Z)
       hipLaunchKernelGGL(conv32_mfma<EPI_GELU_Z>, dim3(grid), dim3(MFMA_THREADS), 0, s, a, ntiles);
     else if (epi == EPI_GELU)
@@ -1205,16 +1225,16 @@ hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(conv32_mfma<EPI_DGELU>, dim3(grid), dim3(MFMA_THREADS), 0, s, a, ntiles);
   } else if (kind == K_IN1) {
     if (epi == EPI_GELU_Z)
-      hipLaunchKernelGGL((conv_in_mfma<false, EPI_GELU_Z>), dim3(small_grid),
-                         dim3(SMALL_THREADS), 0, s, a);
+      hipLaunchKernelGGL((conv_in_mfma<false, EPI_GELU_Z>), dim3(in_grid), dim3(SMALL_THREADS), 0,
+                         s, a, ntiles);
     else
-      hipLaunchKernelGGL((conv_in_mfma<false, EPI_GELU>), dim3(small_grid),
-                         dim3(SMALL_THREADS), 0, s, a);
+      hipLaunchKernelGGL((conv_in_mfma<false, EPI_GELU>), dim3(in_grid), dim3(SMALL_THREADS), 0,
+                         s, a, ntiles);
   } else if (kind == K_OUT1) {
     hipLaunchKernelGGL(conv_out_mfma, dim3(small_grid), dim3(SMALL_THREADS), 0, s, a);
   } else {  // backward data of the last layer: FP32 dY -> bf16 dZ
-    hipLaunchKernelGGL((conv_in_mfma<true, EPI_DGELU>), dim3(small_grid),
-                       dim3(SMALL_THREADS), 0, s, a);
+    hipLaunchKernelGGL((conv_in_mfma<true, EPI_DGELU>), dim3(in_grid), dim3(SMALL_THREADS), 0, s,
+                       a, ntiles);
   }
   return hipGetLastError();
 }
