@@ -334,6 +334,14 @@ evx_status evx_plan_read_pass_times(evx_plan* plan, double ms[4], long long coun
  * EVX_ERR_ARG for steps < -1. */
 evx_status evx_plan_set_step_graph(evx_plan* plan, int steps);
 
+/* Plane pass (the step of the Appendix, "Semi-implicit timestepping", on small grids): on
+ * periodic grids with nx = ny = 32 or 64, evx_ch_advance runs each step's inverse y, fused x and
+ * forward y transforms as one launch per z plane that keeps the plane's spectrum in LDS (the
+ * z pass is unchanged).  Same transforms, tables and operation order as the separate passes, so
+ * the results are bitwise equal.  on = 1 (the default) uses it where the grid allows, on = 0
+ * never; on other grids the call has no effect.  Discards a captured step graph. */
+evx_status evx_plan_set_plane_pass(evx_plan* plan, int on);
+
 /* Block-order option: 1 (default) places consecutive column tiles on the same XCD. */
 evx_status evx_plan_set_xcd_remap(evx_plan* plan, int on);
 

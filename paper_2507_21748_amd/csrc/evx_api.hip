@@ -85,6 +85,7 @@ struct evx_plan {
   // Step loop as captured chunks (evx_plan_set_step_graph): -1 automatic, 0 off, k > 0 chunks of
   // k steps.  gexec replays sched_advance over k steps for the key (coefficients, z mode, remap)
   // it was captured with, on this plan's S and W.
+  int plane_ny = 0;  // the grid's plane-pass size (0: none), restored when re-enabled
   int graph_mode = -1;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -185,6 +186,13 @@ struct TimedLauncher : HipLauncher {
     kind = (mode == ROW_FUSED) ? 1 : -1;
     mark_begin();
     HipLauncher::row(n, bc, mode, a);
+    mark_end();
+  }
+  // the plane pass (inverse y, fused x, forward y in one launch) is timed as the x pass
+  void plane(int ny, const PlaneArgs& a) {
+    kind = 1;
+    mark_begin();
+    HipLauncher::plane(ny, a);
     mark_end();
   }
 };
@@ -361,6 +369,7 @@ evx_status evx_plan_create_axes(evx_plan** out, int nx, int ny, int nz, evx_bc b
   }
   evx_plan* p = new evx_plan();
   p->g = make_geom3(nx, ny, nz, int(bc_x), int(bc_y), int(bc_z), int(scheme), dx);
+  p->plane_ny = p->g.plane_ny;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
@@ -753,6 +762,13 @@ evx_status evx_plan_set_step_graph(evx_plan* p, int steps) {
   if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
   if (steps < -1) return fail(EVX_ERR_ARG, "step graph chunk %d (need -1, 0 or > 0)", steps);
   p->graph_mode = steps;
+  return EVX_OK;
+}
+
+evx_status evx_plan_set_plane_pass(evx_plan* p, int on) {
+  if (!p) return fail(EVX_ERR_ARG, "plan is NULL");
+  drop_graph(p);  // a captured step holds the launches of the previous choice
+  p->g.plane_ny = on ? p->plane_ny : 0;
   return EVX_OK;
 }
 

@@ -238,15 +238,14 @@ EVX_FFT_PLAN(1024, 16, 16, 16, 4)
 
 #undef EVX_FFT_PLAN
 
-template <int N>
+template <int N, class P = FftPlan<N>>
 constexpr int plan_prefix(int s) {
   int p = 1;
-  for (int i = 0; i < s; ++i) p *= FftPlan<N>::R[i];
+  for (int i = 0; i < s; ++i) p *= P::R[i];
   return p;
 }
-template <int N>
+template <int N, class P = FftPlan<N>>
 constexpr bool plan_ok() {
-  using P = FftPlan<N>;
   int prod = 1;
   for (int i = 0; i < P::S; ++i) {
     if (P::E % P::R[i] != 0) return false;
@@ -278,16 +277,15 @@ EVX_DEV int lidx(int n, int b) {
 // In-register/LDS transform of one sequence per lane group (see header comment).  lds must hold
 // B*N float2.  The caller guarantees that no lane still reads lds when this is entered; on return
 // every lane has finished its LDS accesses (the last access is followed by a barrier).
-template <int N, int DIR, int B>
-EVX_DEV void fft_regs(float2 (&x)[FftPlan<N>::E], float2* lds, int b, int t,
+template <int N, int DIR, int B, class P = FftPlan<N>>
+EVX_DEV void fft_regs(float2 (&x)[P::E], float2* lds, int b, int t,
                       const float2* EVX_RESTRICT tw) {
-  using P = FftPlan<N>;
-  static_assert(plan_ok<N>(), "inconsistent FFT plan");
+  static_assert(plan_ok<N, P>(), "inconsistent FFT plan");
   constexpr int E = P::E, TPS = P::TPS, S = P::S;
   static_for<S>([&](auto S_) {
     constexpr int s = decltype(S_)::value;
     constexpr int R = P::R[s];
-    constexpr int p = plan_prefix<N>(s);
+    constexpr int p = plan_prefix<N, P>(s);
     constexpr int NB = E / R;
     constexpr int NR = N / R;
     if constexpr (s > 0) {

@@ -42,6 +42,27 @@ __global__ __launch_bounds__((row_threads<NH, BC>())) void row_kernel_batch(RowA
   rowpass_body<NH, BC, MODE>(a, threadIdx.x, blockIdx.x, gridDim.x, lds);
 }
 
+// One workgroup per z plane (small periodic grids; see planepass_body).
+template <int NY, int NH>
+constexpr int plane_threads() {
+  return PlaneCfg<NY, NH>::THREADS;
+}
+
+template <int NY, int NH>
+__global__ __launch_bounds__((plane_threads<NY, NH>())) void plane_kernel(PlaneArgs a) {
+  __shared__ float2 lds[PlaneCfg<NY, NH>::LDS];
+  planepass_body<NY, NH>(a, threadIdx.x, blockIdx.x, lds);
+}
+
+template <int NY>
+static hipError_t plane_go(const PlaneArgs& a, hipStream_t s) {
+  using C = PlaneCfg<NY, NY / 2>;
+  if (a.nz <= 0) return hipSuccess;
+  if (a.sg.ny != NY || a.ngx != (NY / 2 + 1 + 7) / 8) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((plane_kernel<NY, NY / 2>), dim3(unsigned(a.nz)), dim3(C::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int N, int BC, int MODE>
 static hipError_t col_go(const ColArgs& a, hipStream_t s) {
   using C = ColCfg<N>;
@@ -171,5 +192,11 @@ hipError_t EVX_PASTE(evx_launch_rowb_, EVX_INST_N)(int bc, int mode, const RowAr
   return bc == BC_PERIODIC ? row_mode_batch<EVX_INST_N, BC_PERIODIC>(mode, a, p, s)
                            : row_mode_batch<EVX_INST_N, BC_ZERO_FLUX>(mode, a, p, s);
 }
+
+#if EVX_INST_N == 32 || EVX_INST_N == 64
+hipError_t EVX_PASTE(evx_launch_plane_, EVX_INST_N)(const PlaneArgs& a, hipStream_t s) {
+  return plane_go<EVX_INST_N>(a, s);
+}
+#endif
 
 }  // namespace evx

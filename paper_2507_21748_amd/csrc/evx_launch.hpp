@@ -18,6 +18,8 @@ namespace evx {
 EVX_FOR_EACH_N(EVX_DECL)
 #undef EVX_DECL
 
+hipError_t evx_launch_plane_32(const PlaneArgs& a, hipStream_t s);
+hipError_t evx_launch_plane_64(const PlaneArgs& a, hipStream_t s);
 hipError_t evx_launch_spec(const SpecArgs& a, hipStream_t s);
 hipError_t evx_launch_realsum(const RealSumArgs& a, hipStream_t s);
 hipError_t evx_launch_final(const FinalArgs& a, hipStream_t s);
@@ -63,6 +65,12 @@ struct HipLauncher {
 #undef EVX_CASE
       default: bad_len = true;
     }
+  }
+  void plane(int ny, const PlaneArgs& a) {
+    if (err != hipSuccess || bad_len) return;
+    if (ny == 32) err = evx_launch_plane_32(a, stream);
+    else if (ny == 64) err = evx_launch_plane_64(a, stream);
+    else bad_len = true;
   }
   void spec(const SpecArgs& a) {
     if (err == hipSuccess && !bad_len) err = evx_launch_spec(a, stream);

@@ -25,6 +25,8 @@
 // The real-space field is never stored between steps.
 #pragma once
 
+#include <type_traits>
+
 #include "evx_fft.hpp"
 
 namespace evx {
@@ -1074,6 +1076,184 @@ EVX_DEV void rowpass_body(const RowArgs& a, int tid, int bid, int nblk, float2* 
     else
       spec_rows_out<2 * B, SS, NX / 2, T>(a.out_c, a.sg, r0, a.nrows - r0, lds, tid);
   }
+}
+
+// ------------------------------------------------------------------ plane pass (small grids)
+// On a grid whose xy spectral plane fits in LDS, one workgroup per z plane runs the step's first
+// three passes on that plane in place: it reads the plane's NH + 1 complex x bins of NY rows once,
+// runs the inverse y transforms, the fused x pass (inverse x, f', forward x) and the forward y
+// transforms, and writes the plane back once.  Three launches and three trips through memory
+// become one, which is what bounds a step on such grids (every launch carries a few microseconds
+// of load-transform-store latency).  The transforms use the same twiddle tables and operation
+// order as the column and row passes they replace (and their FFT plans where PlanePlans says so).
+// Periodic x and y (and z) only.
+struct PlaneArgs {
+  float2* W;            // work buffer (grouped layout), read and written in place
+  SpecGeom sg;
+  int nz, ngx;
+  const float2* tw_y;   // exp(-2 pi i j / NY)
+  const float2* tw_x;   // exp(-2 pi i j / NH)
+  const float2* post;   // exp(-2 pi i k / (2 NH)), k <= NH / 2
+  float scale;          // 1 / (nx ny nz), applied after the inverse x transform
+};
+
+// Per plane size: the FFT plans of the y and x transforms (those of the column and row passes, so
+// the results are bitwise theirs) and the lanes of the workgroup, chosen so that one batch covers
+// all NH + 1 columns and all NY rows (every lane is a (sequence, part) pair in both) and the
+// exchange area fits beside the plane.  Measured on 128 x 128 planes the pass lost to the three
+// separate ones (27 us against about 22 us for the three: 128 workgroups fill half the chip), so
+// it stops at 64 x 64.
+template <int NY, int NH>
+struct PlanePlans;
+template <>
+struct PlanePlans<32, 16> {  // 17 columns x 4 lanes, 32 rows x 1 lane
+  using PY = FftPlan<32>;
+  using PX = FftPlan<16>;
+  static constexpr int THREADS = 68;
+};
+template <>
+struct PlanePlans<64, 32> {  // 64 columns x 16 lanes, 256 rows x 4 lanes
+  using PY = FftPlan<64>;
+  using PX = FftPlan<32>;
+  static constexpr int THREADS = 1024;
+};
+
+template <int NY, int NH>
+struct PlaneCfg {
+  using PY = typename PlanePlans<NY, NH>::PY;
+  using PX = typename PlanePlans<NY, NH>::PX;
+  static constexpr int THREADS = PlanePlans<NY, NH>::THREADS;
+  static constexpr int EY = PY::E, TY = PY::TPS;
+  static constexpr int EX = PX::E, TX = PX::TPS;
+  static_assert(THREADS % TY == 0 && THREADS % TX == 0, "lanes split into whole sequences");
+  static constexpr int NC = NH + 1;                       // live x bins
+  // sequences per batch: every lane takes part in every transform (they hold barriers), and
+  // lanes past the live columns or rows work on zeros and store nothing
+  static constexpr int BY = THREADS / TY;                 // y columns per batch
+  static constexpr int BX = THREADS / TX;                 // x rows per batch
+  static constexpr int PW = NC % 2 ? NC : NC + 1;        // plane row pitch (odd: rows in distinct banks)
+  static constexpr int PLANE = NY * PW;
+  static constexpr int XCH = BY * NY > BX * NH ? BY * NY : BX * NH;  // FFT exchange area
+  static constexpr int TWY = PLANE + XCH, TWX = TWY + NY, PO = TWX + NH;
+  static constexpr int NPOST = NH / 2 + 1;
+  static constexpr int LDS = PO + NPOST;  // float2 slots
+  static constexpr int LOADS = (((NC + 7) / 8) * NY * 8 + THREADS - 1) / THREADS;
+};
+
+template <int NY, int NH>
+EVX_DEV void planepass_body(const PlaneArgs& a, int tid, int bid, float2* lds) {
+  using C = PlaneCfg<NY, NH>;
+  constexpr int T = C::THREADS, PW = C::PW, NC = C::NC;
+  float2* const P = lds;
+  float2* const xch = lds + C::PLANE;
+  float2* const twy = lds + C::TWY;
+  float2* const twx = lds + C::TWX;
+  float2* const pol = lds + C::PO;
+  const long long zoff = (long long)bid * a.sg.zstride;  // plane z = bid, group 0
+  // tables and the plane, all loads in flight together; group g's rows are one contiguous run
+  TableStage<NY, T, float2> sty;
+  sty.load(a.tw_y, tid);
+  TableStage<NH, T, float2> stx;
+  stx.load(a.tw_x, tid);
+  TableStage<C::NPOST, T, float2> spo;
+  spo.load(a.post, tid);
+  constexpr int GRUN = NY * 8;  // float2 of one group's rows of the plane
+  float2 r[C::LOADS];
+  static_for<C::LOADS>([&](auto I) {
+    const int f = tid + T * decltype(I)::value;
+    const int g = f / GRUN, rem = f - g * GRUN;
+    const bool ok = g < a.ngx;
+    r[I] = load_or_zero(a.W, g * a.sg.xstride + zoff + rem, ok);
+  });
+  sty.store(twy, tid);
+  stx.store(twx, tid);
+  spo.store(pol, tid);
+  static_for<C::LOADS>([&](auto I) {
+    const int f = tid + T * decltype(I)::value;
+    const int g = f / GRUN, rem = f - g * GRUN;
+    const int col = g * 8 + (rem & 7), y = rem >> 3;
+    if (g < a.ngx && col < NC) P[y * PW + col] = r[I];
+  });
+  evx_sync();
+
+  // y transforms of the live columns, C::BY at a time (dir +1 inverse, -1 forward)
+  auto y_pass = [&](auto dir_) {
+    constexpr int DIR = decltype(dir_)::value;
+    constexpr int B = C::BY, E = C::EY, TPS = C::TY;
+    const int b = tid % B, t = tid / B;
+    for (int c0 = 0; c0 < NC; c0 += B) {  // uniform
+      const int col = c0 + b;
+      const bool live = col < NC;
+      float2 x[E];
+      static_for<E>([&](auto e) {
+        const int yy = t + TPS * decltype(e)::value;
+        x[e] = live ? P[yy * PW + (live ? col : 0)] : make_float2(0.f, 0.f);
+      });
+      fft_regs<NY, DIR, B, typename C::PY>(x, xch, b, t, twy);
+      if (live)
+        static_for<E>([&](auto e) { P[(t + TPS * decltype(e)::value) * PW + col] = x[e]; });
+      evx_sync();  // the next batch reuses the exchange area
+    }
+  };
+  y_pass(std::integral_constant<int, +1>{});
+
+  // fused x pass on rows of NH + 1 complex bins (the periodic row pass's arithmetic)
+  {
+    constexpr int B = C::BX, E = C::EX, TPS = C::TX;
+    const int b = tid % B, t = tid / B;
+    for (int y0 = 0; y0 < NY; y0 += B) {  // uniform
+      const bool act = y0 + b < NY;
+      float2* const row = P + (act ? y0 + b : 0) * PW;
+      float2 x[E];
+      // C2R pre-processing: Z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) e^{+2pi i k/NX}
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        if (act) {
+          const float2 X = row[k];
+          const float2 Xr = cconj(row[NH - k]);
+          const float2 Ev = cadd(X, Xr);
+          const float2 Od = cmulc(csub(X, Xr), post_tw<NH>(pol, k));
+          x[e] = make_float2(Ev.x - Od.y, Ev.y + Od.x);
+        } else {
+          x[e] = make_float2(0.f, 0.f);
+        }
+      });
+      fft_regs<NH, +1, B, typename C::PX>(x, xch, b, t, twx);
+      static_for<E>([&](auto e) { x[e] = cscale(x[e], a.scale); });
+      static_for<E>([&](auto e) { x[e] = make_float2(fprime(x[e].x), fprime(x[e].y)); });
+      fft_regs<NH, -1, B, typename C::PX>(x, xch, b, t, twx);
+      static_for<E>([&](auto e) { xch[lidx<B>(t + TPS * decltype(e)::value, b)] = x[e]; });
+      evx_sync();
+      float2 yv[E];
+      float2 ynyq = make_float2(0.f, 0.f);
+      static_for<E>([&](auto e) {
+        const int k = t + TPS * decltype(e)::value;
+        const float2 Pk = x[e];
+        const float2 Q = cconj(xch[lidx<B>(k == 0 ? 0 : NH - k, b)]);
+        const float2 Ev = cscale(cadd(Pk, Q), 0.5f);
+        const float2 dq = cscale(csub(Pk, Q), 0.5f);
+        const float2 Od = make_float2(dq.y, -dq.x);  // -i (P - Q) / 2
+        yv[e] = cadd(Ev, cmul(post_tw<NH>(pol, k), Od));
+        if (k == 0) ynyq = make_float2(Ev.x - Od.x, 0.f);
+      });
+      evx_sync();  // the exchange area is read; the next batch (or y pass) may write it
+      if (act) {
+        static_for<E>([&](auto e) { row[t + TPS * decltype(e)::value] = yv[e]; });
+        if (t == 0) row[NH] = ynyq;
+      }
+    }
+    evx_sync();
+  }
+  y_pass(std::integral_constant<int, -1>{});
+
+  // write the plane back; the dead columns of the last group are written as zeros
+  static_for<C::LOADS>([&](auto I) {
+    const int f = tid + T * decltype(I)::value;
+    const int g = f / GRUN, rem = f - g * GRUN;
+    const int col = g * 8 + (rem & 7), y = rem >> 3;
+    if (g < a.ngx)
+      a.W[g * a.sg.xstride + zoff + rem] = col < NC ? P[y * PW + col] : make_float2(0.f, 0.f);
+  });
 }
 
 }  // namespace evx

@@ -63,7 +63,11 @@ struct Geom {
   long long spec = 0;    // float2 per spectral buffer (work W): ngx nz ypitch 8
   long long state = 0;   // float2 of the state S (tile-major; whole z-pass tiles)
   long long nrows = 0;   // ny * nz
+  int plane_ny = 0;      // > 0: the step's y, x, y passes run as one plane pass (planepass_body)
 };
+
+// Plane pass sizes: square periodic xy planes of 32 or 64 points (planepass_body).
+inline bool plane_pass_supported(int nx, int ny) { return nx == ny && (ny == 32 || ny == 64); }
 
 // Per-axis boundaries: any mix of periodic, zero flux (cell- or vertex-centred) and Dirichlet.
 // A vertex-centred axis runs the periodic transform of the field's even extension about its end
@@ -100,6 +104,8 @@ inline Geom make_geom3(int nx, int ny, int nz, int bcx, int bcy, int bcz, int sc
   const long long bz = col_block_seqs(g.fz), nseq_z = (long long)g.ngx * ny * 8;
   g.state = bz > 0 ? (nseq_z + bz - 1) / bz * bz * g.fz : g.spec;
   g.nrows = (long long)ny * nz;
+  g.plane_ny = (bcx == BC_PERIODIC && bcy == BC_PERIODIC && bcz == BC_PERIODIC &&
+                plane_pass_supported(nx, ny)) ? ny : 0;
   return g;
 }
 
@@ -271,7 +277,21 @@ inline RowArgs x_args(const Geom& g, const TablePtrs& t, const float2* in_c, con
   return a;
 }
 
-// Launcher L provides col(N, bc, mode, ColArgs) and row(NH, bc, mode, RowArgs).
+inline PlaneArgs plane_args(const Geom& g, const TablePtrs& t, float2* W) {
+  PlaneArgs a{};
+  a.W = W;
+  a.sg = spec_geom(g);
+  a.nz = g.nz;
+  a.ngx = g.ngx;
+  a.tw_y = t.tw_y;
+  a.tw_x = t.tw_x;
+  a.post = t.post_x;
+  a.scale = x_args(g, t, W, nullptr, W, nullptr).scale;  // the row pass's normalisation
+  return a;
+}
+
+// Launcher L provides col(N, bc, mode, ColArgs), row(NH, bc, mode, RowArgs) and
+// plane(NY, PlaneArgs).
 
 // Initial forward transform of the real field c: S <- T[c], W <- F_z^{-1} S.
 template <class L>
@@ -287,9 +307,13 @@ template <class L>
 void sched_advance(L& l, const Geom& g, const TablePtrs& t, float2* S, float2* W, StepCoef c,
                    int nsteps, int remap, int zmode = COL_Z_UPDATE) {
   for (int n = 0; n < nsteps; ++n) {
-    l.col(g.fy, g.bcy, COL_INV, y_args(g, t, W, W, remap));
-    l.row(g.row_len, g.bc, ROW_FUSED, x_args(g, t, W, nullptr, W, nullptr));
-    l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    if (g.plane_ny) {
+      l.plane(g.plane_ny, plane_args(g, t, W));
+    } else {
+      l.col(g.fy, g.bcy, COL_INV, y_args(g, t, W, W, remap));
+      l.row(g.row_len, g.bc, ROW_FUSED, x_args(g, t, W, nullptr, W, nullptr));
+      l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, W, W, remap));
+    }
     l.col(g.fz, g.bcz, zmode, z_args(g, t, W, W, S, c, remap));
   }
 }

@@ -152,6 +152,7 @@ _PROTOS = {
                                  ctypes.POINTER(ctypes.c_longlong)],
     "evx_plan_set_xcd_remap": [ctypes.c_void_p, ctypes.c_int],
     "evx_plan_set_step_graph": [ctypes.c_void_p, ctypes.c_int],
+    "evx_plan_set_plane_pass": [ctypes.c_void_p, ctypes.c_int],
     "evx_ch_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.c_void_p],
@@ -392,6 +393,11 @@ class Plan:
 
     def set_xcd_remap(self, on: bool):
         _check(_LIB.evx_plan_set_xcd_remap(self._h, int(bool(on))), "evx_plan_set_xcd_remap")
+
+    def set_plane_pass(self, on: bool):
+        """Run the step's y, x, y transforms as one launch per z plane where the grid allows
+        (periodic, nx = ny = 32 or 64; the default), or always as three passes."""
+        _check(_LIB.evx_plan_set_plane_pass(self._h, int(bool(on))), "evx_plan_set_plane_pass")
 
     def set_step_graph(self, steps: int):
         """Step-loop launch mode: chunks of `steps` steps replayed as one HIP graph (> 0), every

@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <limits>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include <cstring>
@@ -180,6 +181,18 @@ struct EmuLauncher {
   void vm_rhs(const VmStencilArgs& a) {
     grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
           [&](int tid, int bx, int by, int bz) { vm_rhs_body(a, tid, bx, by, bz); });
+  }
+  void plane(int ny, const PlaneArgs& a) {
+    auto go = [&](auto ny_) {
+      constexpr int NY = decltype(ny_)::value;
+      using C = PlaneCfg<NY, NY / 2>;
+      run_grid(a.nz, C::THREADS, C::LDS, [&](int tid, int bid, int, float2* lds) {
+        planepass_body<NY, NY / 2>(a, tid, bid, lds);
+      });
+    };
+    if (ny == 32) go(std::integral_constant<int, 32>{});
+    else if (ny == 64) go(std::integral_constant<int, 64>{});
+    else { std::fprintf(stderr, "unsupported plane %d\n", ny); std::exit(3); }
   }
   void row(int n, int bc, int mode, const RowArgs& a) {
     switch (n) {

@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2507_21748_amd", "csrc")
 MAIN = os.path.join(ROOT, "tests", "emu", "emu_main.cpp")
 OUT = os.path.join(ROOT, "_build", "emu")
-SIZES = "X(8) X(12) X(16) X(20) X(24) X(48) X(64) X(96)"
+SIZES = "X(8) X(12) X(16) X(20) X(24) X(32) X(48) X(64) X(96)"
 SAN = {"asan": "-fsanitize=address", "tsan": "-fsanitize=thread"}
 
 
@@ -95,6 +95,9 @@ CASES = [
     ((64, 12, 16), "periodic", "spectral", 2),    # 64-point plan (4 points per lane) along z
     ((8, 12, 64), "zero_flux", "stencil7", 2),    # ... as the zero-flux row
     ((8, 12, 128), "periodic", "spectral", -2),   # ... as the periodic row (nx/2 = 64), resume
+    ((8, 64, 64), "periodic", "spectral", 2),     # plane pass (64 x 64 spectral plane in LDS)
+    ((12, 64, 64), "periodic", "stencil7", -3),   # ... stencil K2, resume path
+    ((8, 32, 32), "periodic", "spectral", 2),     # ... 32 x 32 planes (68-lane workgroups)
 ]
 
 
