@@ -197,6 +197,31 @@ struct ConvArgs {
 };
 
 // ----------------------------------------------------------------------------- MFMA 32 -> 32
+// Output channels to MFMA rows: the two 16-row MFMAs of a layer (h = 0, 1) take channel
+// 8 (R / 4) + 4 h + R % 4 as row R, so the D fragments of a lane of lane group lg hold the 8
+// consecutive channels 8 lg .. 8 lg + 7 of its voxel (4 from each MFMA) and leave as one 16-byte
+// store, full 64-byte voxel rows per 16 lanes.
+__device__ __forceinline__ int out_channel(int h, int row) {
+  return 8 * (row >> 2) + 4 * h + (row & 3);
+}
+// Backward-data epilogue of one voxel v: channels 8 lg .. 8 lg + 7 (acc[h][r] is channel
+// 8 lg + 4 h + r) become bf16(acc * gelu'(zprev)), zprev read and the result written 16 bytes at
+// a time.
+__device__ __forceinline__ void store_dgelu(const ConvArgs& a, long long v, int lg,
+                                            const f32x4 (&acc)[2]) {
+  const uint4 zp = *reinterpret_cast<const uint4*>(a.zprev + v * CH + 8 * lg);
+  const unsigned zz[2][2] = {{zp.x, zp.y}, {zp.z, zp.w}};
+  unsigned ow[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const bf16_t lo = f2bf(acc[h][2 * k] * gelu_prime(__uint_as_float(zz[h][k] << 16)));
+      const bf16_t hi = f2bf(acc[h][2 * k + 1] * gelu_prime(__uint_as_float(zz[h][k] & 0xFFFF0000u)));
+      ow[h][k] = unsigned(lo) | (unsigned(hi) << 16);
+    }
+  *reinterpret_cast<uint4*>(a.a_out + v * CH + 8 * lg) = make_uint4(ow[0][0], ow[0][1], ow[1][0], ow[1][1]);
+}
 constexpr int TX = 16, TY = 8, TZ = 4;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int HALO_VOX = HX * HY * HZ;           // 1080
@@ -229,6 +254,7 @@ constexpr int HALO_CS = HALO_VOX + 2;
 // the next tile's halo is loaded into registers while the current one is computed.
 template <int EPI>
 __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntiles) {
+  static_assert(EPI == EPI_GELU || EPI == EPI_GELU_Z || EPI == EPI_DGELU, "epilogue kind");
   __shared__ __attribute__((aligned(16))) bf16_t s_in[HALO_CS * CH];
   __shared__ __attribute__((aligned(16))) bf16_t s_w[27 * CH * CH];
   __shared__ __attribute__((aligned(16))) bf16_t s_gt[GT_N];
@@ -252,8 +278,10 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int i = i0 + k * MFMA_THREADS;
+        // output channel o is row ((o / 8) * 4 + o % 4) of MFMA (o / 4) % 2
         const int row = i >> 2, d = row >> 5, o = row & 31;
-        if (i < W_CHUNKS) sw4[((2 * d + (o >> 4)) * 4 + (i & 3)) * 16 + (o & 15)] = r[k];
+        const int h = (o >> 2) & 1, mr = ((o >> 3) << 2) | (o & 3);
+        if (i < W_CHUNKS) sw4[((2 * d + h) * 4 + (i & 3)) * 16 + mr] = r[k];
       }
     }
   }
@@ -299,7 +327,8 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bias[h][r] = EPI != EPI_DGELU ? a.bias[16 * h + 4 * lg + r] : 0.f;
+    for (int r = 0; r < 4; ++r)
+      bias[h][r] = EPI != EPI_DGELU ? a.bias[out_channel(h, 4 * lg + r)] : 0.f;
 
   for (; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % ntx) * TX;
@@ -359,8 +388,8 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
         }
       __builtin_amdgcn_sched_barrier(0);
     }
-    // D[o][v] of lane (li, lg), element r: channel 16 h + 4 lg + r of voxel x0 + li in output
-    // row m, so each lane leaves 4 consecutive channels of one voxel as an 8-byte store
+    // D[R][v] of lane (li, lg), element r (R = 4 lg + r): channel 8 lg + 4 h + r of voxel x0 + li
+    // in output row m, so each lane leaves channels 8 lg .. 8 lg + 7 of one voxel in 16 bytes
     const int y = y0 + yb, z = z0 + zl, x = x0 + li;
     if constexpr (EPI == EPI_GELU || EPI == EPI_GELU_Z) {
       // z = bf16(acc + b) for all 32 outputs, then every GELU table read, then the rare fix-ups:
@@ -393,37 +422,19 @@ __global__ __launch_bounds__(MFMA_THREADS) void conv32_mfma(ConvArgs a, int ntil
       for (int m = 0; m < WROWS; ++m) {
         if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
         const long long v = ((long long)z * a.ny + y + m) * a.nx + x;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int o0 = 16 * h + 4 * lg;
-          if constexpr (EPI == EPI_GELU_Z)
-            *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) =
-                make_uint2(zw[m][h][0], zw[m][h][1]);
-          *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw[m][h][0], aw[m][h][1]);
-        }
+        if constexpr (EPI == EPI_GELU_Z)
+          *reinterpret_cast<uint4*>(a.z_out + v * CH + 8 * lg) =
+              make_uint4(zw[m][0][0], zw[m][0][1], zw[m][1][0], zw[m][1][1]);
+        *reinterpret_cast<uint4*>(a.a_out + v * CH + 8 * lg) =
+            make_uint4(aw[m][0][0], aw[m][0][1], aw[m][1][0], aw[m][1][1]);
       }
       continue;
     }
+    if constexpr (EPI == EPI_DGELU) {
 #pragma unroll
-    for (int m = 0; m < WROWS; ++m) {
-      if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
-      const long long v = ((long long)z * a.ny + y + m) * a.nx + x;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int o0 = 16 * h + 4 * lg;
-        unsigned aw[2] = {0u, 0u};
-        if constexpr (EPI == EPI_DGELU) {
-          const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
-          const unsigned zz[2] = {zp.x, zp.y};
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const bf16_t lo = f2bf(acc[m][h][2 * k] * gelu_prime(__uint_as_float(zz[k] << 16)));
-            const bf16_t hi =
-                f2bf(acc[m][h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
-            aw[k] = unsigned(lo) | (unsigned(hi) << 16);
-          }
-        }
-        *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw[0], aw[1]);
+      for (int m = 0; m < WROWS; ++m) {
+        if (x >= a.nx || y + m >= a.ny || z >= a.nz) continue;
+        store_dgelu(a, ((long long)z * a.ny + y + m) * a.nx + x, lg, acc[m]);
       }
     }
   }
@@ -436,12 +447,13 @@ constexpr int SMALL_THREADS = TX * TY * TZ;  // 512
 // The 1 -> 32 layer, and the backward data of the 32 -> 1 layer (with flipped weights a 1 -> 32
 // convolution of FP32 dY), as one GEMM per 16 voxels with the 27 offsets as the reduction index
 // (padded to 32): D[o][v] = sum_d W[d][o] x[v + d] on v_mfma_f32_16x16x32_bf16, with the weights
-// as A (held in registers) and B the halo values gathered for 16 voxels of a row.  A lane's D
-// fragment holds 4 consecutive channels of one voxel, so results leave as 8-byte stores without
-// staging.  FP32 input enters as three BF16 terms (hi + mid + lo, exact barring underflow), so
+// as A (held in registers, rows permuted by out_channel) and B the halo values gathered for 16
+// voxels of a row.  A lane's two D fragments hold 8 consecutive channels of one voxel, so results
+// leave as 16-byte stores without staging.  FP32 input enters as three BF16 terms (hi + mid + lo, exact barring underflow), so
 // every product is exact and only the FP32 accumulation rounds.
 template <bool IN_F32, int EPI>
 __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a, int ntiles) {
+  static_assert(EPI == EPI_GELU || EPI == EPI_GELU_Z || EPI == EPI_DGELU, "epilogue kind");
   typedef typename std::conditional<IN_F32, float, bf16_t>::type elem_t;
   constexpr int NT = IN_F32 ? 3 : 1;
   __shared__ elem_t s_h[HALO_VOX];
@@ -456,22 +468,25 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a, int nt
   const elem_t* gin = static_cast<const elem_t*>(a.in);
   const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int zl = wave >> 1, yb = (wave & 1) * 4;
-  // A[o][d] = W[d][o] for o = 16 h + li and this lane's reduction slots d = 8 lg + j
+  // A[R][d] = W[d][o] for row R = li of MFMA h, channel o = out_channel(h, li), and this lane's
+  // reduction slots d = 8 lg + j
   bf16x8 aw[2];
   float bias[2][4];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
+    const int o = out_channel(h, li);
     u32x4 q;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int d = 8 * lg + 2 * k;
-      const unsigned lo = d < 27 ? a.w[d * CH + 16 * h + li] : 0u;
-      const unsigned hi = d + 1 < 27 ? a.w[(d + 1) * CH + 16 * h + li] : 0u;
+      const unsigned lo = d < 27 ? a.w[d * CH + o] : 0u;
+      const unsigned hi = d + 1 < 27 ? a.w[(d + 1) * CH + o] : 0u;
       q[k] = lo | (hi << 16);
     }
     aw[h] = as_bf16x8(q);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bias[h][r] = EPI != EPI_DGELU ? a.bias[16 * h + 4 * lg + r] : 0.f;
+    for (int r = 0; r < 4; ++r)
+      bias[h][r] = EPI != EPI_DGELU ? a.bias[out_channel(h, 4 * lg + r)] : 0.f;
   }
   int rel[8];
   bool ok[8];
@@ -481,38 +496,44 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a, int nt
     ok[j] = d < 27;
     rel[j] = ok[j] ? ((d / 9 - 1) * HY + (d / 3) % 3 - 1) * HX + d % 3 - 1 : 0;
   }
-  // persistent: the table and the weights are staged once, then the block walks tiles
+  // persistent: the table and the weights are staged once, then the block walks tiles; the next
+  // tile's halo is loaded into registers while the current one is computed
+  elem_t pre[IT];
+  auto fetch = [&](int tl) {
+    const int fx0 = (tl % ntx) * TX;
+    const int fy0 = (tl / ntx % nty) * TY;
+    const int fz0 = (tl / ntx / nty) * TZ;
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      // lanes past the halo load voxel 0 (always valid) and store nothing
+      const int i = tid + k * SMALL_THREADS < HALO_VOX ? tid + k * SMALL_THREADS : 0;
+      const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+      int gx = fx0 + hx - 1, gy = fy0 + hy - 1, gz = fz0 + hz - 1;
+      if (narrow) {  // grids narrower than a tile plus halo: true modulo
+        gx = pmod(gx, a.nx);
+        gy = pmod(gy, a.ny);
+        gz = pmod(gz, a.nz);
+      } else {
+        gx = wrap(gx, a.nx);
+        gy = wrap(gy, a.ny);
+        gz = wrap(gz, a.nz);
+      }
+      pre[k] = gin[((long long)gz * a.ny + gy) * a.nx + gx];
+    }
+  };
+  if (int(blockIdx.x) < ntiles) fetch(blockIdx.x);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % ntx) * TX;
     const int y0 = (tile / ntx % nty) * TY;
     const int z0 = (tile / ntx / nty) * TZ;
     __syncthreads();  // the previous tile is done with s_h
-    {
-      elem_t r[IT];
 #pragma unroll
-      for (int k = 0; k < IT; ++k) {
-        // lanes past the halo load voxel 0 (always valid) and store nothing
-        const int i = tid + k * SMALL_THREADS < HALO_VOX ? tid + k * SMALL_THREADS : 0;
-        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-        if (narrow) {  // grids narrower than a tile plus halo: true modulo
-          gx = pmod(gx, a.nx);
-          gy = pmod(gy, a.ny);
-          gz = pmod(gz, a.nz);
-        } else {
-          gx = wrap(gx, a.nx);
-          gy = wrap(gy, a.ny);
-          gz = wrap(gz, a.nz);
-        }
-        r[k] = gin[((long long)gz * a.ny + gy) * a.nx + gx];
-      }
-#pragma unroll
-      for (int k = 0; k < IT; ++k) {
-        const int i = tid + k * SMALL_THREADS;
-        if (i < HALO_VOX) s_h[i] = r[k];
-      }
+    for (int k = 0; k < IT; ++k) {
+      const int i = tid + k * SMALL_THREADS;
+      if (i < HALO_VOX) s_h[i] = pre[k];
     }
     __syncthreads();
+    if (tile + int(gridDim.x) < ntiles) fetch(tile + gridDim.x);
     f32x4 accs[4][2];
   #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -550,65 +571,50 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a, int nt
       }
     }
     if constexpr (EPI == EPI_GELU || EPI == EPI_GELU_Z) {
-      // as in conv32_mfma: every GELU table read before any is used, rare fix-ups after
-      unsigned zw[4][2][2], gw[4][2][2];
-      u16x2 worst = (u16x2)0;
+      // as in conv32_mfma, in two halves of two rows: every GELU table read of a half before any
+      // is used, rare fix-ups after
   #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m0 = 0; m0 < 4; m0 += 2) {
+        unsigned zw[2][2][2], gw[2][2][2];
+        u16x2 worst = (u16x2)0;
   #pragma unroll
-        for (int h = 0; h < 2; ++h)
-  #pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            zw[m][h][k] = f2bf2(accs[m][h][2 * k] + bias[h][2 * k],
-                                accs[m][h][2 * k + 1] + bias[h][2 * k + 1]);
-            gw[m][h][k] = gelu2_lookup(zw[m][h][k], s_gt, &worst);
-          }
-      if (gelu2_any_outside(worst)) {
-  #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 2; ++m)
   #pragma unroll
           for (int h = 0; h < 2; ++h)
   #pragma unroll
-            for (int k = 0; k < 2; ++k) gw[m][h][k] = gelu2_fix(zw[m][h][k], gw[m][h][k]);
-      }
+            for (int k = 0; k < 2; ++k) {
+              zw[m][h][k] = f2bf2(accs[m0 + m][h][2 * k] + bias[h][2 * k],
+                                  accs[m0 + m][h][2 * k + 1] + bias[h][2 * k + 1]);
+              gw[m][h][k] = gelu2_lookup(zw[m][h][k], s_gt, &worst);
+            }
+        if (gelu2_any_outside(worst)) {
   #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int x = x0 + li, y = y0 + yb + m, z = z0 + zl;
-        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-        const long long v = ((long long)z * a.ny + y) * a.nx + x;
+          for (int m = 0; m < 2; ++m)
   #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int o0 = 16 * h + 4 * lg;
+            for (int h = 0; h < 2; ++h)
+  #pragma unroll
+              for (int k = 0; k < 2; ++k) gw[m][h][k] = gelu2_fix(zw[m][h][k], gw[m][h][k]);
+        }
+  #pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int x = x0 + li, y = y0 + yb + m0 + m, z = z0 + zl;
+          if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+          const long long v = ((long long)z * a.ny + y) * a.nx + x;
           if constexpr (EPI == EPI_GELU_Z)
-            *reinterpret_cast<uint2*>(a.z_out + v * CH + o0) = make_uint2(zw[m][h][0], zw[m][h][1]);
-          *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(gw[m][h][0], gw[m][h][1]);
+            *reinterpret_cast<uint4*>(a.z_out + v * CH + 8 * lg) =
+                make_uint4(zw[m][0][0], zw[m][0][1], zw[m][1][0], zw[m][1][1]);
+          *reinterpret_cast<uint4*>(a.a_out + v * CH + 8 * lg) =
+              make_uint4(gw[m][0][0], gw[m][0][1], gw[m][1][0], gw[m][1][1]);
         }
       }
       continue;
     }
+    if constexpr (EPI == EPI_DGELU) {
   #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const f32x4 (&acc)[2] = accs[m];
-      const int yl = yb + m;
-      const int x = x0 + li, y = y0 + yl, z = z0 + zl;
-      if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-      const long long v = ((long long)z * a.ny + y) * a.nx + x;
-  #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int o0 = 16 * h + 4 * lg;
-        unsigned aw2[2] = {0u, 0u};
-        if constexpr (EPI == EPI_DGELU) {
-          const uint2 zp = *reinterpret_cast<const uint2*>(a.zprev + v * CH + o0);
-          const unsigned zz[2] = {zp.x, zp.y};
-  #pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const bf16_t lo = f2bf(acc[h][2 * k] * gelu_prime(__uint_as_float(zz[k] << 16)));
-            const bf16_t hi =
-                f2bf(acc[h][2 * k + 1] * gelu_prime(__uint_as_float(zz[k] & 0xFFFF0000u)));
-            aw2[k] = unsigned(lo) | (unsigned(hi) << 16);
-          }
-        }
-        *reinterpret_cast<uint2*>(a.a_out + v * CH + o0) = make_uint2(aw2[0], aw2[1]);
+      for (int m = 0; m < 4; ++m) {
+        const int x = x0 + li, y = y0 + yb + m, z = z0 + zl;
+        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        store_dgelu(a, ((long long)z * a.ny + y) * a.nx + x, lg, accs[m]);
       }
     }
   }
@@ -616,83 +622,104 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a, int nt
 
 // ----------------------------------------------------------------------------- MFMA 32 -> 1
 // The 32 -> 1 layer (with the residual) with its 27 offsets moved into the GEMM's output: for each
-// halo voxel u, P[u][d] = sum_i W[d][i] a[u][i] on v_mfma_f32_16x16x32_bf16 (A = weights, rows d;
-// B = 16 halo voxels' channels, read straight from memory: 64 contiguous bytes per voxel), then
-// out[v] = c[v] + (sum_d P[v + d][d] + b).  The offsets are taken one z-layer (9 of them) at a
-// time, so P over the 4 halo planes that layer reads (720 voxels, 26 KB) is all the LDS a block
-// needs; each thread sums its voxel's 27 terms in a fixed order.
-constexpr int PO_VOX = TZ * HY * HX;  // 720
-constexpr int PO_GROUPS = PO_VOX / 16;  // 45 MFMA column groups per z-layer
-constexpr int PO_PER_WAVE = (PO_GROUPS + SMALL_THREADS / 64 - 1) / (SMALL_THREADS / 64);  // 6
-static_assert(PO_VOX % 16 == 0, "whole MFMA column groups");
+// voxel u of a halo plane, P[u][d] = sum_i W[d][i] a[u][i] on v_mfma_f32_16x16x32_bf16 (A = the
+// weights, offsets d as rows of two MFMAs; B = 16 voxels' channels, read straight from memory: 64
+// contiguous bytes per voxel), then out[v] = c[v] + (sum_d P[v + d][d] + b).  A block owns a
+// 16 x 16 column of the grid and marches up a range of its z planes: each input plane's P (over
+// the plane's 18 x 18 halo) is computed once, into LDS, and added to the three output planes that
+// plane reaches, whose sums each thread carries in registers; an output plane is complete, and
+// stored, once the plane above it has been added.  The next plane's loads are in flight while a
+// plane is summed.  Every voxel adds its 27 terms in the order (dz, dy, dx).
+constexpr int OX = 16, OY = 16;                                  // output column of a block
+constexpr int OHX = OX + 2, OHY = OY + 2;
+constexpr int O_HALO = OHX * OHY;                                // 324 voxels of a halo plane
+constexpr int O_GROUPS = (O_HALO + 15) / 16;                     // 21 MFMA column groups
+constexpr int O_THREADS = OX * OY;                               // one output column per thread
+constexpr int O_WAVES = O_THREADS / 64;
+constexpr int O_PER_WAVE = (O_GROUPS + O_WAVES - 1) / O_WAVES;   // 6
+constexpr int O_PP = 27;  // P row pitch: odd, so the gathers of a wave's 64 voxels spread over banks
 
-__global__ __launch_bounds__(SMALL_THREADS) void conv_out_mfma(ConvArgs a) {
-  __shared__ float s_p[PO_VOX * 9];
-  const int tid = threadIdx.x;
-  const int ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY;
-  int t = blockIdx.x;
-  const int x0 = (t % ntx) * TX;
-  t /= ntx;
-  const int y0 = (t % nty) * TY;
-  const int z0 = (t / nty) * TZ;
-  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+__global__ __launch_bounds__(O_THREADS) void conv_out_mfma(ConvArgs a, int ncols, int lz) {
+  __shared__ float s_p[O_HALO * O_PP];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int ntx = (a.nx + OX - 1) / OX;
+  const int col = int(blockIdx.x) % ncols, chunk = int(blockIdx.x) / ncols;
+  const int x0 = (col % ntx) * OX, y0 = (col / ntx) * OY;
+  const int z0 = chunk * lz, z1 = z0 + lz < a.nz ? z0 + lz : a.nz;
   const u32x4* gin = static_cast<const u32x4*>(a.in);
-  // A[d_local][i] = W[9 p + d_local][i] for z-layer p, rows 9..15 zero
-  bf16x8 aw[3];
+  // A[R][i] = W[16 q + R][i] for MFMA q, rows past the 27 offsets zero
+  bf16x8 aw[2];
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    u32x4 q = u32x4{0u, 0u, 0u, 0u};
-    if (li < 9) q = *reinterpret_cast<const u32x4*>(a.w + (9 * p + li) * CH + 8 * lg);
-    aw[p] = as_bf16x8(q);
+  for (int q = 0; q < 2; ++q) {
+    const int d = 16 * q + li;
+    u32x4 w = u32x4{0u, 0u, 0u, 0u};
+    if (d < 27) w = *reinterpret_cast<const u32x4*>(a.w + d * CH + 8 * lg);
+    aw[q] = as_bf16x8(w);
   }
-  // global offsets (16-byte chunks) of this lane's halo voxels: group g = wave + 8 k, voxel li
-  long long src[PO_PER_WAVE];
+  // in-plane offsets (16-byte chunks) of this lane's halo voxels: group g = wave + O_WAVES k,
+  // voxel g * 16 + li; slots past the halo load voxel 0 and store nothing
+  long long src[O_PER_WAVE];
 #pragma unroll
-  for (int k = 0; k < PO_PER_WAVE; ++k) {
-    const int g = wave + k * (SMALL_THREADS / 64);
-    const int u = (g < PO_GROUPS ? g : 0) * 16 + li;  // voxel within 4 consecutive halo planes
-    const int hx = u % HX, hy = (u / HX) % HY;
+  for (int k = 0; k < O_PER_WAVE; ++k) {
+    const int u0 = (wave + O_WAVES * k) * 16 + li;
+    const int u = u0 < O_HALO ? u0 : 0;
+    const int hx = u % OHX, hy = u / OHX;
     const long long gx = pmod(x0 + hx - 1, a.nx), gy = pmod(y0 + hy - 1, a.ny);
     src[k] = (gy * a.nx + gx) * 4 + lg;
   }
-  const float bias = a.bias[0];
-  const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
   const long long plane4 = (long long)a.ny * a.nx * 4;
-  float acc = 0.f;
+  u32x4 pre[O_PER_WAVE];
+  auto fetch = [&](int zi) {
+    const long long base = pmod(zi, a.nz) * plane4;
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {  // dz = p - 1: halo planes p .. p + 3
-    u32x4 bq[PO_PER_WAVE];
+    for (int k = 0; k < O_PER_WAVE; ++k) pre[k] = gin[base + src[k]];
+  };
+  const float bias = a.bias[0];
+  const int tx = tid % OX, ty = tid / OX;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < a.nx && y < a.ny;
+  float r_prev = 0.f, r_cur = 0.f, r_next = 0.f;  // sums of out[zi - 1], out[zi], out[zi + 1]
+  fetch(z0 - 1);
+  for (int zi = z0 - 1; zi <= z1; ++zi) {
 #pragma unroll
-    for (int k = 0; k < PO_PER_WAVE; ++k) {
-      const int g = wave + k * (SMALL_THREADS / 64);
+    for (int k = 0; k < O_PER_WAVE; ++k) {
+      const int g = wave + O_WAVES * k;
+      if (g >= O_GROUPS) continue;  // wave-uniform
+      const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[0], as_bf16x8(pre[k]),
+                                                                f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[1], as_bf16x8(pre[k]),
+                                                                f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       const int u = g * 16 + li;
-      const int pz = u / (HX * HY);
-      bq[k] = u32x4{0u, 0u, 0u, 0u};
-      if (g < PO_GROUPS) bq[k] = gin[pmod(z0 + p + pz - 1, a.nz) * plane4 + src[k]];
+      if (u < O_HALO) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {  // D[4 lg + r][li] = P[u][16 q + 4 lg + r]
+          s_p[u * O_PP + 4 * lg + r] = d0[r];
+          if (16 + 4 * lg + r < 27) s_p[u * O_PP + 16 + 4 * lg + r] = d1[r];
+        }
+      }
     }
+    if (zi < z1) fetch(zi + 1);
+    __syncthreads();
+    // plane zi reaches out[zi - dz] through the offsets of layer dz
 #pragma unroll
-    for (int k = 0; k < PO_PER_WAVE; ++k) {
-      const int g = wave + k * (SMALL_THREADS / 64);
-      if (g >= PO_GROUPS) continue;  // wave-uniform
-      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          aw[p], as_bf16x8(bq[k]), f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      const int u = g * 16 + li;
+    for (int dzi = 0; dzi < 3; ++dzi) {
+      float& r = dzi == 0 ? r_next : (dzi == 1 ? r_cur : r_prev);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)  // D[4 lg + r][li] = P[u][d_local]
-        if (4 * lg + r < 9) s_p[u * 9 + 4 * lg + r] = d[r];
+      for (int dyi = 0; dyi < 3; ++dyi)
+#pragma unroll
+        for (int dxi = 0; dxi < 3; ++dxi)
+          r += s_p[((ty + dyi) * OHX + tx + dxi) * O_PP + 9 * dzi + 3 * dyi + dxi];
     }
-    __syncthreads();
-#pragma unroll
-    for (int dyi = 0; dyi < 3; ++dyi)
-#pragma unroll
-      for (int dxi = 0; dxi < 3; ++dxi)
-        acc += s_p[((lz * HY + ly + dyi) * HX + lx + dxi) * 9 + 3 * dyi + dxi];
-    __syncthreads();
+    __syncthreads();  // the next plane rewrites P
+    const int zo = zi - 1;
+    if (zo >= z0 && own) {
+      const long long v = ((long long)zo * a.ny + y) * a.nx + x;
+      a.out[v] = a.c[v] + (r_prev + bias);
+    }
+    r_prev = r_cur;
+    r_cur = r_next;
+    r_next = 0.f;
   }
-  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-  if (x >= a.nx || y >= a.ny || z >= a.nz) return;
-  const long long v = ((long long)z * a.ny + y) * a.nx + x;
-  a.out[v] = a.c[v] + (acc + bias);
 }
 
 // ----------------------------------------------------------------------------- weight gradient
@@ -1210,7 +1237,6 @@ long long g_num_cus = 256;  // set from the device at evx_surrogate_create
 hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
   const long long nt = (long long)((a.nx + TX - 1) / TX) * ((a.ny + TY - 1) / TY) *
                        ((a.nz + TZ - 1) / TZ);
-  const unsigned small_grid = unsigned(nt);
   const int ntiles = int(nt);
   // the 1 -> 32 kernel is persistent too: four blocks per CU (its table and halo take 12 KB)
   const unsigned in_grid = unsigned(nt < 4 * g_num_cus ? nt : 4 * g_num_cus);
@@ -1231,7 +1257,15 @@ hipError_t launch_conv(int kind, int epi, const ConvArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((conv_in_mfma<false, EPI_GELU>), dim3(in_grid), dim3(SMALL_THREADS), 0,
                          s, a, ntiles);
   } else if (kind == K_OUT1) {
-    hipLaunchKernelGGL(conv_out_mfma, dim3(small_grid), dim3(SMALL_THREADS), 0, s, a);
+    // columns of 16 x 16, each marching up lz planes: long runs (few halo planes re-read), but
+    // at least about four blocks per CU
+    const long long ncols = (long long)((a.nx + OX - 1) / OX) * ((a.ny + OY - 1) / OY);
+    long long lz = (a.nz * ncols + 4 * g_num_cus - 1) / (4 * g_num_cus);
+    lz = lz < 2 ? 2 : (lz > a.nz ? a.nz : lz);
+    const long long grid = ncols * ((a.nz + lz - 1) / lz);
+    if (grid >= (1LL << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(conv_out_mfma, dim3(unsigned(grid)), dim3(O_THREADS), 0, s, a, int(ncols),
+                       int(lz));
   } else {  // backward data of the last layer: FP32 dY -> bf16 dZ
     hipLaunchKernelGGL((conv_in_mfma<true, EPI_DGELU>), dim3(in_grid), dim3(SMALL_THREADS), 0, s,
                        a, ntiles);
