@@ -546,16 +546,17 @@ __global__ __launch_bounds__(SMALL_THREADS) void conv_in_mfma(ConvArgs a, int nt
   #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int j = 2 * k + e;
-          float v = 0.f;
-          if (ok[j]) {
-            if constexpr (IN_F32) v = s_h[base + rel[j]];
-            else v = bf2f(s_h[base + rel[j]]);
-          }
+          if constexpr (IN_F32) {
+            float v = ok[j] ? s_h[base + rel[j]] : 0.f;
   #pragma unroll
-          for (int n = 0; n < NT; ++n) {
-            const bf16_t hb = f2bf(v);
-            v -= bf2f(hb);
-            (e ? hi : lo)[n] = hb;
+            for (int n = 0; n < NT; ++n) {
+              const bf16_t hb = f2bf(v);
+              v -= bf2f(hb);
+              (e ? hi : lo)[n] = hb;
+            }
+          } else {
+            // BF16 input is its own single term: its bits, zero in the padded slots
+            (e ? hi : lo)[0] = unsigned(s_h[base + rel[j]]) & (ok[j] ? 0xFFFFu : 0u);
           }
         }
   #pragma unroll
