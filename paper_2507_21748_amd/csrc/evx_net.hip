@@ -14,7 +14,8 @@
 //   conv_in_mfma  1 -> 32 layer (and the last layer's backward data) as a GEMM over the 27
 //                 offsets: D[o][v] = sum_d W[d][o] x[v + d]; GELU by a BF16 table.
 //   conv_out_mfma 32 -> 1 layer: P[u][d] = sum_i W[d][i] a[u][i] on MFMA, then
-//                 out[v] = c[v] + sum_d P[v + d][d] + b.
+//                 out[v] = c[v] + sum_d P[v + d][d] + b; blocks own 16x16 columns and march up z,
+//                 computing each halo plane's P once.
 //   wgrad32_mfma  dW[d,o,i] = sum_v gz[v,o] x[v+d,i] and db of the 32 -> 32 layers as MFMA GEMMs
 //   wgrad1_mfma   over voxels; wgrad1_mfma the same for the 1 -> 32 and 32 -> 1 layers; per-block
 //                 partial sums with a fixed-order reduction (bit-reproducible).
