@@ -62,6 +62,27 @@ hipError_t evx_launch_vm_rhs(const VmStencilArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(VF_THREADS) void vm_fused_kernel(VmStencilArgs a, int lz) {
+  __shared__ float lds[VF_LDS];
+  vm_fused_body(a, lz, threadIdx.x, blockIdx.x, lds);
+}
+
+hipError_t evx_launch_vm_fused(const VmStencilArgs& a, hipStream_t s) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+  }
+  const int lz = vm_fused_lz(a, cus);
+  const long long ncols = (long long)((a.nx + VF_X - 1) / VF_X) * ((a.ny + VF_Y - 1) / VF_Y);
+  const long long grid = ncols * ((a.nz + lz - 1) / lz);
+  if (grid >= (1LL << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(vm_fused_kernel, dim3(unsigned(grid)), dim3(VF_THREADS), 0, s, a, lz);
+  return hipGetLastError();
+}
+
 hipError_t evx_launch_gs_react(const GsReactArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(gs_react_kernel, dim3(AUX_BLOCKS), dim3(AUX_THREADS), 0, s, a);
   return hipGetLastError();

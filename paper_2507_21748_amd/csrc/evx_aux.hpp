@@ -339,6 +339,109 @@ EVX_DEV void vm_rhs_body(const VmStencilArgs& a, int tid, int bx, int by, int bz
   a.out[i] = a.c_flux * acc;
 }
 
+// mu and div(M grad mu) in one pass, for grids periodic on every axis: a block owns a VF_X x VF_Y
+// column and marches up lz of its z planes, with phi (2-point xy halo) and mu (1-point halo) held
+// in LDS rings of 4 and 3 planes.  Per plane z it loads phi of plane z + 2, evaluates mu on plane
+// z + 1 and the fluxes on plane z: each value is vm_mu_body's and vm_rhs_body's expression with
+// the neighbours in the same order, so the results are bitwise theirs, and mu never leaves LDS
+// (8 bytes per voxel instead of 20).
+constexpr int VF_X = 32, VF_Y = 16, VF_THREADS = VF_X * VF_Y;
+constexpr int VF_PX = VF_X + 4, VF_PY = VF_Y + 4, VF_PP = VF_PX * VF_PY;  // phi plane: 36 x 20
+constexpr int VF_MX = VF_X + 2, VF_MY = VF_Y + 2, VF_MP = VF_MX * VF_MY;  // mu plane: 34 x 18
+constexpr int VF_LDS = 4 * VF_PP + 3 * VF_MP;                              // floats
+
+EVX_DEV int vf_mod(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// z planes per block of the fused pass: long runs (few re-read halo planes), but about four
+// blocks per CU
+inline int vm_fused_lz(const VmStencilArgs& a, int cus) {
+  const long long ncols = (long long)((a.nx + VF_X - 1) / VF_X) * ((a.ny + VF_Y - 1) / VF_Y);
+  long long lz = (a.nz * ncols + 4LL * cus - 1) / (4LL * cus);
+  if (lz < 4) lz = 4;
+  if (lz > a.nz) lz = a.nz;
+  return int(lz);
+}
+
+// Launch: ceil(nx / VF_X) ceil(ny / VF_Y) columns times ceil(nz / lz) z ranges, VF_THREADS each.
+EVX_DEV void vm_fused_body(const VmStencilArgs& a, int lz, int tid, int bid, float* lds) {
+  const int ntx = (a.nx + VF_X - 1) / VF_X, nty = (a.ny + VF_Y - 1) / VF_Y;
+  const int ncols = ntx * nty;
+  const int col = bid % ncols, chunk = bid / ncols;
+  const int x0 = (col % ntx) * VF_X, y0 = (col / ntx) * VF_Y;
+  const int z0 = chunk * lz, z1 = z0 + lz < a.nz ? z0 + lz : a.nz;
+  float* const P = lds;               // [4][VF_PP]
+  float* const M = lds + 4 * VF_PP;   // [3][VF_MP]
+  auto pl = [&](int z) { return P + vf_mod(z, 4) * VF_PP; };
+  auto ml = [&](int z) { return M + vf_mod(z, 3) * VF_MP; };
+  // a phi plane travels through registers: its loads are issued a plane ahead of the LDS
+  // writes, every lane always loads (clamped index), and the flux stores below are buffer
+  // stores issued by every lane, so the compiler waits for the loads alone
+  constexpr int PIT = (VF_PP + VF_THREADS - 1) / VF_THREADS;
+  int src_xy[PIT];
+  for (int k = 0; k < PIT; ++k) {
+    const int i0 = tid + k * VF_THREADS, i = i0 < VF_PP ? i0 : 0;
+    src_xy[k] = vf_mod(y0 + i / VF_PX - 2, a.ny) * a.nx + vf_mod(x0 + i % VF_PX - 2, a.nx);
+  }
+  const int plane = a.nx * a.ny;
+  float nxt[PIT];
+  auto fetch_phi = [&](int z) {
+    const float* src = a.phi + vf_mod(z, a.nz) * plane;
+    for (int k = 0; k < PIT; ++k) nxt[k] = src[src_xy[k]];
+  };
+  auto put_phi = [&](int z) {
+    float* dst = pl(z);
+    for (int k = 0; k < PIT; ++k)
+      if (tid + k * VF_THREADS < VF_PP) dst[tid + k * VF_THREADS] = nxt[k];
+  };
+  auto calc_mu = [&](int z) {
+    const float *pc = pl(z), *pu = pl(z + 1), *pd = pl(z - 1);
+    float* dst = ml(z);
+    for (int i = tid; i < VF_MP; i += VF_THREADS) {
+      const int c = (i / VF_MX + 1) * VF_PX + i % VF_MX + 1;  // the point in the phi plane
+      const float p = pc[c];
+      float s = 0.0f;
+      s += pc[c + 1];
+      s += pc[c - 1];
+      s += pc[c + VF_PX];
+      s += pc[c - VF_PX];
+      s += pu[c];
+      s += pd[c];
+      dst[i] = a.c_g * p * (1.0f - p) * (1.0f - 2.0f * p) - a.c_lap * (s - 6.0f * p);
+    }
+  };
+  const int tx = tid % VF_X, ty = tid / VF_X;
+  const int pc0 = (ty + 2) * VF_PX + tx + 2, mc0 = (ty + 1) * VF_MX + tx + 1;
+  const bool own = x0 + tx < a.nx && y0 + ty < a.ny;
+  const unsigned out_off = own ? unsigned(((y0 + ty) * a.nx + x0 + tx) * 4) : 0xfffffff0u;
+  for (int z = z0 - 2; z <= z0 + 1; ++z) {
+    fetch_phi(z);
+    put_phi(z);
+  }
+  fetch_phi(z0 + 2);
+  evx_sync();
+  calc_mu(z0 - 1);
+  calc_mu(z0);
+  for (int z = z0; z < z1; ++z) {
+    evx_sync();  // the previous plane's fluxes are done with phi plane z - 2 and mu plane z - 2
+    put_phi(z + 2);
+    fetch_phi(z + 3);  // past the range on the last planes: a wrapped plane, loaded and unused
+    evx_sync();
+    calc_mu(z + 1);
+    evx_sync();
+    const float *pc = pl(z), *pu = pl(z + 1), *pd = pl(z - 1);
+    const float *mc = ml(z), *mu_ = ml(z + 1), *md = ml(z - 1);
+    const float p = pc[pc0], m = p * (1.0f - p), u = mc[mc0];
+    const float qs[6] = {pc[pc0 + 1], pc[pc0 - 1], pc[pc0 + VF_PX], pc[pc0 - VF_PX], pu[pc0], pd[pc0]};
+    const float us[6] = {mc[mc0 + 1], mc[mc0 - 1], mc[mc0 + VF_MX], mc[mc0 - VF_MX], mu_[mc0], md[mc0]};
+    float acc = 0.0f;
+    for (int d = 0; d < 6; ++d) acc += (m + qs[d] * (1.0f - qs[d])) * (us[d] - u);
+    evx_buf_store1(evx_make_buf(a.out + z * plane, unsigned(plane) * 4u), out_off, a.c_flux * acc);
+  }
+}
+
 // lam <- lam - f''(c) v  (f'' = 3c^2 - 1)
 struct CombineArgs {
   float* lam;

@@ -46,6 +46,10 @@ inline void evx_buf_store2(evx_buf r, unsigned off, float2 v) {
   if (off >= r.nbytes || r.nbytes - off < 8) return;
   __builtin_memcpy(r.base + off, &v, 8);
 }
+inline void evx_buf_store1(evx_buf r, unsigned off, float v) {
+  if (off >= r.nbytes || r.nbytes - off < 4) return;
+  __builtin_memcpy(r.base + off, &v, 4);
+}
 
 #else
 #include <hip/hip_runtime.h>
@@ -76,6 +80,9 @@ __device__ __forceinline__ void evx_buf_store2(evx_buf r, unsigned off, float2 v
   u.x = __float_as_uint(v.x);
   u.y = __float_as_uint(v.y);
   __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, 0);
+}
+__device__ __forceinline__ void evx_buf_store1(evx_buf r, unsigned off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
 }
 #endif
 

@@ -29,6 +29,7 @@ hipError_t evx_launch_finite(const FiniteArgs& a, hipStream_t s);
 hipError_t evx_launch_gs_update(const GsUpdateArgs& a, hipStream_t s);
 hipError_t evx_launch_vm_mu(const VmStencilArgs& a, hipStream_t s);
 hipError_t evx_launch_vm_rhs(const VmStencilArgs& a, hipStream_t s);
+hipError_t evx_launch_vm_fused(const VmStencilArgs& a, hipStream_t s);
 
 // Records the first launch error; the schedule keeps enqueuing nothing after one.
 struct HipLauncher {
@@ -95,6 +96,9 @@ struct HipLauncher {
   }
   void vm_rhs(const VmStencilArgs& a) {
     if (err == hipSuccess && !bad_len) err = evx_launch_vm_rhs(a, stream);
+  }
+  void vm_fused(const VmStencilArgs& a) {
+    if (err == hipSuccess && !bad_len) err = evx_launch_vm_fused(a, stream);
   }
   void row(int n, int bc, int mode, const RowArgs& a) {
     if (err != hipSuccess || bad_len) return;

@@ -182,6 +182,14 @@ struct EmuLauncher {
     grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
           [&](int tid, int bx, int by, int bz) { vm_rhs_body(a, tid, bx, by, bz); });
   }
+  void vm_fused(const VmStencilArgs& a) {
+    const int lz = vm_fused_lz(a, 4);  // a small device: several z ranges per column
+    const int ncols = ((a.nx + VF_X - 1) / VF_X) * ((a.ny + VF_Y - 1) / VF_Y);
+    const int nblk = ncols * ((a.nz + lz - 1) / lz);
+    run_grid(nblk, VF_THREADS, (VF_LDS + 1) / 2, [&](int tid, int bid, int, float2* lds) {
+      vm_fused_body(a, lz, tid, bid, reinterpret_cast<float*>(lds));
+    });
+  }
   void plane(int ny, const PlaneArgs& a) {
     auto go = [&](auto ny_) {
       constexpr int NY = decltype(ny_)::value;

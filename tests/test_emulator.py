@@ -334,13 +334,8 @@ def test_emulated_gray_scott_matches_oracle(asan, shape, bc, scheme):
     assert _rel(uo, ur) <= 1e-6 and _rel(vo, vr) <= 1e-6
 
 
-@pytest.mark.parametrize("shape,bc,scheme", [((16, 12, 16), "periodic", "spectral"),
-                                             ((8, 24, 16), "zero_flux", "stencil7"),
-                                             ((12, 20, 16), ("zero_flux", "periodic",
-                                                             "periodic"), "stencil7")])
-def test_emulated_variable_mobility_matches_oracle(asan, shape, bc, scheme):
-    """The variable-mobility schedule (mu and face-flux stencil kernels, forward transform,
-    spectral multiplier, inverse transform, add) against the oracle's increment steps."""
+def _vm_emulated(exe, shape, bc, scheme):
+    """Three variable-mobility steps in the emulator and in the oracle: (emulated, oracle, start)."""
     from oracle import ch_varmob as vm
     p = vm.VMParams(dt=0.5, D0=1.2, gamma0=0.9, eps=1.8, M0=0.3)
     phi0 = quench_field(shape, 0.5, 0.2, seed=41)
@@ -350,13 +345,33 @@ def test_emulated_variable_mobility_matches_oracle(asan, shape, bc, scheme):
         1000 + 100 * code[bc[2]] + 10 * code[bc[1]] + code[bc[0]]
     with tempfile.TemporaryDirectory() as d:
         phi0.tofile(os.path.join(d, "phi"))
-        r = subprocess.run([asan, "vm", str(nx), str(ny), str(nz), str(bcarg),
+        r = subprocess.run([exe, "vm", str(nx), str(ny), str(nz), str(bcarg),
                             str(int(scheme == "stencil7")), "1.0", repr(p.dt), repr(p.D0),
                             repr(p.gamma0), repr(p.eps), repr(p.M0), "3",
                             os.path.join(d, "phi"), os.path.join(d, "out")],
                            capture_output=True, text=True, timeout=600)
         assert r.returncode == 0, r.stderr[-4000:]
         out = np.fromfile(os.path.join(d, "out"), np.float32).reshape(shape)
-    ref = vm.vm_run(phi0, 3, p, bc, scheme)
+    return out, vm.vm_run(phi0, 3, p, bc, scheme), phi0
+
+
+@pytest.mark.parametrize("shape,bc,scheme", [((16, 12, 16), "periodic", "spectral"),
+                                             ((20, 48, 64), "periodic", "stencil7"),
+                                             ((8, 24, 16), "zero_flux", "stencil7"),
+                                             ((12, 20, 16), ("zero_flux", "periodic",
+                                                             "periodic"), "stencil7")])
+def test_emulated_variable_mobility_matches_oracle(asan, shape, bc, scheme):
+    """The variable-mobility schedule against the oracle's increment steps: on grids periodic
+    on every axis the fused z-marching stencil pass (one grid smaller than a block's column, one
+    with several columns and a short last z range), else the mu and face-flux stencil kernels;
+    then the forward transform, spectral multiplier, inverse transform and add."""
+    out, ref, phi0 = _vm_emulated(asan, shape, bc, scheme)
     assert np.max(np.abs(ref - phi0)) > 1e-3  # the steps moved the field
+    assert _rel(out, ref) <= 1e-6
+
+
+def test_emulated_fused_stencil_race_free(tsan):
+    """The fused stencil pass's LDS rings under the thread sanitizer (every plane's three
+    barriers)."""
+    out, ref, _ = _vm_emulated(tsan, (20, 48, 64), "periodic", "stencil7")
     assert _rel(out, ref) <= 1e-6
