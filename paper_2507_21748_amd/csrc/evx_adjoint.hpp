@@ -182,18 +182,11 @@ void sched_varmob(L& l, const Geom& g, const TablePtrs& t, float* phi, const Adj
                   const VmCoef& co, int nsteps, int remap) {
   const int per = (g.bc == BC_PERIODIC ? 1 : 0) | (g.bcy == BC_PERIODIC ? 2 : 0) |
                   (g.bcz == BC_PERIODIC ? 4 : 0);
-  const VmStencilArgs mu{phi, nullptr, b.v, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
-  const VmStencilArgs rhs{phi, b.v, b.v2, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
   const StepCoef zc{0.0f, co.c4, co.dt};  // the z pass reads dt from dt_m, c4 from dt_m_kappa
-  // all-periodic grids: mu and the fluxes in one z-marching pass (mu stays in LDS)
-  const VmStencilArgs fused{phi, nullptr, b.v2, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
+  // mu and the fluxes in one z-marching pass (mu stays in LDS)
+  const VmStencilArgs fused{phi, b.v2, g.nx, g.ny, g.nz, per, co.c_g, co.c_lap, co.c_flux};
   for (int n = 0; n < nsteps; ++n) {
-    if (per == 7) {
-      l.vm_fused(fused);
-    } else {
-      l.vm_mu(mu);
-      l.vm_rhs(rhs);
-    }
+    l.vm_fused(fused);
     l.row(g.row_len, g.bc, ROW_FWD, x_args(g, t, nullptr, b.v2, b.A, nullptr));
     l.col(g.fy, g.bcy, COL_FWD, y_args(g, t, b.A, b.A, remap));
     l.col(g.fz, g.bcz, COL_Z_VM, z_args(g, t, b.A, b.A, nullptr, zc, remap));

@@ -40,28 +40,6 @@ __global__ __launch_bounds__(AUX_THREADS) void gs_update_kernel(GsUpdateArgs a) 
   gs_update_body(a, threadIdx.x, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(VM_BX * VM_BY) void vm_mu_kernel(VmStencilArgs a) {
-  vm_mu_body(a, threadIdx.x, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
-__global__ __launch_bounds__(VM_BX * VM_BY) void vm_rhs_kernel(VmStencilArgs a) {
-  vm_rhs_body(a, threadIdx.x, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
-static dim3 vm_grid(const VmStencilArgs& a) {
-  return dim3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz);
-}
-
-hipError_t evx_launch_vm_mu(const VmStencilArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(vm_mu_kernel, vm_grid(a), dim3(VM_BX * VM_BY), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t evx_launch_vm_rhs(const VmStencilArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(vm_rhs_kernel, vm_grid(a), dim3(VM_BX * VM_BY), 0, s, a);
-  return hipGetLastError();
-}
-
 __global__ __launch_bounds__(VF_THREADS) void vm_fused_kernel(VmStencilArgs a, int lz) {
   __shared__ float lds[VF_LDS];
   vm_fused_body(a, lz, threadIdx.x, blockIdx.x, lds);

@@ -275,13 +275,12 @@ EVX_DEV void gs_update_body(const GsUpdateArgs& a, int tid, int bid, int nblk) {
 // Variable-mobility Cahn-Hilliard (paper, appendix "Phase transformations of first and second
 // order", eq. cahn-hilliard, stepped as in "Semi-implicit timestepping"): the finite-difference
 // right-hand side div(M grad mu), mu = gamma0 g(phi) - 2 gamma0 eps lap phi, M = D0 phi (1 - phi),
-// g = (18 / eps) phi (1 - phi) (1 - 2 phi), in two real-space passes over the natural (z, y, x)
+// g = (18 / eps) phi (1 - phi) (1 - 2 phi), in one real-space pass over the natural (z, y, x)
 // layout.  Periodic axes wrap; zero-flux axes mirror the edge cell into its ghost, so mu's ghost
 // equals the edge value and a boundary face carries no flux.
 struct VmStencilArgs {
   const float* phi;
-  const float* mu;  // second pass only
-  float* out;       // mu (first pass) or div(M grad mu) (second pass)
+  float* out;       // div(M grad mu)
   int nx, ny, nz;
   int per;          // periodic axes: bit 0 x, bit 1 y, bit 2 z
   float c_g;        // gamma0 * 18 / eps
@@ -289,62 +288,16 @@ struct VmStencilArgs {
   float c_flux;     // D0 / (2 dx^2): the face mobility is the mean of the two cells'
 };
 
-// Stencil blocks: 64 x 4 threads over (x, y) of one z plane; launch grid
-// (ceil(nx / 64), ceil(ny / 4), nz), one voxel per thread.
-constexpr int VM_BX = 64, VM_BY = 4;
-
-EVX_DEV int vm_wrap(int j, int n, bool per) {
-  if (per) return j < 0 ? j + n : (j >= n ? j - n : j);
-  return j < 0 ? 0 : (j >= n ? n - 1 : j);
-}
-
-// Voxel i = (z ny + y) nx + x of thread tid in block (bx, by, bz) and its six neighbours;
-// false for threads past the grid's x or y extent.  Offsets are 32-bit: a grid holds at most
-// 1024^3 = 2^30 voxels.
-EVX_DEV bool vm_voxel(const VmStencilArgs& a, int tid, int bx, int by, int bz, int& i, int nb[6]) {
-  const int x = bx * VM_BX + tid % VM_BX, y = by * VM_BY + tid / VM_BX;
-  if (x >= a.nx || y >= a.ny) return false;
-  const int plane = a.nx * a.ny;
-  const int zo = bz * plane;
-  const int row = zo + y * a.nx;
-  const int xy = y * a.nx + x;
-  i = row + x;
-  nb[0] = row + vm_wrap(x + 1, a.nx, a.per & 1);
-  nb[1] = row + vm_wrap(x - 1, a.nx, a.per & 1);
-  nb[2] = zo + vm_wrap(y + 1, a.ny, a.per & 2) * a.nx + x;
-  nb[3] = zo + vm_wrap(y - 1, a.ny, a.per & 2) * a.nx + x;
-  nb[4] = vm_wrap(bz + 1, a.nz, a.per & 4) * plane + xy;
-  nb[5] = vm_wrap(bz - 1, a.nz, a.per & 4) * plane + xy;
-  return true;
-}
-
-EVX_DEV void vm_mu_body(const VmStencilArgs& a, int tid, int bx, int by, int bz) {
-  int i, nb[6];
-  if (!vm_voxel(a, tid, bx, by, bz, i, nb)) return;
-  const float p = a.phi[i];
-  float s = 0.0f;
-  for (int d = 0; d < 6; ++d) s += a.phi[nb[d]];
-  a.out[i] = a.c_g * p * (1.0f - p) * (1.0f - 2.0f * p) - a.c_lap * (s - 6.0f * p);
-}
-
-EVX_DEV void vm_rhs_body(const VmStencilArgs& a, int tid, int bx, int by, int bz) {
-  int i, nb[6];
-  if (!vm_voxel(a, tid, bx, by, bz, i, nb)) return;
-  const float p = a.phi[i], m = p * (1.0f - p), u = a.mu[i];
-  float acc = 0.0f;
-  for (int d = 0; d < 6; ++d) {
-    const float q = a.phi[nb[d]];
-    acc += (m + q * (1.0f - q)) * (a.mu[nb[d]] - u);
-  }
-  a.out[i] = a.c_flux * acc;
-}
-
-// mu and div(M grad mu) in one pass, for grids periodic on every axis: a block owns a VF_X x VF_Y
-// column and marches up lz of its z planes, with phi (2-point xy halo) and mu (1-point halo) held
+// mu and div(M grad mu) in one pass: a block owns a VF_X x VF_Y column and marches up lz of its
+// z planes, with phi (2-point xy halo) and mu (1-point halo) held
 // in LDS rings of 4 and 3 planes.  Per plane z it loads phi of plane z + 2, evaluates mu on plane
-// z + 1 and the fluxes on plane z: each value is vm_mu_body's and vm_rhs_body's expression with
-// the neighbours in the same order, so the results are bitwise theirs, and mu never leaves LDS
-// (8 bytes per voxel instead of 20).
+// z + 1 and the fluxes on plane z:
+//   mu = c_g p (1 - p)(1 - 2 p) - c_lap (sum of the 6 neighbours' phi - 6 p),
+//   div(M grad mu) = c_flux sum_faces (p (1 - p) + q (1 - q)) (mu_q - mu_p),
+// the neighbours taken in the order +x, -x, +y, -y, +z, -z; mu never leaves LDS (8 bytes per
+// voxel).  On a zero-flux axis phi is loaded clamped (the ghost is the edge cell) and mu at a
+// point past the grid is evaluated at the clamped point, i.e. it is the edge cell's mu, so the
+// boundary face carries no flux.
 constexpr int VF_X = 32, VF_Y = 16, VF_THREADS = VF_X * VF_Y;
 constexpr int VF_PX = VF_X + 4, VF_PY = VF_Y + 4, VF_PP = VF_PX * VF_PY;  // phi plane: 36 x 20
 constexpr int VF_MX = VF_X + 2, VF_MY = VF_Y + 2, VF_MP = VF_MX * VF_MY;  // mu plane: 34 x 18
@@ -353,6 +306,10 @@ constexpr int VF_LDS = 4 * VF_PP + 3 * VF_MP;                              // fl
 EVX_DEV int vf_mod(int v, int n) {
   const int r = v % n;
   return r < 0 ? r + n : r;
+}
+// grid index of point v on an axis of n points: periodic wrap, or the zero-flux clamp
+EVX_DEV int vf_map(int v, int n, bool per) {
+  return per ? vf_mod(v, n) : (v < 0 ? 0 : (v >= n ? n - 1 : v));
 }
 
 // z planes per block of the fused pass: long runs (few re-read halo planes), but about four
@@ -381,14 +338,15 @@ EVX_DEV void vm_fused_body(const VmStencilArgs& a, int lz, int tid, int bid, flo
   // stores issued by every lane, so the compiler waits for the loads alone
   constexpr int PIT = (VF_PP + VF_THREADS - 1) / VF_THREADS;
   int src_xy[PIT];
+  const bool px = a.per & 1, py = a.per & 2, pz = a.per & 4;
   for (int k = 0; k < PIT; ++k) {
     const int i0 = tid + k * VF_THREADS, i = i0 < VF_PP ? i0 : 0;
-    src_xy[k] = vf_mod(y0 + i / VF_PX - 2, a.ny) * a.nx + vf_mod(x0 + i % VF_PX - 2, a.nx);
+    src_xy[k] = vf_map(y0 + i / VF_PX - 2, a.ny, py) * a.nx + vf_map(x0 + i % VF_PX - 2, a.nx, px);
   }
   const int plane = a.nx * a.ny;
   float nxt[PIT];
   auto fetch_phi = [&](int z) {
-    const float* src = a.phi + vf_mod(z, a.nz) * plane;
+    const float* src = a.phi + vf_map(z, a.nz, pz) * plane;
     for (int k = 0; k < PIT; ++k) nxt[k] = src[src_xy[k]];
   };
   auto put_phi = [&](int z) {
@@ -397,10 +355,15 @@ EVX_DEV void vm_fused_body(const VmStencilArgs& a, int lz, int tid, int bid, flo
       if (tid + k * VF_THREADS < VF_PP) dst[tid + k * VF_THREADS] = nxt[k];
   };
   auto calc_mu = [&](int z) {
-    const float *pc = pl(z), *pu = pl(z + 1), *pd = pl(z - 1);
+    const int zc = pz ? z : vf_map(z, a.nz, false);
+    const float *pc = pl(zc), *pu = pl(zc + 1), *pd = pl(zc - 1);
     float* dst = ml(z);
     for (int i = tid; i < VF_MP; i += VF_THREADS) {
-      const int c = (i / VF_MX + 1) * VF_PX + i % VF_MX + 1;  // the point in the phi plane
+      // the point in the phi plane (clamped into the grid along zero-flux axes)
+      const int gx = x0 + i % VF_MX - 1, gy = y0 + i / VF_MX - 1;
+      const int mx = i % VF_MX + (px ? 0 : vf_map(gx, a.nx, false) - gx);
+      const int my = i / VF_MX + (py ? 0 : vf_map(gy, a.ny, false) - gy);
+      const int c = (my + 1) * VF_PX + mx + 1;
       const float p = pc[c];
       float s = 0.0f;
       s += pc[c + 1];

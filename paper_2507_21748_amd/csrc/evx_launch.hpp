@@ -27,8 +27,6 @@ hipError_t evx_launch_combine(const CombineArgs& a, hipStream_t s);
 hipError_t evx_launch_gs_react(const GsReactArgs& a, hipStream_t s);
 hipError_t evx_launch_finite(const FiniteArgs& a, hipStream_t s);
 hipError_t evx_launch_gs_update(const GsUpdateArgs& a, hipStream_t s);
-hipError_t evx_launch_vm_mu(const VmStencilArgs& a, hipStream_t s);
-hipError_t evx_launch_vm_rhs(const VmStencilArgs& a, hipStream_t s);
 hipError_t evx_launch_vm_fused(const VmStencilArgs& a, hipStream_t s);
 
 // Records the first launch error; the schedule keeps enqueuing nothing after one.
@@ -90,12 +88,6 @@ struct HipLauncher {
   }
   void gs_update(const GsUpdateArgs& a) {
     if (err == hipSuccess && !bad_len) err = evx_launch_gs_update(a, stream);
-  }
-  void vm_mu(const VmStencilArgs& a) {
-    if (err == hipSuccess && !bad_len) err = evx_launch_vm_mu(a, stream);
-  }
-  void vm_rhs(const VmStencilArgs& a) {
-    if (err == hipSuccess && !bad_len) err = evx_launch_vm_rhs(a, stream);
   }
   void vm_fused(const VmStencilArgs& a) {
     if (err == hipSuccess && !bad_len) err = evx_launch_vm_fused(a, stream);

@@ -166,22 +166,6 @@ struct EmuLauncher {
       gs_update_body(a, tid, bid, nb);
     });
   }
-  // The stencil and update kernels launch 3D grids (gx, gy, gz); block bid runs as
-  // (bid % gx, bid / gx % gy, bid / (gx gy)).
-  template <class Body>
-  static void grid3(int gx, int gy, int gz, int threads, Body body) {
-    run_grid(gx * gy * gz, threads, 1, [&](int tid, int bid, int, float2*) {
-      body(tid, bid % gx, bid / gx % gy, bid / (gx * gy));
-    });
-  }
-  void vm_mu(const VmStencilArgs& a) {
-    grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
-          [&](int tid, int bx, int by, int bz) { vm_mu_body(a, tid, bx, by, bz); });
-  }
-  void vm_rhs(const VmStencilArgs& a) {
-    grid3((a.nx + VM_BX - 1) / VM_BX, (a.ny + VM_BY - 1) / VM_BY, a.nz, VM_BX * VM_BY,
-          [&](int tid, int bx, int by, int bz) { vm_rhs_body(a, tid, bx, by, bz); });
-  }
   void vm_fused(const VmStencilArgs& a) {
     const int lz = vm_fused_lz(a, 4);  // a small device: several z ranges per column
     const int ncols = ((a.nx + VF_X - 1) / VF_X) * ((a.ny + VF_Y - 1) / VF_Y);
