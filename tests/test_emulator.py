@@ -361,10 +361,10 @@ def _vm_emulated(exe, shape, bc, scheme):
                                              ((12, 20, 16), ("zero_flux", "periodic",
                                                              "periodic"), "stencil7")])
 def test_emulated_variable_mobility_matches_oracle(asan, shape, bc, scheme):
-    """The variable-mobility schedule against the oracle's increment steps: on grids periodic
-    on every axis the fused z-marching stencil pass (one grid smaller than a block's column, one
-    with several columns and a short last z range), else the mu and face-flux stencil kernels;
-    then the forward transform, spectral multiplier, inverse transform and add."""
+    """The variable-mobility schedule against the oracle's increment steps: the fused z-marching
+    stencil pass (one grid smaller than a block's column, one with several columns and a short
+    last z range; zero-flux axes with their clamped ghosts), then the forward transform, spectral
+    multiplier, inverse transform and add."""
     out, ref, phi0 = _vm_emulated(asan, shape, bc, scheme)
     assert np.max(np.abs(ref - phi0)) > 1e-3  # the steps moved the field
     assert _rel(out, ref) <= 1e-6
