@@ -314,7 +314,7 @@ def gray_scott_workload(evx, torch, n: int = 256, steps: int = 100):
 
 def varmob_workload(evx, torch, n: int = 256, steps: int = 100):
     """The variable-mobility Cahn-Hilliard step (M = D0 phi (1 - phi)) on a 256^3 periodic
-    spectral grid, phi a 0.5 +- 0.2 quench: ms per step (two stencil kernels, forward x and y,
+    spectral grid, phi a 0.5 +- 0.2 quench: ms per step (the fused stencil pass, forward x and y,
     the z pass with the multiplier, inverse y, the inverse x pass that adds to phi)."""
     from paper_2507_21748_amd.inputs import quench_field
     shape = (n, n, n)

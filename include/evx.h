@@ -292,7 +292,7 @@ evx_status evx_rd_step(evx_plan* plan, float* c, int nsteps, const evx_rd_params
  * K2 follows the plan's scheme.  phi: caller-owned real field (C order, V floats), advanced
  * nsteps in place.  Dirichlet axes return EVX_ERR_UNSUPPORTED.  Needs a workspace sized for
  * EVX_OP_VAR_MOBILITY (the Gray-Scott size; EVX_ERR_NOMEM otherwise); the stepper's own buffers
- * are untouched.  Per step: two stencil kernels, the forward x and y passes, one z pass holding
+ * are untouched.  Per step: one stencil pass (mu and the fluxes), the forward x and y passes, one z pass holding
  * the multiplier between its forward and inverse transforms, the inverse y pass and an inverse x
  * pass that adds the increment to phi. */
 typedef struct evx_vm_params {
