@@ -422,8 +422,8 @@ def cpu_baseline():
     import numpy as np
     from oracle import ch
     from paper_2507_21748_amd.inputs import quench_field
-    # the host threads this process may use: OMP_NUM_THREADS where the host sets it (a GPU machine
-    # gives one GPU's processes a share of its cores), else every core the OS reports
+    # the host threads this process may use: OMP_NUM_THREADS where the host sets it (a shared
+    # machine gives one GPU's processes a share of its cores), else every core the OS reports
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     ch.WORKERS = cores
     p = ch.CHParams(dt=0.5)

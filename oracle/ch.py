@@ -345,8 +345,8 @@ def mass(c, dx: float = 1.0) -> float:
 
 def energy(c, p: CHParams, bc: str, scheme: str) -> float:
     """Discrete free energy E = dx^3 [ sum f(c) - (kappa/2) sum c L c ] (the Ginzburg-Landau
-    functional of the appendix with the spec double well; -sum c L c is the discrete
-    sum over |grad c|^2, i.e. the face differences for the stencil)."""
+    functional of the appendix with the step's double well f(c) = (c^2 - 1)^2 / 4; -sum c L c is
+    the discrete sum over |grad c|^2, i.e. the face differences for the stencil)."""
     c = np.asarray(c, dtype=np.float64)
     lap = laplacian(c, p.dx, bc, scheme)
     return float(p.dx ** 3 * (np.sum(fwell(c)) - 0.5 * p.kappa * np.sum(c * lap)))
